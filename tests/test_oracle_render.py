@@ -1,0 +1,218 @@
+"""Pins for the oracle's compositing, early termination, snapshot mode,
+gradient and time bake."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.brute import chord_length, dense_render, leaf_boxes, leaf_sigma_rgb, slab_segments
+from paper_2202_08614_amd import synth
+
+T_PERIOD = 60.0
+
+
+def _coeffs(n, seed=0):
+    return synth.gaussian_coeffs(n, seed=seed).astype(np.float64)
+
+
+def _render(oracle_lib, tree, coeffs, o, d, t, **kw):
+    p = oracle_lib.make_params(**kw)
+    out = oracle_lib.render_rays(tree, coeffs, p, [t], np.atleast_2d(o), np.atleast_2d(d),
+                                 np.zeros(len(np.atleast_2d(o)), np.int32))
+    return out
+
+
+def test_single_leaf_closed_form(oracle_lib):
+    dijk = np.array([[2, 1, 2, 1]], dtype=np.int32)
+    tree = oracle_lib.OracleTree(dijk, 4)
+    k = _coeffs(1, seed=5)
+    k[0, 0] = abs(k[0, 0]) + 1.0   # make sure the density is positive at some t
+    lo, hi = leaf_boxes(dijk)
+    rng = np.random.default_rng(0)
+    bg = np.array([0.2, 0.5, 0.9])
+    for _ in range(20):
+        target = lo[0] + rng.uniform(0.1, 0.9, 3) * (hi[0] - lo[0])
+        o = target + rng.standard_normal(3) * 2.0
+        d = target - o
+        t = rng.uniform(0, T_PERIOD)
+        sigma, rgb = leaf_sigma_rgb(k[0], t, d)
+        L = chord_length(lo[0], hi[0], o, d)
+        expect = (1 - math.exp(-sigma * L)) * rgb + math.exp(-sigma * L) * bg
+        out = _render(oracle_lib, tree, k, o, d, t, bg=bg)
+        assert np.allclose(out["rgb"][0, 0], expect, atol=1e-13)
+        assert abs(out["T"][0, 0] - math.exp(-sigma * L)) < 1e-13
+
+
+def test_two_leaves_closed_form(oracle_lib):
+    dijk = np.array([[2, 0, 1, 1], [2, 2, 1, 1]], dtype=np.int32)  # gap between them along x
+    tree = oracle_lib.OracleTree(dijk, 3)
+    k = _coeffs(2, seed=7)
+    k[:, 0] = np.abs(k[:, 0]) + 1.0
+    o = np.array([-1.0, 0.37, 0.41])
+    d = np.array([1.0, 0.013, -0.007])
+    t = 13.3
+    lo, hi = leaf_boxes(dijk)
+    s0, c0 = leaf_sigma_rgb(k[0], t, d)
+    s1, c1 = leaf_sigma_rgb(k[1], t, d)
+    L0 = chord_length(lo[0], hi[0], o, d)
+    L1 = chord_length(lo[1], hi[1], o, d)
+    assert L0 > 0 and L1 > 0
+    a0, a1 = 1 - math.exp(-s0 * L0), 1 - math.exp(-s1 * L1)
+    expect = a0 * c0 + (1 - a0) * a1 * c1
+    out = _render(oracle_lib, tree, k, o, d, t)
+    assert np.allclose(out["rgb"][0, 0], expect, atol=1e-13)
+    assert abs(out["T"][0, 0] - math.exp(-s0 * L0 - s1 * L1)) < 1e-13
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_transmittance_and_dense_sampling(oracle_lib, seed):
+    """T_final = exp(-sum sigma delta); the midpoint Riemann sum of the
+    volume-rendering integral converges to the oracle with error O(h)."""
+    depth = 3
+    dijk = synth.random_tree_leaves(seed + 10, depth)
+    tree = oracle_lib.OracleTree(dijk, depth)
+    k = _coeffs(len(dijk), seed)
+    o_all, d_all = synth.random_rays(40, seed + 20, inside_frac=0.0)
+    t = 21.7
+    tested = 0
+    for o, d in zip(o_all.astype(np.float64), d_all.astype(np.float64)):
+        idx, t0, t1 = slab_segments(dijk, o, d)
+        if len(idx) < 2:
+            continue
+        out = _render(oracle_lib, tree, k, o, d, t, sigma_scale=8.0)
+        tau = sum(leaf_sigma_rgb(k[l], t, d, sigma_scale=8.0)[0] * (b - a) for l, a, b in zip(idx, t0, t1))
+        assert abs(out["T"][0, 0] - math.exp(-tau)) < 1e-12
+        exact = out["rgb"][0, 0]
+        e1 = np.max(np.abs(dense_render(dijk, k, o, d, t, 2e-3, sigma_scale=8.0)[0] - exact))
+        e2 = np.max(np.abs(dense_render(dijk, k, o, d, t, 5e-4, sigma_scale=8.0)[0] - exact))
+        assert e2 < 2e-3
+        assert e2 <= e1 + 1e-9
+        tested += 1
+        if tested >= 4:
+            break
+    assert tested >= 2
+
+
+def test_dc_only_tree_is_a_static_plenoctree(oracle_lib):
+    """With every k_i (i >= 1) zero the image does not depend on t and equals
+    the static PlenOctree rendered from (k^sigma_0, k^z_{.,.,0})."""
+    dijk = synth.shell_leaves(4, 0.35, 0.12)
+    tree = oracle_lib.OracleTree(dijk, 4)
+    k = _coeffs(len(dijk), seed=3)
+    kz = k[:, 31:].reshape(-1, 27, 5).copy()
+    kz[:, :, 1:] = 0
+    k_dc = np.concatenate([np.where(np.arange(31) == 0, k[:, :31], 0.0), kz.reshape(-1, 135)], axis=1)
+    static = np.concatenate([k[:, :1], kz[:, :, 0]], axis=1)           # n1 = n2 = 1 layout
+    cam = synth.ring_camera(0.4, 0.3, 1.6, 50.0, 12, 10, 0.0)
+    o, d = oracle_lib.camera_rays(cam)
+    n = len(o)
+    p = oracle_lib.make_params(sigma_scale=16.0)
+    ref = oracle_lib.render_rays(tree, k_dc, p, [0.0], o, d, np.zeros(n, np.int32))["rgb"][:, 0]
+    assert np.max(ref) > 0.05
+    for t in [3.3, 17.0, 44.4]:
+        img = oracle_lib.render_rays(tree, k_dc, p, [t], o, d, np.zeros(n, np.int32))["rgb"][:, 0]
+        assert np.max(np.abs(img - ref)) < 1e-14
+    p1 = oracle_lib.make_params(n_sigma=1, n_sh_fourier=1, sigma_scale=16.0)
+    img = oracle_lib.render_rays(tree, static, p1, [9.0], o, d, np.zeros(n, np.int32))["rgb"][:, 0]
+    assert np.max(np.abs(img - ref)) < 1e-14
+
+
+def test_early_termination_rule(oracle_lib):
+    """Stop after the segment that drives T below tau; without a straddle both
+    outcomes agree, and the stop happens exactly at the first crossing."""
+    dijk = synth.shell_leaves(5, 0.3, 0.1)
+    tree = oracle_lib.OracleTree(dijk, 5)
+    k = _coeffs(len(dijk), seed=11)
+    o_all, d_all = synth.random_rays(60, 5, inside_frac=0.0)
+    o_all = o_all.astype(np.float64)
+    d_all = d_all.astype(np.float64)
+    tau = 1e-3
+    full = oracle_lib.render_rays(tree, k, oracle_lib.make_params(), [22.2], o_all, d_all,
+                                  np.zeros(60, np.int32))
+    et = oracle_lib.render_rays(tree, k, oracle_lib.make_params(stop_T=tau, band=1e-6), [22.2],
+                                o_all, d_all, np.zeros(60, np.int32))
+    stopped = 0
+    for r in range(60):
+        if full["T"][r, 0] >= tau:
+            assert np.array_equal(et["rgb"][r, 0], full["rgb"][r, 0])
+            continue
+        stopped += 1
+        assert et["n_seg"][r, 0] <= full["n_seg"][r, 0]
+        assert et["T"][r, 0] < tau
+        # the colour difference is what the skipped tail would have added: at most T_stop
+        assert np.max(np.abs(et["rgb"][r, 0] - full["rgb"][r, 0])) <= et["T"][r, 0] + 1e-15
+        # one segment fewer would leave T >= tau: recompute via a shorter stop
+        leaf, t0, t1 = tree.trace(o_all[r], d_all[r])
+        d = d_all[r] / np.linalg.norm(d_all[r])
+        T = 1.0
+        for i in range(et["n_seg"][r, 0] - 1):
+            s, _ = leaf_sigma_rgb(k[leaf[i]], 22.2, d)
+            T *= math.exp(-s * (t1[i] - t0[i]))
+        assert T >= tau
+    assert stopped >= 10
+
+
+def test_snapshot_mode_equals_fpo(oracle_lib):
+    dijk = synth.shell_leaves(4, 0.35, 0.12)
+    tree = oracle_lib.OracleTree(dijk, 4)
+    k = _coeffs(len(dijk), seed=4)
+    p = oracle_lib.make_params(sigma_scale=16.0)
+    t = 31.7
+    snap = oracle_lib.bake(k, p, [t])[0]
+    o, d = oracle_lib.camera_rays(synth.ring_camera(1.0, 0.2, 1.6, 50.0, 9, 9, t))
+    z = np.zeros(len(o), np.int32)
+    a = oracle_lib.render_rays(tree, k, p, [t], o, d, z)["rgb"]
+    b = oracle_lib.render_rays(tree, None, p, [t], o, d, z, snapshot=snap)["rgb"]
+    assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_bake_closed_forms(oracle_lib):
+    """sigma(0) = sum of even-index coefficients; sigma(T/2) alternates their signs."""
+    k = _coeffs(50, seed=9)
+    p = oracle_lib.make_params()
+    out = oracle_lib.bake(k, p, [0.0, T_PERIOD / 2])
+    assert np.allclose(out[0, 0], k[:, 0:31:2].sum(1), atol=1e-13)
+    signs = np.array([(-1) ** (i // 2) for i in range(0, 31, 2)])
+    assert np.allclose(out[1, 0], (k[:, 0:31:2] * signs).sum(1), atol=1e-12)
+    kz = k[:, 31:].reshape(-1, 27, 5)
+    assert np.allclose(out[0, 1:].T, kz[:, :, 0] + kz[:, :, 2] + kz[:, :, 4], atol=1e-13)
+    assert np.allclose(out[1, 1:].T, kz[:, :, 0] - kz[:, :, 2] + kz[:, :, 4], atol=1e-13)
+
+
+def test_gradient_matches_central_differences(oracle_lib):
+    """FP64 analytic gradient vs central differences (h = 1e-3) on 64 coefficients."""
+    depth = 4
+    dijk = synth.shell_leaves(depth, 0.3, 0.1)
+    tree = oracle_lib.OracleTree(dijk, depth)
+    k = _coeffs(len(dijk), seed=12)
+    cam = synth.ring_camera(0.7, 0.25, 1.6, 40.0, 8, 8, 0.0)
+    o, d = oracle_lib.camera_rays(cam)
+    n = len(o)
+    t_idx = np.zeros(n, np.int32)
+    times = [17.3]
+    p = oracle_lib.make_params(sigma_scale=16.0)
+    rng = np.random.default_rng(0)
+    target = rng.uniform(0, 1, (n, 3))
+
+    def loss(kk):
+        rgb = oracle_lib.render_rays(tree, kk, p, times, o, d, t_idx)["rgb"][:, 0]
+        return np.mean(np.sum((rgb - target) ** 2, axis=1))
+
+    rgb0 = oracle_lib.render_rays(tree, k, p, times, o, d, t_idx)["rgb"][:, 0]
+    grad_rgb = 2.0 * (rgb0 - target) / n
+    g, rgb = oracle_lib.render_grad(tree, k, p, times, o, d, t_idx, grad_rgb)
+    assert np.allclose(rgb, rgb0, atol=1e-15)
+    # choose coefficients with clear gradients, avoiding leaves whose density sits at the ReLU kink
+    b = oracle_lib.basis(times[0], 60.0, 31)
+    sraw = k[:, :31] @ b
+    cand = [(l, q) for l in np.nonzero(np.abs(g).sum(1) > 0)[0] for q in range(166)
+            if abs(sraw[l]) > 1e-2 and abs(g[l, q]) > 1e-6]
+    assert len(cand) >= 64
+    pick = rng.choice(len(cand), 64, replace=False)
+    h = 1e-3
+    for i in pick:
+        l, q = cand[i]
+        kp = k.copy(); kp[l, q] += h
+        km = k.copy(); km[l, q] -= h
+        fd = (loss(kp) - loss(km)) / (2 * h)
+        assert abs(fd - g[l, q]) <= 1e-6 * abs(g[l, q]) + 1e-6 * np.max(np.abs(g)) * h, (l, q, fd, g[l, q])
