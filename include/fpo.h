@@ -1,0 +1,204 @@
+/*
+ * fpo.h -- C ABI of libfpo, the MI355X (gfx950) Fourier PlenOctree render
+ * and fine-tune library.
+ *
+ * Paper: Wang et al., "Fourier PlenOctrees for Dynamic Radiance Field
+ * Rendering in Real-time", CVPR 2022.  The scene lives in the leaves of a
+ * union octree (Sec. 4.2); each leaf stores the Fourier coefficients
+ * k^sigma (n1 = 31) and k^z (n2 = 5 per SH coefficient, 9 SH coefficients
+ * per RGB channel) of Eq. 6 (Sec. 4.1).  Rendering at time t inverts them
+ * with the real IDFT of Eq. 7-9, evaluates the SH colour of Eq. 1 (Sec. 3)
+ * and composites front to back; fine-tuning back-propagates the L2 loss of
+ * Eq. 13 (Sec. 4.3) into the coefficients.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Scene: the unit cube [0,1]^3.  A leaf (d, i, j, k) covers
+ *   [i, i+1) 2^-d x [j, j+1) 2^-d x [k, k+1) 2^-d, 1 <= d <= FPO_MAX_DEPTH.
+ * - Leaf coefficient order (166 values): q < 31 is k^sigma_q; then
+ *   q = 31 + (c * 9 + j) * 5 + i is k^z for RGB channel c, SH index
+ *   j = l*l + l + m (real SH, Condon-Shortley phase) and Fourier index i.
+ * - Density: sigma_eff = sigma_scale * max(sigma(t), 0) per unit length.
+ * - Coefficient store ("packed planes"): the coefficients of all leaves are
+ *   held in G planes of 16-byte words; word (g, leaf) at byte offset
+ *   16 * (g * leaf_stride + leaf) packs coefficients q = W g ... W g + W - 1
+ *   of that leaf, W = 4 (FPO_F32), 8 (FPO_BF16) or 16 (FPO_FP8_E4M3), so
+ *   G = ceil(166 / W) = 42, 21 or 11.  Slots past q = 165 hold zero.
+ *   Quantised stores carry a per-leaf FP32 scale: value = scale[leaf] * code.
+ * - Leaves are numbered by Morton slot (the order fpo_build_tree assigns);
+ *   leaf_stride >= n_leaves.
+ * - Ownership: the caller owns every buffer.  The library allocates no
+ *   device memory, creates no streams and keeps no global state except the
+ *   thread-local error message.  Device work is enqueued on `stream` (a
+ *   hipStream_t passed as void*, NULL = the null stream) and is
+ *   asynchronous; kernel faults surface at the caller's next synchronisation.
+ * - Errors: every call returns fpo_status.  On FPO_E_INVALID or
+ *   FPO_E_UNSUPPORTED nothing is launched and outputs are untouched.
+ *   FPO_E_DEVICE reports a HIP launch error.  fpo_last_error() returns a
+ *   message for the last non-OK status on the calling thread.
+ */
+#ifndef FPO_H
+#define FPO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FPO_OK = 0,
+    FPO_E_INVALID = 1,      /* bad argument; nothing launched */
+    FPO_E_UNSUPPORTED = 2,  /* valid but not compiled in (e.g. another layout) */
+    FPO_E_DEVICE = 3,       /* HIP runtime error */
+    FPO_E_CAPACITY = 4      /* caller-provided capacity too small */
+} fpo_status;
+
+typedef enum { FPO_F32 = 0, FPO_BF16 = 1, FPO_FP8_E4M3 = 2 } fpo_dtype;
+
+#define FPO_N_SIGMA 31          /* n1 */
+#define FPO_N_SH_FOURIER 5      /* n2 */
+#define FPO_SH_DEGREE 2         /* l_max */
+#define FPO_N_SH 9              /* (l_max + 1)^2 */
+#define FPO_N_COEFF 166         /* n1 + 3 * 9 * n2 */
+#define FPO_N_BAKED 28          /* sigma(t) + 27 SH coefficients */
+#define FPO_BASIS_STRIDE 32     /* floats per row of a device basis table */
+#define FPO_MAX_DEPTH 10
+
+/* Fourier / SH sizes, period and density scale.  Only (31, 5, 2) is compiled. */
+typedef struct {
+    int32_t n_sigma;       /* n1 = 31 */
+    int32_t n_sh_fourier;  /* n2 = 5 */
+    int32_t sh_degree;     /* l_max = 2 */
+    float period;          /* T of Eq. 8, in frames (60) */
+    float sigma_scale;     /* s: density per unit length per unit ReLU(sigma) (64) */
+} fpo_layout;
+
+/* A built tree resident on the device. */
+typedef struct {
+    const int32_t* children;  /* device [n_nodes][8] int32: 0 empty, >0 node, <0 -(leaf slot + 1);
+                                 node 0 is the root; octant = x | y << 1 | z << 2 */
+    int64_t n_nodes;
+    int32_t max_depth;        /* 1 .. FPO_MAX_DEPTH */
+    const void* coeffs;       /* device packed planes (see above) */
+    const float* leaf_scale;  /* device [leaf_stride] for BF16 / FP8, ignored for F32 */
+    fpo_dtype dtype;
+    int64_t n_leaves;
+    int64_t leaf_stride;
+    fpo_layout layout;
+} fpo_tree_view;
+
+/* Pinhole camera: ray through pixel centre (u + 0.5, v + 0.5), row 0 at the
+ * top, y up.  right = normalise(fwd x up), up' = right x fwd;
+ * direction = normalise(f + sx right + sy up') with
+ * sx = (2 (u + 0.5) / W - 1) tan(fov_y / 2) W / H,
+ * sy = (1 - 2 (v + 0.5) / H) tan(fov_y / 2). */
+typedef struct {
+    float eye[3], fwd[3], up[3];
+    float fov_y_deg;
+    int32_t width, height;
+    double time;              /* t of Eq. 7-9, frames; any finite value (T-periodic) */
+} fpo_camera;
+
+#define FPO_CAMERA_FLOATS 16  /* floats per camera in a device camera table */
+
+typedef struct {
+    float bg[3];              /* background colour added with the final transmittance */
+    float stop_T;             /* early termination: stop after the segment that drives
+                                 T below stop_T; 0 disables */
+    const void* snapshot;     /* NULL: Fourier mode.  Else device [28][leaf_stride] baked
+                                 values (row 0 sigma(t) before activation, row 1 + c*9 + j
+                                 the SH coefficient z_{c,j}); the camera's time is unused */
+    fpo_dtype snapshot_dtype; /* FPO_F32 or FPO_BF16 */
+    int64_t snapshot_cam_stride; /* elements between consecutive cameras' snapshots (0: shared) */
+    int32_t flags;            /* reserved, 0 */
+} fpo_render_opts;
+
+/* ---------------------------------------------------------------------- */
+/* Host-side set-up                                                         */
+/* ---------------------------------------------------------------------- */
+
+/* Build the sparse union octree (Sec. 4.2: the union of the per-frame
+ * structures; a leaf is a cell of the union) from its leaves.
+ *   leaf_dijk    host [n_leaves][4] int32 (depth, i, j, k), caller order.
+ *   children_out host [cap_nodes][8] int32, or NULL to query the node count.
+ *   n_nodes_out  host, receives the number of internal nodes.
+ *   perm_out     host [n_leaves] int64 or NULL: perm_out[slot] = caller index of
+ *                the leaf stored at Morton slot `slot`.
+ * Nodes are numbered breadth first (root 0); leaves in Morton (z-order) order.
+ * FPO_E_INVALID: NULL leaf_dijk, n_leaves < 1, max_depth outside 1..10, a depth
+ * outside 1..max_depth, a coordinate outside [0, 2^depth), duplicate leaves, or
+ * a leaf inside another leaf.  FPO_E_CAPACITY: cap_nodes < node count (the
+ * count is still written).  Runs on the calling thread; no device work. */
+fpo_status fpo_build_tree(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
+                          int32_t* children_out, int64_t cap_nodes, int64_t* n_nodes_out,
+                          int64_t* perm_out);
+
+/* Real Fourier basis of Eq. 8 evaluated in FP64 on the host and rounded to
+ * FP32: basis_out[r * 32 + i] = IDFT_i(times[r]) for i < n_sigma, 0 for the
+ * remaining slots.  basis_out: host [n_t][FPO_BASIS_STRIDE].  The result is
+ * what the device calls below take as their basis table. */
+fpo_status fpo_time_basis(const double* times, int32_t n_t, const fpo_layout* layout,
+                          float* basis_out);
+
+/* Pack cameras into rows of FPO_CAMERA_FLOATS floats (host) for
+ * fpo_camera_rays: eye, unit forward, right * tan_x, up' * tan_y (FP32,
+ * computed in FP64), width, height. */
+fpo_status fpo_camera_pack(const fpo_camera* cams, int32_t n_cams, float* table_out);
+
+/* ---------------------------------------------------------------------- */
+/* Device calls                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Scatter caller-order coefficients into the F32 packed planes.
+ *   src  device [n_leaves][166] F32, caller order.
+ *   perm device [n_leaves] int64 from fpo_build_tree.
+ *   dst  device F32 packed planes with 42 planes of leaf_stride words; padding
+ *        slots (q >= 166) and leaves >= n_leaves are written with zero. */
+fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
+                           int64_t leaf_stride, float* dst, void* stream);
+
+/* Render n_cams pinhole views (Sec. 4.1: per pixel, traverse the octree,
+ * invert the leaf's coefficients at the camera's time with Eq. 7-9, colour
+ * with Eq. 1, composite front to back).
+ *   cams    host [n_cams].
+ *   rgb_out device [n_cams][H][W][3] F32 (all cameras must share W and H).
+ *   T_out   device [n_cams][H][W] F32 final transmittance, or NULL. */
+fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
+                      const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream);
+
+/* Generate rays for (camera, row, column) triples.
+ *   cam_table device [n_cams][FPO_CAMERA_FLOATS] from fpo_camera_pack.
+ *   cam, py, px device [n] int32; must index valid cameras / pixels.
+ *   o_out, d_out device [n][3] F32; d_out is unit length. */
+fpo_status fpo_camera_rays(const float* cam_table, int32_t n_cams, const int32_t* cam,
+                           const int32_t* py, const int32_t* px, int64_t n,
+                           float* o_out, float* d_out, void* stream);
+
+/* Render arbitrary rays; ray r uses basis row t_idx[r].
+ *   o, d   device [n_rays][3] F32 (d is normalised by the kernel; |d| > 0).
+ *   t_idx  device [n_rays] int32 in [0, n_t).
+ *   basis  device [n_t][FPO_BASIS_STRIDE] F32 (fpo_time_basis).
+ *   rgb_out device [n_rays][3]; T_out device [n_rays] or NULL. */
+fpo_status fpo_render_rays(const fpo_tree_view* tree, const float* o, const float* d,
+                           const int32_t* t_idx, const float* basis, int32_t n_t, int64_t n_rays,
+                           const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream);
+
+/* Test support: the ordered leaf segments each ray crosses (no early stop).
+ *   leaf_ids device [n_rays][max_visits] int32 Morton slots.
+ *   t01      device [n_rays][max_visits][2] F32 entry / exit distance along the
+ *            unit direction from o.
+ *   n_visits device [n_rays] int32, the full count (may exceed max_visits, in
+ *            which case only the first max_visits are written). */
+fpo_status fpo_trace_rays(const fpo_tree_view* tree, const float* o, const float* d, int64_t n_rays,
+                          int32_t max_visits, int32_t* leaf_ids, float* t01, int32_t* n_visits,
+                          void* stream);
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char* fpo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPO_H */

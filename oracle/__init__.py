@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package.  It shares no code with
-the HIP library and never imports the HIP package: the arithmetic lives in `fpo_oracle.c` (plain C, FP64) and in the numpy
-checkers `brute.py` and `codec.py`.
+the HIP library and never imports the HIP package: the arithmetic lives in
+`fpo_oracle.c` (plain C, FP64) and in the numpy checkers `brute.py` and
+`codec.py`.
 
 Python here only marshals numpy arrays into the C functions.
 """
@@ -72,7 +73,7 @@ def lib():
         L.or_trace.argtypes = [ctypes.c_void_p, _P, _P, ctypes.c_int64, _P, _P, _P]
         L.or_trace.restype = ctypes.c_int64
         L.or_render_rays.argtypes = [ctypes.c_void_p, _P, _P, ctypes.POINTER(_Params), _P, ctypes.c_int32,
-                                     _P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P]
+                                     _P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P]
         L.or_render_rays.restype = ctypes.c_int32
         L.or_render_grad.argtypes = [ctypes.c_void_p, _P, ctypes.POINTER(_Params), _P, ctypes.c_int32,
                                      _P, _P, _P, ctypes.c_int64, _P, _P, _P]
@@ -188,7 +189,8 @@ def render_rays(tree: OracleTree, coeffs: Optional[np.ndarray], params: _Params,
     """Render rays in FP64.  Returns a dict with both early-termination outcomes.
 
     rgb: [n][2][3] (outcome 0 stops at threshold tau(1+band), outcome 1 at
-    tau(1-band)); T: [n][2]; n_seg: [n][2] composited segments; n_cells: [n]
+    tau(1-band)); T: [n][2]; n_seg: [n][2] composited segments; n_opaque:
+    [n][2] composited segments with positive optical depth; n_cells: [n]
     segments crossed without early stop.
     """
     o = np.ascontiguousarray(o, dtype=np.float64)
@@ -201,13 +203,14 @@ def render_rays(tree: OracleTree, coeffs: Optional[np.ndarray], params: _Params,
     rgb = np.zeros((n, 2, 3))
     T = np.zeros((n, 2))
     n_seg = np.zeros((n, 2), dtype=np.int64)
+    n_opaque = np.zeros((n, 2), dtype=np.int64)
     n_cells = np.zeros(n, dtype=np.int64)
     st = lib().or_render_rays(tree._h, _ptr(c), _ptr(s), ctypes.byref(params), _ptr(times), len(times),
                               _ptr(o), _ptr(d), _ptr(t_idx), n, int(n_threads),
-                              _ptr(rgb), _ptr(T), _ptr(n_seg), _ptr(n_cells))
+                              _ptr(rgb), _ptr(T), _ptr(n_seg), _ptr(n_opaque), _ptr(n_cells))
     if st != 0:
         raise MemoryError("oracle render failed")
-    return {"rgb": rgb, "T": T, "n_seg": n_seg, "n_cells": n_cells}
+    return {"rgb": rgb, "T": T, "n_seg": n_seg, "n_opaque": n_opaque, "n_cells": n_cells}
 
 
 def render_grad(tree: OracleTree, coeffs: np.ndarray, params: _Params, times: Sequence[float],

@@ -345,6 +345,7 @@ typedef struct {
     double rgb[2][3];   /* [0]: earliest admissible stop, [1]: latest */
     double T[2];
     int64_t n_seg[2];   /* composited segments */
+    int64_t n_opaque[2];/* composited segments with sigma_eff * delta > 0 */
     int64_t n_cells;    /* all segments the ray crosses (no early stop) */
 } or_ray_result;
 
@@ -368,7 +369,7 @@ static void or_render_one(const or_tree* tr, const double* coeffs, const double*
     for (int v = 0; v < 2; ++v) {
         const double thr = p->stop_T > 0.0 ? p->stop_T * (v == 0 ? 1.0 + p->band : 1.0 - p->band) : 0.0;
         double T = 1.0, C[3] = {0.0, 0.0, 0.0};
-        int64_t used = 0;
+        int64_t used = 0, opaque = 0;
         for (int64_t s = 0; s < n && s < seg_cap; ++s) {
             const int64_t l = seg_leaf[s];
             double sraw, z[27];
@@ -384,11 +385,13 @@ static void or_render_one(const or_tree* tr, const double* coeffs, const double*
             }
             T *= exp(-sigma * delta);
             ++used;
+            if (sigma * delta > 0.0) ++opaque;
             if (thr > 0.0 && T < thr) break;
         }
         for (int c = 0; c < 3; ++c) res->rgb[v][c] = C[c] + T * p->bg[c];
         res->T[v] = T;
         res->n_seg[v] = used;
+        res->n_opaque[v] = opaque;
     }
 }
 
@@ -406,6 +409,7 @@ typedef struct {
     double* rgb;            /* [n][2][3] */
     double* T;              /* [n][2] */
     int64_t* n_seg;         /* [n][2] */
+    int64_t* n_opaque;      /* [n][2] */
     int64_t* n_cells;       /* [n] */
     int64_t begin, end;
     int32_t status;
@@ -428,6 +432,7 @@ static void* or_render_worker(void* arg)
             for (int c = 0; c < 3; ++c) job->rgb[r * 6 + v * 3 + c] = res.rgb[v][c];
             job->T[r * 2 + v] = res.T[v];
             job->n_seg[r * 2 + v] = res.n_seg[v];
+            job->n_opaque[r * 2 + v] = res.n_opaque[v];
         }
         job->n_cells[r] = res.n_cells;
     }
@@ -437,11 +442,12 @@ static void* or_render_worker(void* arg)
 
 /* Render n rays.  times: [n_t]; t_idx: [n] index into times.  coeffs may be
  * NULL when snap ([28][L]) is given.  Outputs: rgb [n][2][3], T [n][2],
- * n_seg [n][2], n_cells [n].  Returns 0 on success. */
+ * n_seg [n][2], n_opaque [n][2], n_cells [n].  Returns 0 on success. */
 int32_t or_render_rays(const or_tree* tr, const double* coeffs, const double* snap,
                        const or_params* p, const double* times, int32_t n_t,
                        const double* o, const double* d, const int32_t* t_idx, int64_t n,
-                       int32_t n_threads, double* rgb, double* T, int64_t* n_seg, int64_t* n_cells)
+                       int32_t n_threads, double* rgb, double* T, int64_t* n_seg, int64_t* n_opaque,
+                       int64_t* n_cells)
 {
     const int32_t nb = p->n_sigma > p->n_sh_fourier ? p->n_sigma : p->n_sh_fourier;
     double* basis = (double*)malloc(sizeof(double) * (size_t)(n_t > 0 ? n_t : 1) * nb);
@@ -457,7 +463,7 @@ int32_t or_render_rays(const or_tree* tr, const double* coeffs, const double* sn
         or_job* j = &jobs[w];
         j->tr = tr; j->coeffs = coeffs; j->snap = snap; j->p = p; j->basis = basis; j->n_bmax = nb;
         j->o = o; j->d = d; j->t_idx = t_idx; j->n = n;
-        j->rgb = rgb; j->T = T; j->n_seg = n_seg; j->n_cells = n_cells;
+        j->rgb = rgb; j->T = T; j->n_seg = n_seg; j->n_opaque = n_opaque; j->n_cells = n_cells;
         j->begin = n * w / n_threads;
         j->end = n * (w + 1) / n_threads;
         j->status = 0;

@@ -1,0 +1,305 @@
+"""ctypes binding of libfpo (include/fpo.h).
+
+Argument marshalling only: every step of the render / fine-tune path runs in
+the library (host C++ for tree building and the FP64 time basis, HIP kernels
+on the device for everything else).  PyTorch provides device memory and the
+current HIP stream.  If libfpo.so has not been built, importing the library
+raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfpo.so")
+
+FPO_OK, FPO_E_INVALID, FPO_E_UNSUPPORTED, FPO_E_DEVICE, FPO_E_CAPACITY = range(5)
+FPO_F32, FPO_BF16, FPO_FP8_E4M3 = 0, 1, 2
+N_SIGMA, N_SH_FOURIER, SH_DEGREE, N_SH = 31, 5, 2, 9
+N_COEFF = 166
+N_BAKED = 28
+BASIS_STRIDE = 32
+CAMERA_FLOATS = 16
+MAX_DEPTH = 10
+COEFFS_PER_WORD = {FPO_F32: 4, FPO_BF16: 8, FPO_FP8_E4M3: 16}
+
+
+def n_planes(dtype: int) -> int:
+    w = COEFFS_PER_WORD[dtype]
+    return (N_COEFF + w - 1) // w
+
+
+class FpoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libfpo status {status}: {msg}")
+        self.status = status
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("n_sigma", ctypes.c_int32), ("n_sh_fourier", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32), ("period", ctypes.c_float),
+                ("sigma_scale", ctypes.c_float)]
+
+
+class TreeView(ctypes.Structure):
+    _fields_ = [("children", ctypes.c_void_p), ("n_nodes", ctypes.c_int64),
+                ("max_depth", ctypes.c_int32), ("coeffs", ctypes.c_void_p),
+                ("leaf_scale", ctypes.c_void_p), ("dtype", ctypes.c_int),
+                ("n_leaves", ctypes.c_int64), ("leaf_stride", ctypes.c_int64),
+                ("layout", Layout)]
+
+
+class CameraC(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("fwd", ctypes.c_float * 3),
+                ("up", ctypes.c_float * 3), ("fov_y_deg", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("time", ctypes.c_double)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("bg", ctypes.c_float * 3), ("stop_T", ctypes.c_float),
+                ("snapshot", ctypes.c_void_p), ("snapshot_dtype", ctypes.c_int),
+                ("snapshot_cam_stride", ctypes.c_int64), ("flags", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_lib = None
+
+# name -> argtypes; every function returns fpo_status (int)
+_SIGS = {
+    "fpo_build_tree": [_P, _I64, _I32, _P, _I64, _P, _P],
+    "fpo_time_basis": [_P, _I32, ctypes.POINTER(Layout), _P],
+    "fpo_camera_pack": [ctypes.POINTER(CameraC), _I32, _P],
+    "fpo_pack_coeffs": [_P, _P, _I64, _I64, _P, _P],
+    "fpo_render": [ctypes.POINTER(TreeView), ctypes.POINTER(CameraC), _I32,
+                   ctypes.POINTER(RenderOpts), _P, _P, _P],
+    "fpo_camera_rays": [_P, _I32, _P, _P, _P, _I64, _P, _P, _P],
+    "fpo_render_rays": [ctypes.POINTER(TreeView), _P, _P, _P, _P, _I32, _I64,
+                        ctypes.POINTER(RenderOpts), _P, _P, _P],
+    "fpo_trace_rays": [ctypes.POINTER(TreeView), _P, _P, _I64, _I32, _P, _P, _P, _P],
+}
+
+
+def lib():
+    """Load libfpo.so (raises if it is missing: build it with build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.fpo_last_error.argtypes = []
+        L.fpo_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> Sequence[str]:
+    return list(_SIGS) + ["fpo_last_error"]
+
+
+def _check(st: int):
+    if st != FPO_OK:
+        raise FpoError(st, lib().fpo_last_error().decode())
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _t_ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_layout(period: float = 60.0, sigma_scale: float = 64.0) -> Layout:
+    return Layout(N_SIGMA, N_SH_FOURIER, SH_DEGREE, float(period), float(sigma_scale))
+
+
+def camera_struct(cams) -> ctypes.Array:
+    arr = (CameraC * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].eye[:] = [float(v) for v in c.eye]
+        arr[i].fwd[:] = [float(v) for v in c.fwd]
+        arr[i].up[:] = [float(v) for v in c.up]
+        arr[i].fov_y_deg = float(c.fov_y_deg)
+        arr[i].width = int(c.width)
+        arr[i].height = int(c.height)
+        arr[i].time = float(c.time)
+    return arr
+
+
+def make_opts(bg=(0.0, 0.0, 0.0), stop_T: float = 0.0, snapshot=None, snapshot_dtype: int = FPO_F32,
+              snapshot_cam_stride: int = 0) -> RenderOpts:
+    o = RenderOpts()
+    o.bg[:] = [float(v) for v in bg]
+    o.stop_T = float(stop_T)
+    o.snapshot = None if snapshot is None else snapshot.data_ptr()
+    o.snapshot_dtype = int(snapshot_dtype)
+    o.snapshot_cam_stride = int(snapshot_cam_stride)
+    o.flags = 0
+    return o
+
+
+# ---------------------------------------------------------------------------
+# host calls
+# ---------------------------------------------------------------------------
+def build_tree(leaf_dijk: np.ndarray, max_depth: int):
+    """fpo_build_tree -> (children [n_nodes][8] int32, perm [L] int64)."""
+    dijk = np.ascontiguousarray(leaf_dijk, dtype=np.int32)
+    n = dijk.shape[0]
+    n_nodes = ctypes.c_int64(0)
+    _check(lib().fpo_build_tree(_np_ptr(dijk), n, int(max_depth), None, 0, ctypes.byref(n_nodes), None))
+    children = np.zeros((n_nodes.value, 8), dtype=np.int32)
+    perm = np.zeros(n, dtype=np.int64)
+    _check(lib().fpo_build_tree(_np_ptr(dijk), n, int(max_depth), _np_ptr(children), n_nodes.value,
+                                ctypes.byref(n_nodes), _np_ptr(perm)))
+    return children, perm
+
+
+def time_basis(times: Sequence[float], layout: Optional[Layout] = None) -> np.ndarray:
+    layout = layout or make_layout()
+    t = np.ascontiguousarray(times, dtype=np.float64)
+    out = np.zeros((len(t), BASIS_STRIDE), dtype=np.float32)
+    _check(lib().fpo_time_basis(_np_ptr(t), len(t), ctypes.byref(layout), _np_ptr(out)))
+    return out
+
+
+def camera_pack(cams) -> np.ndarray:
+    arr = camera_struct(cams)
+    out = np.zeros((len(cams), CAMERA_FLOATS), dtype=np.float32)
+    _check(lib().fpo_camera_pack(arr, len(cams), _np_ptr(out)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# device tree
+# ---------------------------------------------------------------------------
+class DeviceTree:
+    """A tree resident on the GPU: child table, packed coefficient planes and
+    (for quantised stores) per-leaf scales.  Coefficient planes are
+    [n_planes][leaf_stride][16 bytes]."""
+
+    def __init__(self, children, n_nodes: int, max_depth: int, planes, scale, dtype: int,
+                 n_leaves: int, leaf_stride: int, perm: np.ndarray, layout: Layout):
+        self.children = children
+        self.n_nodes = int(n_nodes)
+        self.max_depth = int(max_depth)
+        self.planes = planes
+        self.scale = scale
+        self.dtype = int(dtype)
+        self.n_leaves = int(n_leaves)
+        self.leaf_stride = int(leaf_stride)
+        self.perm = perm
+        self.layout = layout
+
+    @classmethod
+    def from_leaves(cls, leaf_dijk: np.ndarray, coeffs: np.ndarray, max_depth: int,
+                    device="cuda", period: float = 60.0, sigma_scale: float = 64.0,
+                    leaf_stride: Optional[int] = None) -> "DeviceTree":
+        import torch
+        children, perm = build_tree(leaf_dijk, max_depth)
+        n = int(leaf_dijk.shape[0])
+        stride = int(leaf_stride or n)
+        src = torch.from_numpy(np.ascontiguousarray(coeffs, dtype=np.float32)).to(device)
+        perm_d = torch.from_numpy(perm).to(device)
+        planes = torch.empty((n_planes(FPO_F32), stride, 4), dtype=torch.float32, device=device)
+        pack_coeffs(src, perm_d, n, stride, planes)
+        del src
+        return cls(torch.from_numpy(children).to(device), children.shape[0], max_depth, planes, None,
+                   FPO_F32, n, stride, perm, make_layout(period, sigma_scale))
+
+    def with_store(self, planes, scale, dtype: int) -> "DeviceTree":
+        return DeviceTree(self.children, self.n_nodes, self.max_depth, planes, scale, dtype,
+                          self.n_leaves, self.leaf_stride, self.perm, self.layout)
+
+    def view(self) -> TreeView:
+        v = TreeView()
+        v.children = self.children.data_ptr()
+        v.n_nodes = self.n_nodes
+        v.max_depth = self.max_depth
+        v.coeffs = None if self.planes is None else self.planes.data_ptr()
+        v.leaf_scale = None if self.scale is None else self.scale.data_ptr()
+        v.dtype = self.dtype
+        v.n_leaves = self.n_leaves
+        v.leaf_stride = self.leaf_stride
+        v.layout = self.layout
+        return v
+
+
+# ---------------------------------------------------------------------------
+# device calls
+# ---------------------------------------------------------------------------
+def pack_coeffs(src, perm, n_leaves: int, leaf_stride: int, dst):
+    _check(lib().fpo_pack_coeffs(_t_ptr(src), _t_ptr(perm), int(n_leaves), int(leaf_stride), _t_ptr(dst),
+                                 _stream()))
+
+
+def render(tree: DeviceTree, cams, opts: Optional[RenderOpts] = None, rgb=None, T=None, want_T: bool = False):
+    """fpo_render -> (rgb [n][H][W][3], T [n][H][W] or None)."""
+    import torch
+    opts = opts or make_opts()
+    n, H, W = len(cams), int(cams[0].height), int(cams[0].width)
+    dev = tree.children.device
+    if rgb is None:
+        rgb = torch.empty((n, H, W, 3), dtype=torch.float32, device=dev)
+    if T is None and want_T:
+        T = torch.empty((n, H, W), dtype=torch.float32, device=dev)
+    tv = tree.view()
+    arr = camera_struct(cams)
+    _check(lib().fpo_render(ctypes.byref(tv), arr, n, ctypes.byref(opts), _t_ptr(rgb), _t_ptr(T), _stream()))
+    return rgb, T
+
+
+def camera_rays(cam_table, cam, py, px, o=None, d=None):
+    import torch
+    n = int(cam.numel())
+    dev = cam.device
+    o = o if o is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
+    d = d if d is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
+    _check(lib().fpo_camera_rays(_t_ptr(cam_table), int(cam_table.shape[0]), _t_ptr(cam), _t_ptr(py), _t_ptr(px),
+                                 n, _t_ptr(o), _t_ptr(d), _stream()))
+    return o, d
+
+
+def render_rays(tree: DeviceTree, o, d, t_idx, basis, opts: Optional[RenderOpts] = None, rgb=None, T=None,
+                want_T: bool = False):
+    import torch
+    opts = opts or make_opts()
+    n = int(o.shape[0])
+    dev = o.device
+    if rgb is None:
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    if T is None and want_T:
+        T = torch.empty((n,), dtype=torch.float32, device=dev)
+    tv = tree.view()
+    _check(lib().fpo_render_rays(ctypes.byref(tv), _t_ptr(o), _t_ptr(d), _t_ptr(t_idx), _t_ptr(basis),
+                                 int(basis.shape[0]), n, ctypes.byref(opts), _t_ptr(rgb), _t_ptr(T), _stream()))
+    return rgb, T
+
+
+def trace_rays(tree: DeviceTree, o, d, max_visits: int):
+    """fpo_trace_rays -> (leaf_ids [n][cap], t01 [n][cap][2], n_visits [n])."""
+    import torch
+    n = int(o.shape[0])
+    dev = o.device
+    ids = torch.full((n, max_visits), -1, dtype=torch.int32, device=dev)
+    t01 = torch.zeros((n, max_visits, 2), dtype=torch.float32, device=dev)
+    nv = torch.zeros((n,), dtype=torch.int32, device=dev)
+    tv = tree.view()
+    _check(lib().fpo_trace_rays(ctypes.byref(tv), _t_ptr(o), _t_ptr(d), n, int(max_visits), _t_ptr(ids),
+                                _t_ptr(t01), _t_ptr(nv), _stream()))
+    return ids, t01, nv

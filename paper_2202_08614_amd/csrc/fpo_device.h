@@ -1,0 +1,367 @@
+// Device-side building blocks of libfpo (gfx950): ray set-up, the sparse
+// octree walk, packed-plane coefficient gathers, the per-leaf inverse real
+// Fourier transform (Eq. 7, 9), the SH colour (Eq. 1) and front-to-back
+// compositing.  Shared by the render, trace and backward kernels so that all
+// three walk exactly the same segments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fpo.h"
+
+namespace fpo {
+namespace dev {
+
+constexpr int kBlock = 256;          // threads per block: 4 wave64
+constexpr int kWave = 64;
+constexpr int kStackLevels = FPO_MAX_DEPTH;
+
+// Plain-old-data view of a tree, passed by value to kernels.
+struct TreeDev {
+    const int32_t* children;
+    const uint4* planes;    // packed planes, one 16-byte word per (plane, leaf)
+    const float* scale;     // per-leaf scale for quantised stores
+    int64_t stride;         // words per plane (leaf_stride)
+    int32_t n_nodes;
+    int32_t n_leaves;
+    int32_t max_depth;
+    float sigma_scale;
+};
+
+// --------------------------------------------------------------------------
+// Coefficient words.  W coefficients per 16-byte word.
+// --------------------------------------------------------------------------
+template <int DT> struct Pack;
+
+template <> struct Pack<FPO_F32> {
+    static constexpr int W = 4;
+    __device__ static inline void unpack(const uint4& w, float* o)
+    {
+        o[0] = __uint_as_float(w.x); o[1] = __uint_as_float(w.y);
+        o[2] = __uint_as_float(w.z); o[3] = __uint_as_float(w.w);
+    }
+};
+
+template <> struct Pack<FPO_BF16> {
+    static constexpr int W = 8;
+    __device__ static inline void unpack(const uint4& w, float* o)
+    {
+        const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = __uint_as_float(v[i] << 16);
+            o[2 * i + 1] = __uint_as_float(v[i] & 0xFFFF0000u);
+        }
+    }
+};
+
+// OCP E4M3FN byte -> FP32.  Placing the 7 magnitude bits at bit 20 gives an
+// FP32 whose value is 2^(e-127) (1 + m/8) for e >= 1 and the FP32 subnormal
+// 2^-126 (m/8) for e = 0; scaling by 2^120 maps both onto 2^(e-7)(1 + m/8)
+// and 2^-6 (m/8), the E4M3 normal and subnormal values.
+__device__ inline float e4m3_to_f32(uint32_t byte)
+{
+    const uint32_t bits = ((byte & 0x7Fu) << 20) | ((byte & 0x80u) << 24);
+    return __uint_as_float(bits) * 0x1p120f;
+}
+
+template <> struct Pack<FPO_FP8_E4M3> {
+    static constexpr int W = 16;
+    __device__ static inline void unpack(const uint4& w, float* o)
+    {
+        const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) o[4 * i + b] = e4m3_to_f32((v[i] >> (8 * b)) & 0xFFu);
+    }
+};
+
+// --------------------------------------------------------------------------
+// Real spherical harmonics of degree <= 2 (Eq. 1): orthonormal, Condon-Shortley
+// phase, index j = l^2 + l + m.  Constants: Y00 = 1/(2 sqrt(pi)),
+// Y1m = sqrt(3/(4 pi)), Y2{-2,-1,1} = sqrt(15/pi)/2, Y20 = sqrt(5/pi)/4,
+// Y22 = sqrt(15/pi)/4.
+// --------------------------------------------------------------------------
+__device__ inline void sh9(float x, float y, float z, float* Y)
+{
+    const float c0 = 0.28209479177387814f;
+    const float c1 = 0.48860251190291992f;
+    const float c2 = 1.09254843059207907f;
+    const float c20 = 0.31539156525252005f;
+    const float c22 = 0.54627421529603953f;
+    Y[0] = c0;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    Y[4] = c2 * x * y;
+    Y[5] = -c2 * y * z;
+    Y[6] = c20 * (3.0f * z * z - 1.0f);
+    Y[7] = -c2 * x * z;
+    Y[8] = c22 * (x * x - y * y);
+}
+
+// --------------------------------------------------------------------------
+// Ray set-up: normalise d, clip against the unit cube, re-base the origin at
+// the entry point so that distances along the ray stay small.
+// --------------------------------------------------------------------------
+struct Ray {
+    float o[3];     // entry point (origin + t_in d)
+    float d[3];     // unit direction
+    float inv[3];   // 1 / d (unused where d == 0)
+    float t_in;     // distance from the caller's origin to the entry point
+    float t_len;    // length inside the cube
+};
+
+__device__ inline bool setup_ray(float ox, float oy, float oz, float dx, float dy, float dz, Ray& r)
+{
+    const float n2 = dx * dx + dy * dy + dz * dz;
+    if (!(n2 > 0.0f)) return false;
+    const float inv_n = 1.0f / sqrtf(n2);
+    const float o[3] = {ox, oy, oz};
+    const float d[3] = {dx * inv_n, dy * inv_n, dz * inv_n};
+    float lo = 0.0f, hi = __builtin_inff();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.d[a] = d[a];
+        if (d[a] == 0.0f) {
+            r.inv[a] = 0.0f;
+            if (o[a] < 0.0f || o[a] > 1.0f) return false;
+            continue;
+        }
+        const float inv = 1.0f / d[a];
+        r.inv[a] = inv;
+        float t1 = (0.0f - o[a]) * inv;
+        float t2 = (1.0f - o[a]) * inv;
+        if (t1 > t2) { const float s = t1; t1 = t2; t2 = s; }
+        lo = fmaxf(lo, t1);
+        hi = fminf(hi, t2);
+    }
+    if (!(lo < hi)) return false;
+    r.t_in = lo;
+    r.t_len = hi - lo;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.o[a] = fmaf(lo, d[a], o[a]);
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// Sparse octree walk.
+//
+// The walk keeps the ray's current cell on the finest lattice (G = 2^D cells
+// per axis) and the chain of internal nodes above it (a per-lane stack in
+// LDS).  Each step descends from the deepest node that still contains the
+// cell to the leaf or empty child holding it, reports the leaf segment
+// [t_cur, t_exit), and steps to the neighbouring cell across the exit face:
+// the exit axis moves by one lattice cell past the face, the other axes are
+// re-derived from the exit point and clamped into the cell just left (so the
+// walk is monotone and ends within 3G steps).  Exit-axis ties break x < y < z.
+//
+// Visitor: bool segment(int leaf, float t0, float t1) returns true to stop.
+// Distances are measured from the entry point r.o.
+// --------------------------------------------------------------------------
+template <class Visitor>
+__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
+{
+    const int D = T.max_depth;
+    const int G = 1 << D;
+    const float fG = (float)G;
+    const float invG = 1.0f / fG;
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int v = (int)floorf(r.o[a] * fG);
+        c[a] = min(max(v, 0), G - 1);
+    }
+    int lvl = 0;
+    int node = 0;
+    stk[0] = 0;
+    float t_cur = 0.0f;
+    const int max_steps = 3 * G + 4;
+    for (int it = 0; it < max_steps; ++it) {
+        int ch;
+        for (;;) {
+            const int sh = D - 1 - lvl;
+            const int oct = ((c[0] >> sh) & 1) | (((c[1] >> sh) & 1) << 1) | (((c[2] >> sh) & 1) << 2);
+            ch = T.children[node * 8 + oct];
+            if (ch > 0 && ch < T.n_nodes && lvl < D - 1) {
+                ++lvl;
+                node = ch;
+                stk[lvl * kBlock] = node;
+                continue;
+            }
+            if (ch > 0) ch = 0;   // malformed table: treat as empty
+            break;
+        }
+        const int csh = D - 1 - lvl;
+        const int size = 1 << csh;
+        int lo[3];
+        float te[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = c[a] & ~(size - 1);
+            if (r.d[a] > 0.0f)
+                te[a] = ((float)(lo[a] + size) * invG - r.o[a]) * r.inv[a];
+            else if (r.d[a] < 0.0f)
+                te[a] = ((float)lo[a] * invG - r.o[a]) * r.inv[a];
+            else
+                te[a] = __builtin_inff();
+        }
+        int ax = 0;
+        float t_exit = te[0];
+        if (te[1] < t_exit) { t_exit = te[1]; ax = 1; }
+        if (te[2] < t_exit) { t_exit = te[2]; ax = 2; }
+        t_exit = fmaxf(t_exit, t_cur);
+        if (ch < 0) {
+            const int leaf = -ch - 1;
+            if (leaf < T.n_leaves && vis.segment(leaf, t_cur, t_exit)) return;
+        }
+        int nc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a == ax) {
+                nc[a] = r.d[a] > 0.0f ? lo[a] + size : lo[a] - 1;
+            } else if (r.d[a] == 0.0f) {
+                nc[a] = c[a];
+            } else {
+                int v = (int)floorf(fmaf(t_exit, r.d[a], r.o[a]) * fG);
+                v = min(max(v, lo[a]), lo[a] + size - 1);
+                nc[a] = r.d[a] > 0.0f ? max(v, c[a]) : min(v, c[a]);
+            }
+        }
+        if (nc[ax] < 0 || nc[ax] >= G) return;
+        const unsigned diff = (unsigned)((c[0] ^ nc[0]) | (c[1] ^ nc[1]) | (c[2] ^ nc[2]));
+        const int h = 31 - __builtin_clz(diff);
+        const int keep = D - 1 - h;     // deepest stack level still containing the new cell
+        if (keep < lvl) {
+            lvl = keep;
+            node = stk[lvl * kBlock];
+        }
+        c[0] = nc[0]; c[1] = nc[1]; c[2] = nc[2];
+        t_cur = t_exit;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Leaf evaluation at time t (Eq. 7 and Eq. 9): sigma_raw = sum_i k^sigma_i b_i
+// and h_c = sum_j z_{c,j} Y_j with z_{c,j} = sum_{i<5} k^z_{c,j,i} b_i.
+// ----------------------------------------------------------------------------
+template <int DT>
+struct LeafEval {
+    static constexpr int W = Pack<DT>::W;
+    static constexpr int kSigmaWords = (FPO_N_SIGMA + 1 + W - 1) / W;   // words holding q < 32
+    static constexpr int kWords = (FPO_N_COEFF + W - 1) / W;
+
+    // Loads the words holding q < 32 and returns sigma_raw (scaled for
+    // quantised stores).  `k` keeps the unpacked values for colour().
+    __device__ static inline float sigma(const TreeDev& T, int leaf, const float* b, float* k, float& scale)
+    {
+        const uint4* P = T.planes + leaf;
+#pragma unroll
+        for (int g = 0; g < kSigmaWords; ++g) {
+            const uint4 w = P[(int64_t)g * T.stride];
+            Pack<DT>::unpack(w, k + g * W);
+        }
+        float s = 0.0f;
+#pragma unroll
+        for (int q = 0; q < FPO_N_SIGMA; ++q) s = fmaf(k[q], b[q], s);
+        scale = (DT == FPO_F32) ? 1.0f : T.scale[leaf];
+        return s * scale;
+    }
+
+    // Colour pre-activations h[3]; k holds the first kSigmaWords words.
+    __device__ static inline void colour(const TreeDev& T, int leaf, const float* b, const float* Y,
+                                         const float* k, float scale, float* h)
+    {
+        const uint4* P = T.planes + leaf;
+        float kz[(kWords - kSigmaWords + 1) * W];
+        // coefficient q >= 31 lives at kz[q - 31 + off]
+        constexpr int off = FPO_N_SIGMA - (kSigmaWords - 1) * W;   // index of q = 31 inside the last sigma word
+#pragma unroll
+        for (int e = 0; e < W; ++e) kz[e] = k[(kSigmaWords - 1) * W + e];
+#pragma unroll
+        for (int g = kSigmaWords; g < kWords; ++g) {
+            const uint4 w = P[(int64_t)g * T.stride];
+            Pack<DT>::unpack(w, kz + (g - kSigmaWords + 1) * W);
+        }
+        h[0] = h[1] = h[2] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < FPO_N_SH; ++j) {
+                const int base = off + (c * FPO_N_SH + j) * FPO_N_SH_FOURIER;
+                float z = 0.0f;
+#pragma unroll
+                for (int i = 0; i < FPO_N_SH_FOURIER; ++i) z = fmaf(kz[base + i], b[i], z);
+                h[c] = fmaf(z, Y[j], h[c]);
+            }
+        h[0] *= scale; h[1] *= scale; h[2] *= scale;
+    }
+};
+
+__device__ inline float sigmoidf_(float h) { return __builtin_amdgcn_rcpf(1.0f + __expf(-h)); }
+
+// Snapshot reads: 28 baked values per leaf in planes [28][stride].
+template <int SDT>
+__device__ inline float snap_load(const void* S, int64_t stride, int row, int leaf)
+{
+    if (SDT == FPO_F32) return static_cast<const float*>(S)[(int64_t)row * stride + leaf];
+    const uint16_t v = static_cast<const uint16_t*>(S)[(int64_t)row * stride + leaf];
+    return __uint_as_float((uint32_t)v << 16);
+}
+
+// --------------------------------------------------------------------------
+// Front-to-back compositing visitor.  MODE: a coefficient dtype (Fourier
+// mode) or 16 + snapshot dtype (snapshot mode).
+// --------------------------------------------------------------------------
+constexpr int kSnapF32 = 16 + FPO_F32;
+constexpr int kSnapBF16 = 16 + FPO_BF16;
+
+template <int MODE>
+struct Shade {
+    const TreeDev& T;
+    const float* b;       // basis row (Fourier mode)
+    const void* snap;     // snapshot planes (snapshot mode)
+    float Y[9];
+    float Tr;             // transmittance
+    float C[3];
+    float stop_T;
+
+    __device__ inline bool segment(int leaf, float t0, float t1)
+    {
+        const float delta = t1 - t0;
+        float sraw, h[3];
+        if constexpr (MODE >= 16) {
+            constexpr int SDT = MODE - 16;
+            sraw = snap_load<SDT>(snap, T.stride, 0, leaf);
+            const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
+            if (!(sig * delta > 0.0f)) return false;
+            h[0] = h[1] = h[2] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < FPO_N_SH; ++j)
+                    h[c] = fmaf(snap_load<SDT>(snap, T.stride, 1 + c * FPO_N_SH + j, leaf), Y[j], h[c]);
+        } else {
+            constexpr int W = LeafEval<MODE>::W;
+            float k[LeafEval<MODE>::kSigmaWords * W];
+            float scale;
+            sraw = LeafEval<MODE>::sigma(T, leaf, b, k, scale);
+            const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
+            if (!(sig * delta > 0.0f)) return false;   // transparent: contributes nothing
+            LeafEval<MODE>::colour(T, leaf, b, Y, k, scale, h);
+        }
+        const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
+        const float e = __expf(-sig * delta);
+        const float w = Tr * (1.0f - e);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) C[c] = fmaf(w, sigmoidf_(h[c]), C[c]);
+        Tr *= e;
+        return Tr < stop_T;
+    }
+};
+
+}  // namespace dev
+}  // namespace fpo

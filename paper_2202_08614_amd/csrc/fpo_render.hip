@@ -1,0 +1,418 @@
+// libfpo render entry points: camera renders, ray renders, traces, camera
+// ray generation and coefficient packing (gfx950).
+//
+// Work mapping for camera renders: one wave64 renders an 8x8 pixel tile, a
+// 256-thread block a 16x16 tile.  Blocks are dispatched round-robin over the
+// 8 XCDs of the MI355X (each with its own L2); the block-to-tile map hands
+// each XCD a contiguous band of tiles so that neighbouring rays, which cross
+// the same leaves, share one L2.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "fpo.h"
+#include "fpo_device.h"
+#include "fpo_internal.h"
+
+namespace fpo {
+namespace dev {
+
+constexpr int kCamsPerLaunch = 16;
+
+struct CamDev {
+    float frame[12];                 // eye, forward, right * tan_x, up * tan_y
+    float basis[FPO_BASIS_STRIDE];   // Eq. 8 at the camera's time
+    const void* snap;                // snapshot planes for this camera (snapshot mode)
+};
+
+struct CamLaunch {
+    TreeDev tree;
+    CamDev cam[kCamsPerLaunch];
+    float* rgb;                      // [n_cams][H][W][3] of this launch
+    float* Tout;                     // [n_cams][H][W] or null
+    int32_t W, H, bx_per_cam, blocks_per_cam, n_cams;
+    float bg[3];
+    float stop_T;
+};
+static_assert(sizeof(CamLaunch) <= 4096, "kernel argument block too large");
+
+// Block index -> logical tile, giving XCD x (blocks x, x+8, ...) the
+// contiguous range [x * per, (x + 1) * per).  gridDim.x is a multiple of 8.
+__device__ inline int xcd_band(int bid, int nblocks)
+{
+    const int per = nblocks >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
+{
+    __shared__ int s_stack[kStackLevels * kBlock];
+    const int lin = xcd_band(blockIdx.x, gridDim.x);
+    if (lin >= a.n_cams * a.blocks_per_cam) return;
+    const int ci = lin / a.blocks_per_cam;
+    const int tb = lin - ci * a.blocks_per_cam;
+    const int bx = tb % a.bx_per_cam;
+    const int by = tb / a.bx_per_cam;
+    const int wv = threadIdx.x >> 6;
+    const int ln = threadIdx.x & 63;
+    const int px = bx * 16 + (wv & 1) * 8 + (ln & 7);
+    const int py = by * 16 + (wv >> 1) * 8 + (ln >> 3);
+    if (px >= a.W || py >= a.H) return;
+
+    const CamDev& cam = a.cam[ci];
+    float b[FPO_BASIS_STRIDE];
+#pragma unroll
+    for (int i = 0; i < FPO_BASIS_STRIDE; ++i) b[i] = cam.basis[i];
+    const float sx = (float)(2 * px + 1) / (float)a.W - 1.0f;
+    const float sy = 1.0f - (float)(2 * py + 1) / (float)a.H;
+    const float dx = cam.frame[3] + sx * cam.frame[6] + sy * cam.frame[9];
+    const float dy = cam.frame[4] + sx * cam.frame[7] + sy * cam.frame[10];
+    const float dz = cam.frame[5] + sx * cam.frame[8] + sy * cam.frame[11];
+
+    Shade<MODE> sh{a.tree, b, cam.snap};
+    sh.Tr = 1.0f;
+    sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
+    sh.stop_T = a.stop_T;
+    Ray r;
+    if (setup_ray(cam.frame[0], cam.frame[1], cam.frame[2], dx, dy, dz, r)) {
+        sh9(r.d[0], r.d[1], r.d[2], sh.Y);
+        walk(a.tree, r, s_stack + threadIdx.x, sh);
+    }
+    const int64_t pix = ((int64_t)ci * a.H + py) * a.W + px;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.rgb[pix * 3 + c] = fmaf(sh.Tr, a.bg[c], sh.C[c]);
+    if (a.Tout) a.Tout[pix] = sh.Tr;
+}
+
+struct RaysLaunch {
+    TreeDev tree;
+    const float* o;
+    const float* d;
+    const int32_t* t_idx;
+    const float* basis;     // [n_t][32]
+    const void* snap;
+    int64_t snap_stride;    // elements between consecutive time indices' snapshots
+    int64_t n;
+    int32_t n_t;
+    float* rgb;
+    float* Tout;
+    float bg[3];
+    float stop_T;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void render_rays_kernel(RaysLaunch a)
+{
+    __shared__ int s_stack[kStackLevels * kBlock];
+    const int64_t r_id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r_id >= a.n) return;
+    int ti = a.t_idx[r_id];
+    ti = min(max(ti, 0), a.n_t - 1);
+    float b[FPO_BASIS_STRIDE];
+    const float4* brow = reinterpret_cast<const float4*>(a.basis + (int64_t)ti * FPO_BASIS_STRIDE);
+#pragma unroll
+    for (int i = 0; i < FPO_BASIS_STRIDE / 4; ++i) {
+        const float4 v = brow[i];
+        b[4 * i] = v.x; b[4 * i + 1] = v.y; b[4 * i + 2] = v.z; b[4 * i + 3] = v.w;
+    }
+    const void* snap = a.snap;
+    if constexpr (MODE >= 16) {
+        const size_t esz = (MODE - 16) == FPO_F32 ? 4 : 2;
+        snap = static_cast<const char*>(a.snap) + (size_t)ti * (size_t)a.snap_stride * esz;
+    }
+    Shade<MODE> sh{a.tree, b, snap};
+    sh.Tr = 1.0f;
+    sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
+    sh.stop_T = a.stop_T;
+    Ray r;
+    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+                  a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
+        sh9(r.d[0], r.d[1], r.d[2], sh.Y);
+        walk(a.tree, r, s_stack + threadIdx.x, sh);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.rgb[r_id * 3 + c] = fmaf(sh.Tr, a.bg[c], sh.C[c]);
+    if (a.Tout) a.Tout[r_id] = sh.Tr;
+}
+
+// Records the walk's segments, with distances from the caller's origin.
+struct TraceVisitor {
+    int32_t* ids;
+    float* t01;
+    int32_t cap;
+    int32_t n;
+    float t_in;
+    __device__ inline bool segment(int leaf, float t0, float t1)
+    {
+        if (n < cap) {
+            ids[n] = leaf;
+            t01[2 * n] = t_in + t0;
+            t01[2 * n + 1] = t_in + t1;
+        }
+        ++n;
+        return false;
+    }
+};
+
+struct TraceLaunch {
+    TreeDev tree;
+    const float* o;
+    const float* d;
+    int64_t n;
+    int32_t cap;
+    int32_t* ids;
+    float* t01;
+    int32_t* n_visits;
+};
+
+__global__ __launch_bounds__(kBlock) void trace_rays_kernel(TraceLaunch a)
+{
+    __shared__ int s_stack[kStackLevels * kBlock];
+    const int64_t r_id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r_id >= a.n) return;
+    TraceVisitor v{a.ids + r_id * a.cap, a.t01 + r_id * a.cap * 2, a.cap, 0, 0.0f};
+    Ray r;
+    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+                  a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
+        v.t_in = r.t_in;
+        walk(a.tree, r, s_stack + threadIdx.x, v);
+    }
+    a.n_visits[r_id] = v.n;
+}
+
+__global__ __launch_bounds__(kBlock) void camera_rays_kernel(const float* table, int32_t n_cams,
+                                                             const int32_t* cam, const int32_t* py,
+                                                             const int32_t* px, int64_t n, float* o, float* d)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n) return;
+    const int ci = min(max(cam[r], 0), n_cams - 1);
+    const float* f = table + (int64_t)ci * FPO_CAMERA_FLOATS;
+    const float W = f[12], H = f[13];
+    const float sx = (float)(2 * px[r] + 1) / W - 1.0f;
+    const float sy = 1.0f - (float)(2 * py[r] + 1) / H;
+    float v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = f[3 + a] + sx * f[6 + a] + sy * f[9 + a];
+    const float inv = 1.0f / sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o[3 * r + a] = f[a];
+        d[3 * r + a] = v[a] * inv;
+    }
+}
+
+// dst word (g, slot) = coefficients 4g .. 4g+3 of leaf perm[slot].
+__global__ __launch_bounds__(kBlock) void pack_coeffs_kernel(const float* src, const int64_t* perm,
+                                                             int64_t n_leaves, int64_t stride, float4* dst)
+{
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t n_planes = (FPO_N_COEFF + 3) / 4;
+    if (id >= n_planes * stride) return;
+    const int64_t g = id / stride;
+    const int64_t slot = id - g * stride;
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (slot < n_leaves) {
+        const int64_t p = perm[slot];
+        if (p >= 0 && p < n_leaves) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t q = 4 * g + e;
+                if (q < FPO_N_COEFF) v[e] = src[p * FPO_N_COEFF + q];
+            }
+        }
+    }
+    dst[id] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+}  // namespace dev
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+static dev::TreeDev tree_dev(const fpo_tree_view* t)
+{
+    dev::TreeDev d;
+    d.children = t->children;
+    d.planes = static_cast<const uint4*>(t->coeffs);
+    d.scale = t->leaf_scale;
+    d.stride = t->leaf_stride;
+    d.n_nodes = (int32_t)t->n_nodes;
+    d.n_leaves = (int32_t)t->n_leaves;
+    d.max_depth = t->max_depth;
+    d.sigma_scale = t->layout.sigma_scale;
+    return d;
+}
+
+static fpo_status launch_status(const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FPO_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return FPO_OK;
+}
+
+static int mode_of(const fpo_tree_view* t, const fpo_render_opts* o)
+{
+    if (o->snapshot) return 16 + (int)o->snapshot_dtype;
+    return (int)t->dtype;
+}
+
+}  // namespace fpo
+
+using namespace fpo;
+
+template <int MODE>
+static void launch_cam(const dev::CamLaunch& a, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::render_cam_kernel<MODE>, dim3(grid), dim3(dev::kBlock), 0, s, a);
+}
+
+extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
+                                 const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
+{
+    fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr);
+    if (st != FPO_OK) return st;
+    if ((st = check_opts(opts, tree)) != FPO_OK) return st;
+    if (!cams || n_cams < 1) return fail(FPO_E_INVALID, "cams is NULL or n_cams < 1");
+    if (!rgb_out) return fail(FPO_E_INVALID, "rgb_out is NULL");
+    const int W = cams[0].width, H = cams[0].height;
+    for (int i = 0; i < n_cams; ++i)
+        if (cams[i].width != W || cams[i].height != H)
+            return fail(FPO_E_INVALID, "all cameras of one call must share width and height");
+    if ((int64_t)W * H > (1ll << 30)) return fail(FPO_E_INVALID, "image too large");
+    // Validate every camera before launching anything.
+    static thread_local dev::CamLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    for (int i = 0; i < n_cams; ++i) {
+        float fr[12];
+        if ((st = camera_frame(cams[i], fr)) != FPO_OK) return st;
+    }
+    a.tree = tree_dev(tree);
+    a.W = W;
+    a.H = H;
+    a.bx_per_cam = (W + 15) / 16;
+    a.blocks_per_cam = a.bx_per_cam * ((H + 15) / 16);
+    for (int c = 0; c < 3; ++c) a.bg[c] = opts->bg[c];
+    a.stop_T = opts->stop_T;
+    const int mode = mode_of(tree, opts);
+    const size_t snap_esz = opts->snapshot_dtype == FPO_F32 ? 4 : 2;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int c0 = 0; c0 < n_cams; c0 += dev::kCamsPerLaunch) {
+        const int nc = std::min(dev::kCamsPerLaunch, n_cams - c0);
+        a.n_cams = nc;
+        for (int i = 0; i < nc; ++i) {
+            const fpo_camera& cam = cams[c0 + i];
+            camera_frame(cam, a.cam[i].frame);
+            basis_row(cam.time, (double)tree->layout.period, tree->layout.n_sigma, a.cam[i].basis);
+            a.cam[i].snap = opts->snapshot
+                ? static_cast<const char*>(opts->snapshot) + (size_t)(c0 + i) * (size_t)opts->snapshot_cam_stride * snap_esz
+                : nullptr;
+        }
+        a.rgb = rgb_out + (int64_t)c0 * W * H * 3;
+        a.Tout = T_out ? T_out + (int64_t)c0 * W * H : nullptr;
+        const int64_t total = (int64_t)nc * a.blocks_per_cam;
+        if (total > INT32_MAX - 8) return fail(FPO_E_INVALID, "launch too large");
+        const int grid = (int)((total + 7) / 8 * 8);
+        switch (mode) {
+            case FPO_F32: launch_cam<FPO_F32>(a, grid, s); break;
+            case FPO_BF16: launch_cam<FPO_BF16>(a, grid, s); break;
+            case FPO_FP8_E4M3: launch_cam<FPO_FP8_E4M3>(a, grid, s); break;
+            case dev::kSnapF32: launch_cam<dev::kSnapF32>(a, grid, s); break;
+            case dev::kSnapBF16: launch_cam<dev::kSnapBF16>(a, grid, s); break;
+            default: return fail(FPO_E_INVALID, "unknown render mode");
+        }
+        if ((st = launch_status("fpo_render")) != FPO_OK) return st;
+    }
+    return FPO_OK;
+}
+
+template <int MODE>
+static void launch_rays(const dev::RaysLaunch& a, int64_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::render_rays_kernel<MODE>, dim3((unsigned)grid), dim3(dev::kBlock), 0, s, a);
+}
+
+extern "C" fpo_status fpo_render_rays(const fpo_tree_view* tree, const float* o, const float* d,
+                                      const int32_t* t_idx, const float* basis, int32_t n_t, int64_t n_rays,
+                                      const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
+{
+    fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr);
+    if (st != FPO_OK) return st;
+    if ((st = check_opts(opts, tree)) != FPO_OK) return st;
+    if (n_rays < 0) return fail(FPO_E_INVALID, "n_rays < 0");
+    if (n_rays == 0) return FPO_OK;
+    if (!o || !d || !t_idx || !basis || !rgb_out) return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
+    if (n_rays > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rays");
+    dev::RaysLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.tree = tree_dev(tree);
+    a.o = o; a.d = d; a.t_idx = t_idx; a.basis = basis; a.n_t = n_t; a.n = n_rays;
+    a.snap = opts->snapshot;
+    a.snap_stride = opts->snapshot_cam_stride;
+    a.rgb = rgb_out; a.Tout = T_out;
+    for (int c = 0; c < 3; ++c) a.bg[c] = opts->bg[c];
+    a.stop_T = opts->stop_T;
+    const int64_t grid = (n_rays + dev::kBlock - 1) / dev::kBlock;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (mode_of(tree, opts)) {
+        case FPO_F32: launch_rays<FPO_F32>(a, grid, s); break;
+        case FPO_BF16: launch_rays<FPO_BF16>(a, grid, s); break;
+        case FPO_FP8_E4M3: launch_rays<FPO_FP8_E4M3>(a, grid, s); break;
+        case dev::kSnapF32: launch_rays<dev::kSnapF32>(a, grid, s); break;
+        case dev::kSnapBF16: launch_rays<dev::kSnapBF16>(a, grid, s); break;
+        default: return fail(FPO_E_INVALID, "unknown render mode");
+    }
+    return launch_status("fpo_render_rays");
+}
+
+extern "C" fpo_status fpo_trace_rays(const fpo_tree_view* tree, const float* o, const float* d, int64_t n_rays,
+                                     int32_t max_visits, int32_t* leaf_ids, float* t01, int32_t* n_visits,
+                                     void* stream)
+{
+    fpo_status st = check_tree(tree, false);
+    if (st != FPO_OK) return st;
+    if (n_rays < 0 || max_visits < 0) return fail(FPO_E_INVALID, "negative size");
+    if (n_rays == 0) return FPO_OK;
+    if (!o || !d || !n_visits || (max_visits > 0 && (!leaf_ids || !t01)))
+        return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_rays > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rays");
+    dev::TraceLaunch a;
+    a.tree = tree_dev(tree);
+    a.o = o; a.d = d; a.n = n_rays; a.cap = max_visits; a.ids = leaf_ids; a.t01 = t01; a.n_visits = n_visits;
+    const int64_t grid = (n_rays + dev::kBlock - 1) / dev::kBlock;
+    hipLaunchKernelGGL(dev::trace_rays_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,
+                       static_cast<hipStream_t>(stream), a);
+    return launch_status("fpo_trace_rays");
+}
+
+extern "C" fpo_status fpo_camera_rays(const float* cam_table, int32_t n_cams, const int32_t* cam,
+                                      const int32_t* py, const int32_t* px, int64_t n,
+                                      float* o_out, float* d_out, void* stream)
+{
+    if (n < 0) return fail(FPO_E_INVALID, "n < 0");
+    if (n == 0) return FPO_OK;
+    if (!cam_table || !cam || !py || !px || !o_out || !d_out) return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_cams < 1) return fail(FPO_E_INVALID, "n_cams must be >= 1");
+    if (n > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rays");
+    const int64_t grid = (n + dev::kBlock - 1) / dev::kBlock;
+    hipLaunchKernelGGL(dev::camera_rays_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,
+                       static_cast<hipStream_t>(stream), cam_table, n_cams, cam, py, px, n, o_out, d_out);
+    return launch_status("fpo_camera_rays");
+}
+
+extern "C" fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
+                                      int64_t leaf_stride, float* dst, void* stream)
+{
+    if (!src || !perm || !dst) return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_leaves < 1 || leaf_stride < n_leaves) return fail(FPO_E_INVALID, "bad n_leaves / leaf_stride");
+    const int64_t total = (int64_t)((FPO_N_COEFF + 3) / 4) * leaf_stride;
+    if (total > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many leaves");
+    const int64_t grid = (total + dev::kBlock - 1) / dev::kBlock;
+    hipLaunchKernelGGL(dev::pack_coeffs_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,
+                       static_cast<hipStream_t>(stream), src, perm, n_leaves, leaf_stride,
+                       reinterpret_cast<float4*>(dst));
+    return launch_status("fpo_pack_coeffs");
+}

@@ -1,0 +1,165 @@
+"""libfpo host-side checks that need no GPU: the library loads and exports
+every symbol of include/fpo.h, the octree builder, the FP64 time basis,
+camera packing and argument validation."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_08614_amd import _lib, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "fpo.h")).read()
+    return sorted(set(re.findall(r"^(?:fpo_status|const char\*)\s+(fpo_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _header_functions()
+    assert "fpo_render" in names and "fpo_build_tree" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(_lib.exported_symbols()) | {"fpo_last_error"}
+
+
+def _descend(children, max_depth, x, y, z):
+    node = 0
+    for lvl in range(max_depth):
+        sh = max_depth - 1 - lvl
+        oct_ = ((x >> sh) & 1) | (((y >> sh) & 1) << 1) | (((z >> sh) & 1) << 2)
+        ch = int(children[node, oct_])
+        if ch > 0:
+            node = ch
+            continue
+        return -ch - 1 if ch < 0 else -1
+    raise AssertionError("walked below max_depth")
+
+
+@pytest.mark.parametrize("seed,depth", [(0, 3), (4, 5), (7, 6)])
+def test_build_tree_point_location(oracle_lib, seed, depth):
+    dijk = synth.random_tree_leaves(seed, depth)
+    children, perm = _lib.build_tree(dijk, depth)
+    tree = oracle_lib.OracleTree(dijk, depth)
+    G = 1 << depth
+    rng = np.random.default_rng(seed)
+    for _ in range(400):
+        x, y, z = (int(v) for v in rng.integers(0, G, 3))
+        slot = _descend(children, depth, x, y, z)
+        want = tree.locate(x, y, z)
+        assert (perm[slot] if slot >= 0 else -1) == want
+
+
+def test_build_tree_morton_order_and_bfs():
+    dijk = synth.random_tree_leaves(3, 5)
+    children, perm = _lib.build_tree(dijk, 5)
+    assert sorted(perm.tolist()) == list(range(len(dijk)))
+
+    def morton(d, i, j, k):
+        sh = 5 - d
+        i, j, k = i << sh, j << sh, k << sh
+        m = 0
+        for b in range(5):
+            m |= ((i >> b) & 1) << (3 * b) | ((j >> b) & 1) << (3 * b + 1) | ((k >> b) & 1) << (3 * b + 2)
+        return m
+    codes = [morton(*dijk[p]) for p in perm]
+    assert codes == sorted(codes)
+    # breadth first: a child node id is always larger than its parent's
+    for n in range(children.shape[0]):
+        for ch in children[n]:
+            if ch > 0:
+                assert ch > n
+
+
+def test_build_tree_c1_counts():
+    sc = synth.c1_scene()
+    children, perm = _lib.build_tree(sc.leaf_dijk, 6)
+    assert len(perm) == 20536
+    assert (children < 0).sum() == 20536
+
+
+def test_build_tree_errors():
+    cases = [
+        (np.array([[0, 0, 0, 0]], np.int32), 3, _lib.FPO_E_INVALID, "depth"),
+        (np.array([[2, 4, 0, 0]], np.int32), 3, _lib.FPO_E_INVALID, "coordinate"),
+        (np.array([[2, 1, 1, 1], [2, 1, 1, 1]], np.int32), 3, _lib.FPO_E_INVALID, "duplicate"),
+        (np.array([[1, 0, 0, 0], [2, 1, 1, 1]], np.int32), 3, _lib.FPO_E_INVALID, "overlapping"),
+        (np.array([[1, 0, 0, 0]], np.int32), 11, _lib.FPO_E_INVALID, "max_depth"),
+    ]
+    for dijk, md, st, msg in cases:
+        with pytest.raises(_lib.FpoError, match=msg) as e:
+            _lib.build_tree(dijk, md)
+        assert e.value.status == st
+    # capacity: a too-small node buffer reports the count
+    L = _lib.lib()
+    dijk = np.array([[3, 1, 2, 3], [3, 7, 7, 7]], np.int32)
+    n_nodes = ctypes.c_int64(0)
+    buf = np.zeros((1, 8), np.int32)
+    st = L.fpo_build_tree(dijk.ctypes.data_as(ctypes.c_void_p), 2, 3, buf.ctypes.data_as(ctypes.c_void_p), 1,
+                          ctypes.byref(n_nodes), None)
+    assert st == _lib.FPO_E_CAPACITY and n_nodes.value == 5
+
+
+def test_time_basis_matches_oracle(oracle_lib):
+    times = [0.0, 22.2, 59.99, -7.5, 1234.5]
+    got = _lib.time_basis(times)
+    for r, t in enumerate(times):
+        ref = oracle_lib.basis(t, 60.0, 31)
+        assert np.array_equal(got[r, :31], ref.astype(np.float32))
+        assert np.all(got[r, 31:] == 0)
+
+
+def test_camera_pack_reproduces_oracle_rays(oracle_lib):
+    cam = synth.ring_camera(0.3, 0.2, 1.5, 45.0, 7, 5, 0.0)
+    tab = _lib.camera_pack([cam])[0]
+    o_ref, d_ref = oracle_lib.camera_rays(cam)
+    k = 0
+    for py in range(5):
+        for px in range(7):
+            sx = (2 * px + 1) / 7 - 1
+            sy = 1 - (2 * py + 1) / 5
+            v = tab[3:6].astype(np.float64) + sx * tab[6:9] + sy * tab[9:12]
+            v /= np.linalg.norm(v)
+            assert np.allclose(v, d_ref[k], atol=2e-7)
+            assert np.allclose(tab[:3], o_ref[k])
+            k += 1
+    assert tab[12] == 7 and tab[13] == 5
+
+
+def test_camera_validation():
+    bad = synth.Camera(eye=[0, 0, 0], fwd=[0, 1, 0], up=[0, 1, 0], fov_y_deg=30, width=4, height=4, time=0)
+    with pytest.raises(_lib.FpoError, match="parallel"):
+        _lib.camera_pack([bad])
+    bad = synth.Camera(eye=[0, 0, 0], fwd=[0, 0, 1], up=[0, 1, 0], fov_y_deg=30, width=0, height=4, time=0)
+    with pytest.raises(_lib.FpoError, match="size"):
+        _lib.camera_pack([bad])
+    with pytest.raises(_lib.FpoError, match="finite"):
+        _lib.time_basis([math.nan])
+
+
+def test_device_calls_reject_bad_arguments_without_launching():
+    """Validation happens on the host before any launch, so these run without a GPU."""
+    L = _lib.lib()
+    view = _lib.TreeView()
+    opts = _lib.make_opts()
+    cams = _lib.camera_struct([synth.ring_camera(0, 0, 1.5, 30, 4, 4, 0)])
+    st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), None, None, None)
+    assert st == _lib.FPO_E_INVALID and b"children" in L.fpo_last_error()
+    view.children = 16
+    view.n_nodes = 1
+    view.max_depth = 3
+    view.n_leaves = 1
+    view.leaf_stride = 1
+    view.coeffs = 16
+    view.layout = _lib.Layout(21, 5, 2, 60.0, 64.0)
+    st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_UNSUPPORTED
+    view.layout = _lib.make_layout()
+    opts.stop_T = 1.5
+    st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_INVALID and b"stop_T" in L.fpo_last_error()
