@@ -65,6 +65,7 @@ def lib():
         L.or_basis.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P]
         L.or_sh9.argtypes = [_P, _P]
         L.or_camera_ray.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int32, ctypes.c_int32, _P, _P]
+        L.or_camera_rays.argtypes = [ctypes.POINTER(_Camera), ctypes.c_int64, _P, _P, _P, _P]
         L.or_tree_build.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.or_tree_build.restype = ctypes.c_void_p
         L.or_tree_free.argtypes = [ctypes.c_void_p]
@@ -117,16 +118,12 @@ def camera_rays(cam, px: Optional[np.ndarray] = None, py: Optional[np.ndarray] =
         yy, xx = np.meshgrid(np.arange(cam.height), np.arange(cam.width), indexing="ij")
         px, py = xx.reshape(-1), yy.reshape(-1)
     c = _camera_struct(cam)
+    px = np.ascontiguousarray(px, dtype=np.int32)
+    py = np.ascontiguousarray(py, dtype=np.int32)
     n = len(px)
     o = np.zeros((n, 3))
     d = np.zeros((n, 3))
-    L = lib()
-    ob = np.zeros(3)
-    db = np.zeros(3)
-    for r in range(n):
-        L.or_camera_ray(ctypes.byref(c), int(px[r]), int(py[r]), _ptr(ob), _ptr(db))
-        o[r] = ob
-        d[r] = db
+    lib().or_camera_rays(ctypes.byref(c), n, _ptr(px), _ptr(py), _ptr(o), _ptr(d))
     return o, d
 
 

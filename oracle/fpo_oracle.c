@@ -116,6 +116,13 @@ void or_camera_ray(const or_camera* cam, int32_t px, int32_t py, double o[3], do
     or_normalize(d);
 }
 
+/* Rays for n pixels of one camera. */
+void or_camera_rays(const or_camera* cam, int64_t n, const int32_t* px, const int32_t* py,
+                    double* o, double* d)
+{
+    for (int64_t r = 0; r < n; ++r) or_camera_ray(cam, px[r], py[r], o + 3 * r, d + 3 * r);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Octree leaves, located through a hash of (depth, i, j, k).                */
 /* ------------------------------------------------------------------------ */

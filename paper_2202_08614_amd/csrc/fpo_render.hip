@@ -65,8 +65,9 @@ __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
     float b[FPO_BASIS_STRIDE];
 #pragma unroll
     for (int i = 0; i < FPO_BASIS_STRIDE; ++i) b[i] = cam.basis[i];
-    const float sx = (float)(2 * px + 1) / (float)a.W - 1.0f;
-    const float sy = 1.0f - (float)(2 * py + 1) / (float)a.H;
+    // exact integer numerators: no cancellation near the image centre
+    const float sx = (float)(2 * px + 1 - a.W) / (float)a.W;
+    const float sy = (float)(a.H - 2 * py - 1) / (float)a.H;
     const float dx = cam.frame[3] + sx * cam.frame[6] + sy * cam.frame[9];
     const float dy = cam.frame[4] + sx * cam.frame[7] + sy * cam.frame[10];
     const float dz = cam.frame[5] + sx * cam.frame[8] + sy * cam.frame[11];
@@ -190,9 +191,9 @@ __global__ __launch_bounds__(kBlock) void camera_rays_kernel(const float* table,
     if (r >= n) return;
     const int ci = min(max(cam[r], 0), n_cams - 1);
     const float* f = table + (int64_t)ci * FPO_CAMERA_FLOATS;
-    const float W = f[12], H = f[13];
-    const float sx = (float)(2 * px[r] + 1) / W - 1.0f;
-    const float sy = 1.0f - (float)(2 * py[r] + 1) / H;
+    const int W = (int)f[12], H = (int)f[13];
+    const float sx = (float)(2 * px[r] + 1 - W) / (float)W;
+    const float sy = (float)(H - 2 * py[r] - 1) / (float)H;
     float v[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[a] = f[3 + a] + sx * f[6 + a] + sy * f[9 + a];

@@ -3,7 +3,12 @@
 Bar: FP32 render within 1e-4 absolute per RGB channel of the oracle (the
 closer of its two outcomes where the FP64 transmittance straddles the
 early-termination threshold); visited-leaf lists equal after dropping
-segments whose FP64 length is below 1e-6 (grazing and tie cases).
+segments whose FP64 length is below 1e-6.  Ties: a ray whose visited list
+changes when it is shifted sideways by 1e-6 runs within 1e-6 of a cell face
+and is exempt from the list check; a ray whose FP64 colour moves by more than
+1e-4 under a 2e-7 shift (the FP32 resolution of a camera ray) is exempt from
+the colour bar and held to its spread at 1e-6 instead.  Exempt rays are
+counted and must stay rare.
 """
 import math
 
@@ -12,7 +17,7 @@ import pytest
 
 from oracle.brute import chord_length, leaf_boxes
 from paper_2202_08614_amd import _lib, synth
-from tests.gpu_util import note, require_gpu, straddle_err
+from tests.gpu_util import check_parity, conditioned_reference, note, perpendicular_pair, require_gpu, straddle_err
 
 pytestmark = pytest.mark.gpu
 
@@ -42,12 +47,11 @@ def test_c1_render_parity(oracle_lib, c1, dev):
     T = T.cpu().numpy().reshape(-1)
     o, d = oracle_lib.camera_rays(cam)
     ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
-    ref = oracle_lib.render_rays(ot, sc.coeffs, oracle_lib.make_params(), [cam.time], o, d,
-                                 np.zeros(len(o), np.int32), n_threads=8)
-    err = np.max(np.abs(rgb - ref["rgb"][:, 0]), axis=1)
+    ref = conditioned_reference(oracle_lib, ot, sc.coeffs, oracle_lib.make_params(), [cam.time], o, d,
+                                np.zeros(len(o), np.int32))
     assert (ref["T"][:, 0] < 0.99).sum() > 500          # the view hits the shell
-    assert err.max() <= TOL, (err.max(), int(err.argmax()))
-    assert np.max(np.abs(T - ref["T"][:, 0])) <= TOL
+    err, exempt = check_parity(rgb, ref, TOL)
+    assert np.max(np.abs(T - ref["T"][:, 0])[~exempt]) <= TOL
 
 
 def _compare_lists(gpu_ids, gpu_t, n_vis, o, d, ref_trace, boxes, perm):
@@ -75,12 +79,24 @@ def test_c1_trace_lists(oracle_lib, c1, dev):
     ids, t01, nv = ids.cpu().numpy(), t01.cpu().numpy(), nv.cpu().numpy()
     ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
     boxes = leaf_boxes(sc.leaf_dijk)
+    o_all = o32.astype(np.float64)
+    d_all = d32.astype(np.float64)
+    d_all /= np.linalg.norm(d_all, axis=1, keepdims=True)
+    u_all, v_all = perpendicular_pair(d_all)
     total = 0
+    exempt = 0
     for r in range(len(o32)):
-        o, d = o32[r].astype(np.float64), d32[r].astype(np.float64)
-        d = d / np.linalg.norm(d)
+        o, d = o_all[r], d_all[r]
         assert nv[r] <= 256
         ref = ot.trace(o, d)
+        want = list(ref[0][(ref[2] - ref[1]) >= 1e-6])
+        stable = True
+        for w in (u_all[r], -u_all[r], v_all[r], -v_all[r]):
+            alt = ot.trace(o + 1e-6 * w, d)
+            stable &= list(alt[0][(alt[2] - alt[1]) >= 1e-6]) == want
+        if not stable:        # the ray runs within 1e-6 of a cell face
+            exempt += 1
+            continue
         total += _compare_lists(ids[r], t01[r], nv[r], o, d, ref, boxes, tree.perm)
         # entry/exit distances of the kept segments agree to FP32 accuracy
         if len(ref[0]):
@@ -91,6 +107,7 @@ def test_c1_trace_lists(oracle_lib, c1, dev):
             for l, a, b in kept:
                 assert abs(mp[l][0] - a) < 2e-6 and abs(mp[l][1] - b) < 2e-6
     assert total > 5000
+    assert exempt <= 0.01 * len(o32)
 
 
 @pytest.mark.parametrize("seed,depth,stop_T", [(11, 5, 0.0), (12, 7, 0.0), (13, 6, 1e-2)])
@@ -111,10 +128,9 @@ def test_random_trees_render_rays(oracle_lib, dev, seed, depth, stop_T):
     torch.cuda.synchronize()
     ot = oracle_lib.OracleTree(dijk, depth)
     p = oracle_lib.make_params(stop_T=stop_T, bg=(0.1, 0.2, 0.3), sigma_scale=16.0)
-    ref = oracle_lib.render_rays(ot, coeffs, p, times, o.astype(np.float64), d.astype(np.float64), t_idx, n_threads=8)
-    err = straddle_err(rgb.cpu().numpy(), ref["rgb"])
+    ref = conditioned_reference(oracle_lib, ot, coeffs, p, times, o, d, t_idx)
     assert (ref["n_cells"] > 0).sum() > n // 3
-    assert err.max() <= TOL, (err.max(), int(err.argmax()))
+    check_parity(rgb.cpu().numpy(), ref, TOL)
 
 
 def test_edge_rays(oracle_lib, dev):
@@ -164,12 +180,11 @@ def test_ragged_images(oracle_lib, c1, dev, W, H):
     torch.cuda.synchronize()
     o, d = oracle_lib.camera_rays(cam)
     ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
-    ref = oracle_lib.render_rays(ot, sc.coeffs, oracle_lib.make_params(stop_T=1e-3), [cam.time], o, d,
-                                 np.zeros(len(o), np.int32), n_threads=8)
+    ref = conditioned_reference(oracle_lib, ot, sc.coeffs, oracle_lib.make_params(stop_T=1e-3), [cam.time], o, d,
+                                np.zeros(len(o), np.int32))
     g = rgb.cpu().numpy()
     assert np.array_equal(g[0], g[1])
-    err = straddle_err(g[0].reshape(-1, 3), ref["rgb"])
-    assert err.max() <= TOL
+    check_parity(g[0].reshape(-1, 3), ref, TOL, max_exempt_frac=0.02 if W * H > 1 else 0.0)
 
 
 def test_camera_rays_match_oracle(oracle_lib, dev):
@@ -238,18 +253,18 @@ def test_c2_sampled_parity(oracle_lib, c2, dev):
     m = 3000
     ci = rng.integers(0, 16, m)
     central = rng.random(m) < 0.8
-    px = np.where(central, rng.integers(1920 // 4, 3 * 1920 // 4, m), rng.integers(0, 1920, m))
-    py = np.where(central, rng.integers(1080 // 6, 5 * 1080 // 6, m), rng.integers(0, 1080, m))
+    # the blob covers roughly the central third of the columns and half of the rows
+    px = np.where(central, rng.integers(int(0.35 * 1920), int(0.65 * 1920), m), rng.integers(0, 1920, m))
+    py = np.where(central, rng.integers(int(0.25 * 1080), int(0.75 * 1080), m), rng.integers(0, 1080, m))
     ot = oracle_lib.OracleTree(sc.leaf_dijk, 9)
     p = oracle_lib.make_params(stop_T=sc.stop_T, band=1e-3)
     o = np.zeros((m, 3)); d = np.zeros((m, 3))
     for k in range(m):
         ro, rd = oracle_lib.camera_rays(cams[ci[k]], np.array([px[k]]), np.array([py[k]]))
         o[k], d[k] = ro[0], rd[0]
-    ref = oracle_lib.render_rays(ot, sc.coeffs, p, [cams[0].time], o, d, np.zeros(m, np.int32), n_threads=8)
+    ref = conditioned_reference(oracle_lib, ot, sc.coeffs, p, [cams[0].time], o, d, np.zeros(m, np.int32))
     got = rgb[ci, py, px]
-    err = straddle_err(got, ref["rgb"])
     hit = ref["n_seg"][:, 0] > 0
     assert hit.sum() > m // 3
     assert (ref["T"][:, 1] < 1e-3).sum() > 50          # early termination is exercised
-    assert err.max() <= TOL, (err.max(), int(err.argmax()))
+    check_parity(got, ref, TOL)
