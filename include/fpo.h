@@ -194,6 +194,46 @@ fpo_status fpo_trace_rays(const fpo_tree_view* tree, const float* o, const float
                           int32_t max_visits, int32_t* leaf_ids, float* t01, int32_t* n_visits,
                           void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Fine-tuning (Sec. 4.3)                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Gradient of a loss L w.r.t. the leaf coefficients, through the render of
+ * fpo_render_rays (Sec. 4.3: the IDFT is differentiable, so the photometric
+ * loss of Eq. 13 back-propagates into the Fourier coefficients).  Each ray's
+ * walk and shading are recomputed; nothing per sample is stored.
+ *   o, d, t_idx, basis, n_t, n_rays, opts: as passed to fpo_render_rays
+ *            (opts->snapshot must be NULL; the store must be FPO_F32).
+ *   rgb_fwd  device [n_rays][3], the forward colours of these rays.
+ *   grad_rgb device [n_rays][3], dL/d rgb.
+ *   grad_coeffs device F32 packed planes shaped like the coefficient store
+ *            (42 planes x leaf_stride words); gradients are ADDED (FP32 atomics,
+ *            so the summation order, and the last bits, vary run to run).
+ * The early-termination decision is taken as in the forward pass and treated
+ * as constant; the ReLU derivative at sigma = 0 is 0. */
+fpo_status fpo_render_backward(const fpo_tree_view* tree, const float* o, const float* d,
+                               const int32_t* t_idx, const float* basis, int32_t n_t, int64_t n_rays,
+                               const fpo_render_opts* opts, const float* rgb_fwd, const float* grad_rgb,
+                               float* grad_coeffs, void* stream);
+
+/* L2 photometric loss of Eq. 13 over a batch of rays, as a mean over rays of
+ * the squared RGB error: loss[0] += sum_r sum_c (rgb - target)^2 / n_rays,
+ * grad_rgb = 2 (rgb - target) / n_rays.
+ *   rgb      device [n_rays][3]; images device [n_images][height][width][3];
+ *   image_idx, py, px device [n_rays] int32 (clamped into range);
+ *   grad_rgb device [n_rays][3]; loss device [1] (accumulated, caller zeroes). */
+fpo_status fpo_l2_loss(const float* rgb, const float* images, int32_t n_images, int32_t width,
+                       int32_t height, const int32_t* image_idx, const int32_t* py, const int32_t* px,
+                       int64_t n_rays, float* grad_rgb, float* loss, void* stream);
+
+/* One Adam step (Kingma and Ba 2015; the paper names no optimiser) over n
+ * floats, n a multiple of 4, all four buffers 16-byte aligned:
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *   p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps);
+ * then g = 0.  step counts from 1. */
+fpo_status fpo_adam_step(float* params, float* grad, float* m, float* v, int64_t n, float lr,
+                         float beta1, float beta2, float eps, int32_t step, void* stream);
+
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* fpo_last_error(void);
 

@@ -83,6 +83,11 @@ _SIGS = {
     "fpo_render_rays": [ctypes.POINTER(TreeView), _P, _P, _P, _P, _I32, _I64,
                         ctypes.POINTER(RenderOpts), _P, _P, _P],
     "fpo_trace_rays": [ctypes.POINTER(TreeView), _P, _P, _I64, _I32, _P, _P, _P, _P],
+    "fpo_render_backward": [ctypes.POINTER(TreeView), _P, _P, _P, _P, _I32, _I64,
+                            ctypes.POINTER(RenderOpts), _P, _P, _P, _P],
+    "fpo_l2_loss": [_P, _P, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _P, _P],
+    "fpo_adam_step": [_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float, _I32, _P],
 }
 
 
@@ -303,3 +308,34 @@ def trace_rays(tree: DeviceTree, o, d, max_visits: int):
     _check(lib().fpo_trace_rays(ctypes.byref(tv), _t_ptr(o), _t_ptr(d), n, int(max_visits), _t_ptr(ids),
                                 _t_ptr(t01), _t_ptr(nv), _stream()))
     return ids, t01, nv
+
+
+def render_backward(tree: DeviceTree, o, d, t_idx, basis, rgb_fwd, grad_rgb, grad_planes,
+                    opts: Optional[RenderOpts] = None):
+    """fpo_render_backward: adds dL/dk into grad_planes (F32 packed planes)."""
+    opts = opts or make_opts()
+    tv = tree.view()
+    _check(lib().fpo_render_backward(ctypes.byref(tv), _t_ptr(o), _t_ptr(d), _t_ptr(t_idx), _t_ptr(basis),
+                                     int(basis.shape[0]), int(o.shape[0]), ctypes.byref(opts), _t_ptr(rgb_fwd),
+                                     _t_ptr(grad_rgb), _t_ptr(grad_planes), _stream()))
+    return grad_planes
+
+
+def l2_loss(rgb, images, image_idx, py, px, grad_rgb=None, loss=None):
+    """fpo_l2_loss -> (grad_rgb [n][3], loss [1])."""
+    import torch
+    n = int(rgb.shape[0])
+    if grad_rgb is None:
+        grad_rgb = torch.empty_like(rgb)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=rgb.device)
+    _check(lib().fpo_l2_loss(_t_ptr(rgb), _t_ptr(images), int(images.shape[0]), int(images.shape[2]),
+                             int(images.shape[1]), _t_ptr(image_idx), _t_ptr(py), _t_ptr(px), n,
+                             _t_ptr(grad_rgb), _t_ptr(loss), _stream()))
+    return grad_rgb, loss
+
+
+def adam_step(params, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    _check(lib().fpo_adam_step(_t_ptr(params), _t_ptr(grad), _t_ptr(m), _t_ptr(v), int(params.numel()),
+                               float(lr), float(beta1), float(beta2), float(eps), int(step), _stream()))

@@ -1,0 +1,57 @@
+"""torch.autograd glue for direct fine-tuning of the leaf coefficients (Sec. 4.3).
+
+The forward and backward passes are libfpo calls (fpo_render_rays and
+fpo_render_backward); the optimiser step is fpo_adam_step.  Nothing here
+computes on tensors itself.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+
+class FPORender(torch.autograd.Function):
+    """rgb = render(planes) for given rays; planes are the F32 packed planes
+    of `tree` (passed explicitly so that autograd tracks them)."""
+
+    @staticmethod
+    def forward(ctx, planes, tree: _lib.DeviceTree, o, d, t_idx, basis, opts: _lib.RenderOpts):
+        if planes.data_ptr() != tree.planes.data_ptr():
+            raise ValueError("planes must be the tree's coefficient store")
+        rgb, _ = _lib.render_rays(tree, o, d, t_idx, basis, opts)
+        ctx.save_for_backward(o, d, t_idx, basis, rgb)
+        ctx.tree = tree
+        ctx.opts = opts
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        o, d, t_idx, basis, rgb = ctx.saved_tensors
+        grad = torch.zeros_like(ctx.tree.planes)
+        _lib.render_backward(ctx.tree, o, d, t_idx, basis, rgb, grad_rgb.contiguous(), grad, ctx.opts)
+        return grad, None, None, None, None, None, None
+
+
+def render(tree: _lib.DeviceTree, o, d, t_idx, basis, opts: Optional[_lib.RenderOpts] = None):
+    return FPORender.apply(tree.planes, tree, o, d, t_idx, basis, opts or _lib.make_opts())
+
+
+class Adam:
+    """Adam over a flat float tensor (the coefficient planes), one fused
+    fpo_adam_step per step; the gradient buffer is cleared by the step."""
+
+    def __init__(self, params: torch.Tensor, lr: float = 1e-2, betas=(0.9, 0.999), eps: float = 1e-8):
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.lr = float(lr)
+        self.betas = (float(betas[0]), float(betas[1]))
+        self.eps = float(eps)
+        self.t = 0
+
+    def step(self, grad: torch.Tensor):
+        self.t += 1
+        _lib.adam_step(self.params, grad, self.m, self.v, self.t, self.lr, self.betas[0], self.betas[1], self.eps)

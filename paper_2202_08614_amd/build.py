@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfpo.so")
 SOURCES = [
     "fpo_host.cpp",
     "fpo_render.hip",
+    "fpo_train.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

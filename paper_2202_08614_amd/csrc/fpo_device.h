@@ -30,6 +30,21 @@ struct TreeDev {
     float sigma_scale;
 };
 
+// Host helper: the kernel-side view of a validated fpo_tree_view.
+inline TreeDev tree_dev(const fpo_tree_view* t)
+{
+    TreeDev d;
+    d.children = t->children;
+    d.planes = static_cast<const uint4*>(t->coeffs);
+    d.scale = t->leaf_scale;
+    d.stride = t->leaf_stride;
+    d.n_nodes = (int32_t)t->n_nodes;
+    d.n_leaves = (int32_t)t->n_leaves;
+    d.max_depth = t->max_depth;
+    d.sigma_scale = t->layout.sigma_scale;
+    return d;
+}
+
 // --------------------------------------------------------------------------
 // Coefficient words.  W coefficients per 16-byte word.
 // --------------------------------------------------------------------------

@@ -1,5 +1,7 @@
 // Host side of libfpo: error reporting, octree construction, the FP64 time
 // basis and camera packing.  No device work happens here.
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -22,11 +24,18 @@ fpo_status fail(fpo_status st, const std::string& msg)
 
 fpo_status ok() { return FPO_OK; }
 
+fpo_status launch_status(const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FPO_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return FPO_OK;
+}
+
 fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs)
 {
     if (!tree) return fail(FPO_E_INVALID, "tree is NULL");
     if (!tree->children) return fail(FPO_E_INVALID, "tree->children is NULL");
-    if (tree->n_nodes < 1 || tree->n_nodes > INT32_MAX)
+    if (tree->n_nodes < 1 || tree->n_nodes > INT32_MAX / 8)
         return fail(FPO_E_INVALID, "tree->n_nodes out of range");
     if (tree->max_depth < 1 || tree->max_depth > FPO_MAX_DEPTH)
         return fail(FPO_E_INVALID, "tree->max_depth must be in 1..10");

@@ -30,4 +30,7 @@ fpo_status camera_frame(const fpo_camera& cam, float out[12]);
 // FP64 basis of Eq. 8 rounded to FP32 (FPO_BASIS_STRIDE values, zero padded).
 void basis_row(double t, double period, int n, float* out);
 
+// FPO_E_DEVICE with the HIP error string if the last launch failed, else FPO_OK.
+fpo_status launch_status(const char* what);
+
 }  // namespace fpo

@@ -233,26 +233,7 @@ __global__ __launch_bounds__(kBlock) void pack_coeffs_kernel(const float* src, c
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
-static dev::TreeDev tree_dev(const fpo_tree_view* t)
-{
-    dev::TreeDev d;
-    d.children = t->children;
-    d.planes = static_cast<const uint4*>(t->coeffs);
-    d.scale = t->leaf_scale;
-    d.stride = t->leaf_stride;
-    d.n_nodes = (int32_t)t->n_nodes;
-    d.n_leaves = (int32_t)t->n_leaves;
-    d.max_depth = t->max_depth;
-    d.sigma_scale = t->layout.sigma_scale;
-    return d;
-}
-
-static fpo_status launch_status(const char* what)
-{
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(FPO_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-    return FPO_OK;
-}
+using dev::tree_dev;
 
 static int mode_of(const fpo_tree_view* t, const fpo_render_opts* o)
 {

@@ -1,0 +1,270 @@
+// libfpo fine-tuning entry points (Sec. 4.3): the backward pass of the
+// render into the leaf Fourier coefficients, the L2 photometric loss of
+// Eq. 13 and a fused Adam update over the coefficient planes.
+//
+// Backward: per ray, the forward walk is recomputed (no per-sample state is
+// stored); the only forward state used is the ray's final colour.  Walking
+// front to back with transmittance T_i and accumulated colour A_i, the
+// suffix R_i = C - A_i gives
+//     dL/dsigma_i = delta_i * sum_c g_c (T_{i+1} c_{i,c} - R_{i,c}),
+//     dL/dh_{i,c} = g_c T_i alpha_i c_{i,c} (1 - c_{i,c}),
+// and through Eq. 7 / Eq. 9 and the SH basis of Eq. 1
+//     dL/dk^sigma_q     = s [sigma_raw > 0] dL/dsigma_i b_q,
+//     dL/dk^z_{c,j,i}   = dL/dh_{i,c} Y_j b_i.
+// The 166 coefficient gradients of each sample are scattered with FP32
+// atomics into planes laid out like the F32 coefficient store.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "fpo.h"
+#include "fpo_device.h"
+#include "fpo_internal.h"
+
+namespace fpo {
+namespace dev {
+
+struct BackwardVisitor {
+    const TreeDev& T;
+    const float* b;
+    float* grad;          // F32 packed planes: word (g, leaf) holds 4 floats
+    float Y[9];
+    float Tr;
+    float acc[3];         // accumulated colour sum_{j<=i} T_j alpha_j c_j
+    float Cf[3];          // final colour of the forward pass (incl. T_N bg)
+    float g[3];           // dL/dC
+    float stop_T;
+    float sigma_scale;
+
+    __device__ inline void add(int q, int leaf, float v)
+    {
+        float* p = grad + ((int64_t)(q >> 2) * T.stride + leaf) * 4 + (q & 3);
+        unsafeAtomicAdd(p, v);
+    }
+
+    __device__ inline bool segment(int leaf, float t0, float t1)
+    {
+        using E = LeafEval<FPO_F32>;
+        const float delta = t1 - t0;
+        float k[E::kSigmaWords * 4];
+        float scale;
+        const float sraw = E::sigma(T, leaf, b, k, scale);
+        const float sig = sigma_scale * fmaxf(sraw, 0.0f);
+        if (!(sig * delta > 0.0f)) return false;
+        float h[3];
+        E::colour(T, leaf, b, Y, k, scale, h);
+        const float e = __expf(-sig * delta);
+        const float alpha = 1.0f - e;
+        const float w = Tr * alpha;
+        const float T_next = Tr * e;
+        float dsig = 0.0f;
+        float dh[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float col = sigmoidf_(h[c]);
+            acc[c] = fmaf(w, col, acc[c]);
+            const float R = Cf[c] - acc[c];
+            dsig = fmaf(g[c], T_next * col - R, dsig);
+            dh[c] = g[c] * w * col * (1.0f - col);
+        }
+        dsig *= delta * sigma_scale;      // d/dsigma_raw (sigma_raw > 0 here)
+#pragma unroll
+        for (int q = 0; q < FPO_N_SIGMA; ++q) add(q, leaf, dsig * b[q]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < FPO_N_SH; ++j) {
+                const float dz = dh[c] * Y[j];
+#pragma unroll
+                for (int i = 0; i < FPO_N_SH_FOURIER; ++i)
+                    add(FPO_N_SIGMA + (c * FPO_N_SH + j) * FPO_N_SH_FOURIER + i, leaf, dz * b[i]);
+            }
+        Tr = T_next;
+        return Tr < stop_T;
+    }
+};
+
+struct BackwardLaunch {
+    TreeDev tree;
+    const float* o;
+    const float* d;
+    const int32_t* t_idx;
+    const float* basis;
+    int64_t n;
+    int32_t n_t;
+    const float* rgb_fwd;
+    const float* grad_rgb;
+    float* grad;
+    float stop_T;
+};
+
+__global__ __launch_bounds__(kBlock) void render_backward_kernel(BackwardLaunch a)
+{
+    __shared__ int s_stack[kStackLevels * kBlock];
+    const int64_t r_id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r_id >= a.n) return;
+    int ti = min(max(a.t_idx[r_id], 0), a.n_t - 1);
+    float b[FPO_BASIS_STRIDE];
+    const float4* brow = reinterpret_cast<const float4*>(a.basis + (int64_t)ti * FPO_BASIS_STRIDE);
+#pragma unroll
+    for (int i = 0; i < FPO_BASIS_STRIDE / 4; ++i) {
+        const float4 v = brow[i];
+        b[4 * i] = v.x; b[4 * i + 1] = v.y; b[4 * i + 2] = v.z; b[4 * i + 3] = v.w;
+    }
+    BackwardVisitor vis{a.tree, b, a.grad};
+    vis.Tr = 1.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        vis.acc[c] = 0.0f;
+        vis.Cf[c] = a.rgb_fwd[r_id * 3 + c];
+        vis.g[c] = a.grad_rgb[r_id * 3 + c];
+    }
+    vis.stop_T = a.stop_T;
+    vis.sigma_scale = a.tree.sigma_scale;
+    if (vis.g[0] == 0.0f && vis.g[1] == 0.0f && vis.g[2] == 0.0f) return;
+    Ray r;
+    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+                  a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
+        sh9(r.d[0], r.d[1], r.d[2], vis.Y);
+        walk(a.tree, r, s_stack + threadIdx.x, vis);
+    }
+}
+
+// Mean over rays of the squared RGB error against target pixels, and its
+// gradient: loss += sum_c (rgb - target)^2 / n, grad = 2 (rgb - target) / n.
+__global__ __launch_bounds__(kBlock) void l2_loss_kernel(const float* rgb, const float* images,
+                                                         const int32_t* img, const int32_t* py,
+                                                         const int32_t* px, int64_t n, int32_t n_img,
+                                                         int32_t W, int32_t H, float* grad, float* loss)
+{
+    __shared__ float s_part[kBlock / kWave];
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    float part = 0.0f;
+    if (r < n) {
+        const int ii = min(max(img[r], 0), n_img - 1);
+        const int yy = min(max(py[r], 0), H - 1);
+        const int xx = min(max(px[r], 0), W - 1);
+        const float* tgt = images + (((int64_t)ii * H + yy) * W + xx) * 3;
+        const float inv_n = 1.0f / (float)n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float e = rgb[r * 3 + c] - tgt[c];
+            part = fmaf(e, e, part);
+            grad[r * 3 + c] = 2.0f * e * inv_n;
+        }
+        part *= inv_n;
+    }
+    // wave reduction, then one atomic per block
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_part[threadIdx.x / kWave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) s += s_part[w];
+        unsafeAtomicAdd(loss, s);
+    }
+}
+
+// Adam (Kingma and Ba 2015) over n floats; the gradient is cleared after use.
+// c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
+__global__ __launch_bounds__(kBlock) void adam_kernel(float4* p, float4* g, float4* m, float4* v, int64_t n4,
+                                                      float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n4) return;
+    float4 pp = p[i], gg = g[i], mm = m[i], vv = v[i];
+    float* P = &pp.x;
+    float* G = &gg.x;
+    float* M = &mm.x;
+    float* V = &vv.x;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        M[e] = fmaf(b1, M[e], (1.0f - b1) * G[e]);
+        V[e] = fmaf(b2, V[e], (1.0f - b2) * G[e] * G[e]);
+        const float mh = M[e] * c1;
+        const float vh = V[e] * c2;
+        P[e] -= lr * mh / (sqrtf(vh) + eps);
+    }
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
+    g[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+}  // namespace dev
+
+}  // namespace fpo
+
+using namespace fpo;
+
+extern "C" fpo_status fpo_render_backward(const fpo_tree_view* tree, const float* o, const float* d,
+                                          const int32_t* t_idx, const float* basis, int32_t n_t, int64_t n_rays,
+                                          const fpo_render_opts* opts, const float* rgb_fwd,
+                                          const float* grad_rgb, float* grad_coeffs, void* stream)
+{
+    fpo_status st = check_tree(tree, true);
+    if (st != FPO_OK) return st;
+    if ((st = check_opts(opts, tree)) != FPO_OK) return st;
+    if (opts->snapshot) return fail(FPO_E_UNSUPPORTED, "backward runs in Fourier mode only");
+    if (tree->dtype != FPO_F32) return fail(FPO_E_UNSUPPORTED, "backward needs the F32 coefficient store");
+    if (n_rays < 0) return fail(FPO_E_INVALID, "n_rays < 0");
+    if (n_rays == 0) return FPO_OK;
+    if (!o || !d || !t_idx || !basis || !rgb_fwd || !grad_rgb || !grad_coeffs)
+        return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
+    if (n_rays > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rays");
+    dev::BackwardLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.tree = dev::tree_dev(tree);
+    a.o = o; a.d = d; a.t_idx = t_idx; a.basis = basis; a.n = n_rays; a.n_t = n_t;
+    a.rgb_fwd = rgb_fwd; a.grad_rgb = grad_rgb; a.grad = grad_coeffs;
+    a.stop_T = opts->stop_T;
+    const int64_t grid = (n_rays + dev::kBlock - 1) / dev::kBlock;
+    hipLaunchKernelGGL(dev::render_backward_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,
+                       static_cast<hipStream_t>(stream), a);
+    return launch_status("fpo_render_backward");
+}
+
+extern "C" fpo_status fpo_l2_loss(const float* rgb, const float* images, int32_t n_images, int32_t width,
+                                  int32_t height, const int32_t* image_idx, const int32_t* py, const int32_t* px,
+                                  int64_t n_rays, float* grad_rgb, float* loss, void* stream)
+{
+    if (n_rays < 0) return fail(FPO_E_INVALID, "n_rays < 0");
+    if (n_rays == 0) return FPO_OK;
+    if (!rgb || !images || !image_idx || !py || !px || !grad_rgb || !loss)
+        return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_images < 1 || width < 1 || height < 1) return fail(FPO_E_INVALID, "bad image shape");
+    if (n_rays > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rays");
+    const int64_t grid = (n_rays + dev::kBlock - 1) / dev::kBlock;
+    hipLaunchKernelGGL(dev::l2_loss_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,
+                       static_cast<hipStream_t>(stream), rgb, images, image_idx, py, px, n_rays, n_images, width,
+                       height, grad_rgb, loss);
+    return launch_status("fpo_l2_loss");
+}
+
+extern "C" fpo_status fpo_adam_step(float* params, float* grad, float* m, float* v, int64_t n, float lr,
+                                    float beta1, float beta2, float eps, int32_t step, void* stream)
+{
+    if (!params || !grad || !m || !v) return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n < 0 || n % 4 != 0) return fail(FPO_E_INVALID, "n must be a non-negative multiple of 4");
+    if (step < 1) return fail(FPO_E_INVALID, "step counts from 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(FPO_E_INVALID, "betas must be in [0, 1)");
+    if (!(lr >= 0.0f) || !(eps > 0.0f)) return fail(FPO_E_INVALID, "lr must be >= 0 and eps > 0");
+    if ((((uintptr_t)params) | ((uintptr_t)grad) | ((uintptr_t)m) | ((uintptr_t)v)) & 15)
+        return fail(FPO_E_INVALID, "buffers must be 16-byte aligned");
+    if (n == 0) return FPO_OK;
+    const double c1 = 1.0 / (1.0 - std::pow((double)beta1, (double)step));
+    const double c2 = 1.0 / (1.0 - std::pow((double)beta2, (double)step));
+    const int64_t n4 = n / 4;
+    if (n4 > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many parameters");
+    const int64_t grid = (n4 + dev::kBlock - 1) / dev::kBlock;
+    hipLaunchKernelGGL(dev::adam_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0, static_cast<hipStream_t>(stream),
+                       reinterpret_cast<float4*>(params), reinterpret_cast<float4*>(grad), reinterpret_cast<float4*>(m),
+                       reinterpret_cast<float4*>(v), n4, lr, beta1, beta2, eps, (float)c1, (float)c2);
+    return launch_status("fpo_adam_step");
+}

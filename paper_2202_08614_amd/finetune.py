@@ -1,0 +1,80 @@
+"""Direct fine-tuning of a Fourier PlenOctree on posed images (Sec. 4.3).
+
+One step: draw a batch of (image, row, column) samples, generate their rays
+(fpo_camera_rays), render them (fpo_render_rays), take the L2 photometric
+loss of Eq. 13 against the images (fpo_l2_loss), back-propagate into the
+leaf coefficients (fpo_render_backward) and apply Adam (fpo_adam_step).
+Each image carries its own camera and time.
+"""
+from __future__ import annotations
+
+from typing import List, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+class FineTuner:
+    def __init__(self, tree: _lib.DeviceTree, images: torch.Tensor, cams: Sequence, stop_T: float = 1e-3,
+                 lr: float = 1e-2, batch: int = 8192, seed: int = 2022):
+        dev = tree.children.device
+        self.tree = tree
+        self.images = images
+        self.n_img, self.H, self.W = int(images.shape[0]), int(images.shape[1]), int(images.shape[2])
+        self.cam_table = torch.from_numpy(_lib.camera_pack(cams)).to(dev)
+        times = sorted({float(c.time) for c in cams})
+        self.basis = torch.from_numpy(_lib.time_basis(times, tree.layout)).to(dev)
+        self.img_t = torch.tensor([times.index(float(c.time)) for c in cams], dtype=torch.int32, device=dev)
+        self.opts = _lib.make_opts(stop_T=stop_T)
+        self.batch = int(batch)
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(seed)
+        self.grad = torch.zeros_like(tree.planes)
+        self.m = torch.zeros_like(tree.planes)
+        self.v = torch.zeros_like(tree.planes)
+        self.lr = float(lr)
+        self.t = 0
+        n = self.batch
+        self.o = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        self.d = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        self.rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        self.grad_rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
+
+    @classmethod
+    def from_scene(cls, leaf_dijk: np.ndarray, gt_coeffs: np.ndarray, init_coeffs: np.ndarray, max_depth: int,
+                   cams: Sequence, dev, sigma_scale: float = 64.0, stop_T: float = 1e-3, lr: float = 1e-2,
+                   batch: int = 8192, seed: int = 2022) -> "FineTuner":
+        """Targets are rendered from the ground-truth coefficients by fpo_render."""
+        gt = _lib.DeviceTree.from_leaves(leaf_dijk, gt_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
+        images, _ = _lib.render(gt, cams, _lib.make_opts(stop_T=stop_T))
+        del gt
+        tree = _lib.DeviceTree.from_leaves(leaf_dijk, init_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
+        return cls(tree, images, cams, stop_T=stop_T, lr=lr, batch=batch, seed=seed)
+
+    def sample(self):
+        dev = self.images.device
+        n = self.batch
+        img = torch.randint(0, self.n_img, (n,), generator=self.gen, device=dev, dtype=torch.int32)
+        py = torch.randint(0, self.H, (n,), generator=self.gen, device=dev, dtype=torch.int32)
+        px = torch.randint(0, self.W, (n,), generator=self.gen, device=dev, dtype=torch.int32)
+        return img, py, px
+
+    def step(self, img, py, px, loss_out: torch.Tensor, with_adam: bool = True):
+        t_idx = self.img_t[img.long()]
+        _lib.camera_rays(self.cam_table, img, py, px, self.o, self.d)
+        _lib.render_rays(self.tree, self.o, self.d, t_idx, self.basis, self.opts, rgb=self.rgb)
+        _lib.l2_loss(self.rgb, self.images, img, py, px, grad_rgb=self.grad_rgb, loss=loss_out)
+        _lib.render_backward(self.tree, self.o, self.d, t_idx, self.basis, self.rgb, self.grad_rgb, self.grad,
+                             self.opts)
+        if with_adam:
+            self.t += 1
+            _lib.adam_step(self.tree.planes, self.grad, self.m, self.v, self.t, lr=self.lr)
+
+    def train(self, n_steps: int) -> List[float]:
+        losses = torch.zeros(n_steps, dtype=torch.float32, device=self.images.device)
+        for s in range(n_steps):
+            img, py, px = self.sample()
+            self.step(img, py, px, losses[s:s + 1])
+        return losses.cpu().tolist()
