@@ -44,6 +44,47 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def finetune_leg(dev, steps: int = 40, warmup: int = 5):
+    """Fine-tune throughput on the 500k-leaf depth-8 scene: 8192-ray batches
+    drawn uniformly over 24 cameras x 30 times at 800x800, L2 loss, Adam."""
+    import torch
+    from paper_2202_08614_amd import synth
+    from paper_2202_08614_amd.finetune import FineTuner
+    t0 = time.time()
+    dijk = synth.blob_leaves(8, 500_000)
+    gt = synth.gaussian_coeffs(len(dijk))
+    init = synth.perturb_coeffs(gt, 0.05, seed=synth.COEFF_SEED + 1)
+    cams = synth.c4_cameras()
+    ft = FineTuner.from_scene(dijk, gt, init, 8, cams, dev, stop_T=1e-3, lr=1e-2, batch=8192,
+                              seed=synth.RAY_SEED)
+    torch.cuda.synchronize()
+    log(f"fine-tune scene: {len(dijk)} leaves, {len(cams)} target images, ready in {time.time() - t0:.1f}s")
+    loss = torch.zeros(1, device=dev)
+    batches = [ft.sample() for _ in range(steps + warmup)]
+    res = {}
+    for with_adam in (True, False):
+        for b in batches[:warmup]:
+            ft.step(*b, loss, with_adam=with_adam)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for b in batches[warmup:]:
+            ft.step(*b, loss, with_adam=with_adam)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res["rays_per_s_with_adam" if with_adam else "rays_per_s_fwd_bwd"] = round(8192 / (ms * 1e-3), 1)
+        res["ms_per_step_with_adam" if with_adam else "ms_per_step_fwd_bwd"] = round(ms, 4)
+    res["batch"] = 8192
+    res["params"] = int(ft.tree.planes.numel())
+    res["workload"] = ("depth-8 union octree, 500k leaves x 166 FP32 coeffs; 8192-ray batches over 24 cameras x "
+                       "30 times at 800x800; L2 loss; dense Adam over all coefficient planes")
+    log(f"fine-tune: {res}")
+    del ft
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +92,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=300000, help="rays rendered by the oracle for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-finetune", action="store_true")
+    ap.add_argument("--ft-steps", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -159,6 +202,9 @@ def main():
         f"({int(ill.sum())} ill-conditioned rays, max err {err.max():.2e}); "
         f"segments/ray {seg.mean():.2f} (opaque {opq.mean():.2f})")
 
+    ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
+    del frames
+
     out = {
         "metric": METRIC,
         "value": round(mrays, 2),
@@ -205,6 +251,7 @@ def main():
             "kind": "oracle",
             "sample": f"{m} rays drawn uniformly from the step's 160 frames, FP64 C oracle",
         },
+        "finetune": ft,
         "paper_context": "100 fps at 800x800 (64 Mrays/s) on one RTX 3090, the paper's own scenes",
     }
     print(json.dumps(out), flush=True)

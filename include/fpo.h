@@ -234,6 +234,35 @@ fpo_status fpo_l2_loss(const float* rgb, const float* images, int32_t n_images, 
 fpo_status fpo_adam_step(float* params, float* grad, float* m, float* v, int64_t n, float lr,
                          float beta1, float beta2, float eps, int32_t step, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Precision and time bake                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Quantise an F32 coefficient store (the paper states no precision; this is
+ * the storage reading of this library).  Per leaf: scale = max |k| over its 166
+ * coefficients for FPO_BF16, max |k| / 448 for FPO_FP8_E4M3 (OCP E4M3FN),
+ * 1 for an all-zero leaf; code = round-to-nearest-even(k / scale) with the
+ * quotient formed in FP32 (IEEE division), FP8 saturating at +-448.
+ *   coeffs    device F32 packed planes (42 planes x leaf_stride words).
+ *   q_out     device packed planes of `dtype` (21 or 11 planes x leaf_stride
+ *             words); slots q >= 166 and leaves >= n_leaves are zero.
+ *   scale_out device [leaf_stride] F32 (1 for leaves >= n_leaves). */
+fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride, fpo_dtype dtype,
+                        void* q_out, float* scale_out, void* stream);
+
+/* Evaluate Eq. 7 and Eq. 9 at n_t times for every leaf (a time bake), with
+ * matrix-core (MFMA) contractions: [times x K] x [K x leaves].
+ *   basis   device [n_t][FPO_BASIS_STRIDE] F32 (fpo_time_basis).
+ *   out     device [n_t][28][leaf_stride] of out_dtype (F32 or BF16, RNE):
+ *           row 0 = sigma(t) before activation, row 1 + c*9 + j = z_{c,j}(t),
+ *           multiplied by the leaf scale for quantised stores; leaves >= n_leaves
+ *           are not written.
+ * Accuracy: operands are split into BF16 hi + lo parts and three partial
+ * products are accumulated in FP32, so each term k_i b_i carries a relative
+ * error below 2^-15 before the FP32 sum (plus BF16 output rounding). */
+fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t, fpo_dtype out_dtype,
+                          void* out, void* stream);
+
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* fpo_last_error(void);
 

@@ -88,6 +88,8 @@ _SIGS = {
     "fpo_l2_loss": [_P, _P, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _P, _P],
     "fpo_adam_step": [_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, _I32, _P],
+    "fpo_quantize": [_P, _I64, _I64, ctypes.c_int, _P, _P, _P],
+    "fpo_bake_times": [ctypes.POINTER(TreeView), _P, _I32, ctypes.c_int, _P, _P],
 }
 
 
@@ -339,3 +341,28 @@ def adam_step(params, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.
               eps: float = 1e-8):
     _check(lib().fpo_adam_step(_t_ptr(params), _t_ptr(grad), _t_ptr(m), _t_ptr(v), int(params.numel()),
                                float(lr), float(beta1), float(beta2), float(eps), int(step), _stream()))
+
+
+def quantize(tree: DeviceTree, dtype: int) -> DeviceTree:
+    """fpo_quantize: a BF16 / FP8 copy of an F32 tree (same structure)."""
+    import torch
+    if tree.dtype != FPO_F32:
+        raise ValueError("quantize needs an F32 tree")
+    dev = tree.planes.device
+    q = torch.zeros((n_planes(dtype), tree.leaf_stride, 4), dtype=torch.int32, device=dev)
+    scale = torch.empty((tree.leaf_stride,), dtype=torch.float32, device=dev)
+    _check(lib().fpo_quantize(_t_ptr(tree.planes), tree.n_leaves, tree.leaf_stride, int(dtype), _t_ptr(q),
+                              _t_ptr(scale), _stream()))
+    return tree.with_store(q, scale, dtype)
+
+
+def bake_times(tree: DeviceTree, basis, out_dtype: int = FPO_F32, out=None):
+    """fpo_bake_times -> out [n_t][28][leaf_stride] (float32 or bfloat16 tensor)."""
+    import torch
+    n_t = int(basis.shape[0])
+    if out is None:
+        dt = torch.float32 if out_dtype == FPO_F32 else torch.bfloat16
+        out = torch.empty((n_t, N_BAKED, tree.leaf_stride), dtype=dt, device=basis.device)
+    tv = tree.view()
+    _check(lib().fpo_bake_times(ctypes.byref(tv), _t_ptr(basis), n_t, int(out_dtype), _t_ptr(out), _stream()))
+    return out

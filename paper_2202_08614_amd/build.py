@@ -20,6 +20,7 @@ SOURCES = [
     "fpo_host.cpp",
     "fpo_render.hip",
     "fpo_train.hip",
+    "fpo_bake.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,169 @@
+"""GPU parity of the precision path: per-leaf-scaled BF16 / FP8 quantisation
+(bit-exact codes and scales against the reference codec), renders from the
+quantised stores, the MFMA time bake, and snapshot-mode renders."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import codec
+from paper_2202_08614_amd import _lib, synth
+from tests.gpu_util import check_parity, conditioned_reference, note, psnr, require_gpu, straddle_err
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def _codes_from_planes(q: np.ndarray, dtype: int, perm: np.ndarray, n: int) -> np.ndarray:
+    """Packed int32 planes [G][stride][4] -> per-leaf codes [L][166] caller order."""
+    raw = np.ascontiguousarray(q).view(np.uint8)                  # [G][stride][16]
+    per = raw.transpose(1, 0, 2).reshape(raw.shape[1], -1)        # [stride][G*16] bytes
+    if dtype == _lib.FPO_BF16:
+        codes = per.view(np.uint16)[:n, :166]
+    else:
+        codes = per[:n, :166]
+    out = np.zeros_like(codes)
+    out[perm] = codes
+    return out
+
+
+def _special_coeffs(n, seed):
+    """Gaussian coefficients plus leaves that exercise the codecs' edges: an
+    all-zero leaf, magnitudes across 12 binades (FP8 subnormals), exact
+    power-of-two leaves."""
+    k = synth.gaussian_coeffs(n, seed=seed)
+    k[0] = 0.0
+    k[1] = (np.linspace(-1, 1, 166) * 2.0 ** -np.arange(166) % 13).astype(np.float32)
+    k[2] = np.float32(2.0) ** -(np.arange(166) % 12).astype(np.float32)
+    k[3, 0] = 1e-30
+    return k
+
+
+@pytest.mark.parametrize("dtype,kind", [(_lib.FPO_BF16, "bf16"), (_lib.FPO_FP8_E4M3, "fp8")])
+def test_quantize_bit_exact(dev, dtype, kind):
+    import torch
+    dijk = synth.random_tree_leaves(8, 6, p_split=0.6)
+    k = _special_coeffs(len(dijk), 8)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=len(dijk) + 5)
+    note(f"fpo_quantize {kind}")
+    qt = _lib.quantize(tree, dtype)
+    torch.cuda.synchronize()
+    want_codes, want_scale = codec.quantize(k, kind)
+    got_scale = np.zeros(len(dijk), np.float32)
+    got_scale[tree.perm] = qt.scale.cpu().numpy()[:len(dijk)]
+    assert np.array_equal(got_scale.view(np.uint32), want_scale.view(np.uint32))
+    got = _codes_from_planes(qt.planes.cpu().numpy(), dtype, tree.perm, len(dijk))
+    assert np.array_equal(got, want_codes), np.argwhere(got != want_codes)[:5]
+    assert np.all(qt.scale.cpu().numpy()[len(dijk):] == 1.0)
+
+
+@pytest.mark.parametrize("dtype,kind,min_db", [(_lib.FPO_BF16, "bf16", 50.0), (_lib.FPO_FP8_E4M3, "fp8", 25.0)])
+def test_quantised_render_c1(oracle_lib, dev, dtype, kind, min_db):
+    """Kernel error: GPU render of the quantised store against the oracle on
+    the dequantised coefficients (1e-4).  Total error: PSNR against the
+    oracle on the original FP32 coefficients."""
+    import torch
+    sc = synth.c1_scene()
+    cam = sc.cameras[0]
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, 6, device=dev)
+    qt = _lib.quantize(tree, dtype)
+    note(f"c1 render {kind}")
+    rgb, _ = _lib.render(qt, [cam], _lib.make_opts())
+    torch.cuda.synchronize()
+    got = rgb.cpu().numpy().reshape(-1, 3)
+    codes, scale = codec.quantize(sc.coeffs, kind)
+    deq = codec.dequantize(codes, scale, kind)
+    o, d = oracle_lib.camera_rays(cam)
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
+    z = np.zeros(len(o), np.int32)
+    ref = conditioned_reference(oracle_lib, ot, deq, oracle_lib.make_params(), [cam.time], o, d, z)
+    check_parity(got, ref, TOL)
+    full = oracle_lib.render_rays(ot, sc.coeffs, oracle_lib.make_params(), [cam.time], o, d, z)["rgb"][:, 0]
+    db = psnr(got, full)
+    print(f"[{kind}] PSNR vs FP64 oracle on FP32 coefficients: {db:.2f} dB")
+    assert db >= min_db
+
+
+@pytest.mark.parametrize("store", [_lib.FPO_F32, _lib.FPO_BF16, _lib.FPO_FP8_E4M3])
+def test_bake_matches_oracle(oracle_lib, dev, store):
+    import torch
+    dijk = synth.random_tree_leaves(9, 6, p_split=0.6)
+    k = synth.gaussian_coeffs(len(dijk), seed=9)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=len(dijk) + 3)
+    kind = {_lib.FPO_BF16: "bf16", _lib.FPO_FP8_E4M3: "fp8"}.get(store)
+    if kind:
+        tree = _lib.quantize(tree, store)
+        codes, scale = codec.quantize(k, kind)
+        k_eff = codec.dequantize(codes, scale, kind)
+    else:
+        k_eff = k.astype(np.float64)
+    times = [i * 60.0 / 37 + 0.3 for i in range(37)]          # ragged: 3 tiles of 16 times
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    note(f"fpo_bake_times store={store}")
+    out32 = _lib.bake_times(tree, basis, _lib.FPO_F32)
+    out16 = _lib.bake_times(tree, basis, _lib.FPO_BF16)
+    torch.cuda.synchronize()
+    p = oracle_lib.make_params()
+    want = oracle_lib.bake(k_eff, p, times)                      # [n_t][28][L]
+    # magnitude scale of each output: sum_i |k_i b_i|
+    B = np.stack([oracle_lib.basis(t, 60.0, 31) for t in times])
+    ka = np.abs(k_eff)
+    mag = np.zeros_like(want)
+    mag[:, 0] = np.abs(B) @ ka[:, :31].T
+    kz = ka[:, 31:].reshape(-1, 27, 5)
+    mag[:, 1:] = np.einsum("ti,lmi->tml", np.abs(B[:, :5]), kz)
+    g32 = out32.cpu().numpy()[:, :, :len(dijk)][:, :, np.argsort(tree.perm)]
+    g16 = out16.float().cpu().numpy()[:, :, :len(dijk)][:, :, np.argsort(tree.perm)]
+    assert np.all(np.abs(g32 - want) <= 2.0 ** -14 * mag + 1e-6)
+    assert np.all(np.abs(g16 - want) <= 2.0 ** -8 * np.abs(want) + 2.0 ** -14 * mag + 1e-6)
+
+
+def test_snapshot_render_matches_oracle(oracle_lib, dev):
+    """Snapshot mode: leaves hold the 28 values at one time (a static
+    PlenOctree); each camera reads its own snapshot."""
+    import torch
+    sc = synth.c1_scene()
+    times = [5.0, 22.2, 47.5]
+    cams = [synth.ring_camera(0.4 + k, 0.3, 1.5, 45.0, 64, 48, times[k]) for k in range(3)]
+    p = oracle_lib.make_params()
+    snap = oracle_lib.bake(sc.coeffs.astype(np.float64), p, times)      # [3][28][L] caller order
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, 6, device=dev)
+    snap_slots = np.ascontiguousarray(snap[:, :, tree.perm]).astype(np.float32)
+    snap_d = torch.from_numpy(snap_slots).to(dev)
+    note("c1 snapshot render F32")
+    opts = _lib.make_opts(snapshot=snap_d, snapshot_dtype=_lib.FPO_F32,
+                          snapshot_cam_stride=_lib.N_BAKED * tree.leaf_stride)
+    rgb, _ = _lib.render(tree, cams, opts)
+    rgb_fpo, _ = _lib.render(tree, cams, _lib.make_opts())
+    torch.cuda.synchronize()
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
+    for k in range(3):
+        o, d = oracle_lib.camera_rays(cams[k])
+        z = np.zeros(len(o), np.int32)
+        ref = conditioned_reference(oracle_lib, ot, None, p, [times[k]], o, d, z,
+                                    snapshot=snap_slots[k][:, np.argsort(tree.perm)].astype(np.float64))
+        check_parity(rgb[k].cpu().numpy().reshape(-1, 3), ref, TOL)
+    # the snapshot image and the Fourier-mode image agree to FP32 accuracy
+    assert float((rgb - rgb_fpo).abs().max()) < 2e-4
+
+
+def test_dc_only_tree_is_time_invariant_on_gpu(dev):
+    """With every k_i (i >= 1) zero the image does not depend on t, bit for bit."""
+    import torch
+    sc = synth.c1_scene()
+    k = sc.coeffs.copy()
+    k[:, 1:31] = 0.0
+    kz = k[:, 31:].reshape(-1, 27, 5)
+    kz[:, :, 1:] = 0.0
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, k, 6, device=dev)
+    cams = [synth.ring_camera(0.7, 0.2, 1.5, 45.0, 64, 64, t) for t in (0.0, 13.7, 44.1)]
+    note("dc-only time invariance")
+    rgb, _ = _lib.render(tree, cams, _lib.make_opts(stop_T=1e-3))
+    torch.cuda.synchronize()
+    assert torch.equal(rgb[0], rgb[1]) and torch.equal(rgb[0], rgb[2])
+    assert float(rgb.max()) > 0.05
