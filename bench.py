@@ -44,6 +44,80 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bake_leg(dev, sc, tree, oracle_mod, n_t: int = 64, reps: int = 5):
+    """Precision + MFMA bake on the 2M-leaf scene: quantise to BF16, bake 64
+    times with fpo_bake_times into BF16 snapshots (7.2 GB), render 64 views at
+    800x800, view k from snapshot k.  Same for FP8 (bake only)."""
+    import torch
+    from paper_2202_08614_amd import _lib, synth
+    res = {}
+    times = [k * synth.PERIOD / n_t for k in range(n_t)]
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    cams = synth.c3_cameras(800, 800, n_t)
+    stream = torch.cuda.current_stream()
+    L = tree.n_leaves
+    for name, dt in (("bf16", _lib.FPO_BF16), ("fp8", _lib.FPO_FP8_E4M3)):
+        qt = _lib.quantize(tree, dt)
+        snaps = torch.empty((n_t, tree.leaf_stride, _lib.SNAP_VALUES), dtype=torch.bfloat16, device=dev)
+        _lib.bake_times(qt, basis, _lib.FPO_BF16, out=snaps)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            _lib.bake_times(qt, basis, _lib.FPO_BF16, out=snaps)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+        data_words = {_lib.FPO_BF16: 21, _lib.FPO_FP8_E4M3: 11}[dt]      # words holding the 166 codes
+        nbytes = L * (data_words * 16 + 4) + n_t * _lib.N_BAKED * L * 2
+        flops = 2.0 * L * n_t * 166
+        r = {"bake_ms": round(ms, 4), "bake_bytes": nbytes, "bake_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+             "bake_hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+             "bake_mfma_frac": round(flops / (ms * 1e-3) / 2.5e15, 5)}
+        if name == "bf16":
+            opts = _lib.make_opts(stop_T=1e-3, snapshot=snaps, snapshot_dtype=_lib.FPO_BF16,
+                                  snapshot_cam_stride=tree.leaf_stride)
+            frames = torch.empty((n_t, 800, 800, 3), dtype=torch.float32, device=dev)
+            _lib.render(tree, cams, opts, rgb=frames)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                _lib.render(tree, cams, opts, rgb=frames)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rms = e0.elapsed_time(e1) / reps
+            r["snapshot_render_ms_64x800x800"] = round(rms, 4)
+            r["snapshot_render_Mrays_s"] = round(n_t * 800 * 800 / (rms * 1e-3) / 1e6, 1)
+            if oracle_mod is not None:
+                rng = np.random.default_rng(7)
+                m = 20000
+                ci = rng.integers(0, n_t, m)
+                py = rng.integers(0, 800, m)
+                px = rng.integers(0, 800, m)
+                got = frames[torch.from_numpy(ci).to(dev), torch.from_numpy(py).to(dev),
+                             torch.from_numpy(px).to(dev)].cpu().numpy().astype(np.float64)
+                o = np.zeros((m, 3)); d = np.zeros((m, 3))
+                for c in np.unique(ci):
+                    sel = np.nonzero(ci == c)[0]
+                    o[sel], d[sel] = oracle_mod.camera_rays(cams[c], px[sel], py[sel])
+                ot = oracle_mod.OracleTree(sc.leaf_dijk, sc.max_depth)
+                ref = oracle_mod.render_rays(ot, sc.coeffs, oracle_mod.make_params(stop_T=1e-3), times, o, d,
+                                             ci.astype(np.int32), n_threads=len(os.sched_getaffinity(0)))
+                e = np.minimum(np.abs(got - ref["rgb"][:, 0]).max(1), np.abs(got - ref["rgb"][:, 1]).max(1))
+                mse = float(np.mean(np.min([((got - ref["rgb"][:, j]) ** 2).mean(1) for j in range(2)], 0)))
+                r["psnr_vs_oracle_fp32_coeffs_db"] = round(10 * np.log10(1.0 / mse), 2) if mse > 0 else None
+                r["max_abs_err_vs_oracle_fp32_coeffs"] = float(e.max())
+            del frames
+        res[name] = r
+        del snaps, qt
+        torch.cuda.empty_cache()
+    res["workload"] = ("2.0M-leaf depth-9 scene quantised per leaf; 64 times baked into BF16 snapshots "
+                       "[64][28][L] by MFMA; 64 views 800x800, view k from snapshot k, T<1e-3")
+    log(f"bake: {res}")
+    return res
+
+
 def finetune_leg(dev, steps: int = 40, warmup: int = 5):
     """Fine-tune throughput on the 500k-leaf depth-8 scene: 8192-ray batches
     drawn uniformly over 24 cameras x 30 times at 800x800, L2 loss, Adam."""
@@ -76,9 +150,9 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5):
         res["rays_per_s_with_adam" if with_adam else "rays_per_s_fwd_bwd"] = round(8192 / (ms * 1e-3), 1)
         res["ms_per_step_with_adam" if with_adam else "ms_per_step_fwd_bwd"] = round(ms, 4)
     res["batch"] = 8192
-    res["params"] = int(ft.tree.planes.numel())
+    res["params"] = int(ft.tree.coeffs.numel())
     res["workload"] = ("depth-8 union octree, 500k leaves x 166 FP32 coeffs; 8192-ray batches over 24 cameras x "
-                       "30 times at 800x800; L2 loss; dense Adam over all coefficient planes")
+                       "30 times at 800x800; L2 loss; dense Adam over all coefficient records")
     log(f"fine-tune: {res}")
     del ft
     torch.cuda.empty_cache()
@@ -93,7 +167,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300000, help="rays rendered by the oracle for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-finetune", action="store_true")
+    ap.add_argument("--no-bake", action="store_true")
     ap.add_argument("--ft-steps", type=int, default=40)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (calibrates rocprof byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -104,6 +181,14 @@ def main():
     from paper_2202_08614_amd import _lib, synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 5 x 1 GiB")
+        return
     t0 = time.time()
     sc = synth.c2_scene()
     log(f"scene: {sc.n_leaves} leaves, generated in {time.time() - t0:.1f}s")
@@ -150,6 +235,12 @@ def main():
 
     # ---- uniform ray sample: oracle quality check, work counts, CPU baseline
     import oracle
+    if args.no_cpu:
+        log("--no-cpu: skipping the oracle sample")
+        print(json.dumps({"metric": METRIC, "value": round(mrays, 2), "unit": "Mrays/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+                          "launch_ms": round(launch_ms, 4)}), flush=True)
+        return
     rng = np.random.default_rng(2022)
     m = args.cpu_sample
     ci = rng.integers(0, len(cams), m)
@@ -202,8 +293,9 @@ def main():
         f"({int(ill.sum())} ill-conditioned rays, max err {err.max():.2e}); "
         f"segments/ray {seg.mean():.2f} (opaque {opq.mean():.2f})")
 
-    ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
     del frames
+    bake = None if args.no_bake else bake_leg(dev, sc, tree, None if args.no_cpu else oracle)
+    ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
 
     out = {
         "metric": METRIC,
@@ -251,6 +343,7 @@ def main():
             "kind": "oracle",
             "sample": f"{m} rays drawn uniformly from the step's 160 frames, FP64 C oracle",
         },
+        "bake": bake,
         "finetune": ft,
         "paper_context": "100 fps at 800x800 (64 Mrays/s) on one RTX 3090, the paper's own scenes",
     }

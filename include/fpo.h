@@ -19,12 +19,17 @@
  *   q = 31 + (c * 9 + j) * 5 + i is k^z for RGB channel c, SH index
  *   j = l*l + l + m (real SH, Condon-Shortley phase) and Fourier index i.
  * - Density: sigma_eff = sigma_scale * max(sigma(t), 0) per unit length.
- * - Coefficient store ("packed planes"): the coefficients of all leaves are
- *   held in G planes of 16-byte words; word (g, leaf) at byte offset
- *   16 * (g * leaf_stride + leaf) packs coefficients q = W g ... W g + W - 1
- *   of that leaf, W = 4 (FPO_F32), 8 (FPO_BF16) or 16 (FPO_FP8_E4M3), so
- *   G = ceil(166 / W) = 42, 21 or 11.  Slots past q = 165 hold zero.
- *   Quantised stores carry a per-leaf FP32 scale: value = scale[leaf] * code.
+ * - Coefficient store ("leaf records"): each leaf slot owns one record of R
+ *   16-byte words, R = 48 (FPO_F32), 24 (FPO_BF16) or 16 (FPO_FP8_E4M3), i.e.
+ *   768, 384 or 256 bytes; word g of slot l sits at byte offset
+ *   16 * (l * R + g) and packs coefficients q = W g ... W g + W - 1 with
+ *   W = 4, 8 or 16 per word.  Slots past q = 165 hold zero.  Records start on
+ *   128-byte boundaries, so the 31 density coefficients of a leaf share one
+ *   cache line.  Quantised stores carry a per-leaf FP32 scale:
+ *   value = scale[leaf] * code.
+ * - Snapshot records (baked values of one time): 32 values per leaf slot,
+ *   F32 (128 bytes) or BF16 (64 bytes): value 0 = sigma(t) before activation,
+ *   value 1 + c*9 + j = z_{c,j}(t), values 28..31 zero.
  * - Leaves are numbered by Morton slot (the order fpo_build_tree assigns);
  *   leaf_stride >= n_leaves.
  * - Ownership: the caller owns every buffer.  The library allocates no
@@ -80,7 +85,7 @@ typedef struct {
                                  node 0 is the root; octant = x | y << 1 | z << 2 */
     int64_t n_nodes;
     int32_t max_depth;        /* 1 .. FPO_MAX_DEPTH */
-    const void* coeffs;       /* device packed planes (see above) */
+    const void* coeffs;       /* device leaf records (see above) */
     const float* leaf_scale;  /* device [leaf_stride] for BF16 / FP8, ignored for F32 */
     fpo_dtype dtype;
     int64_t n_leaves;
@@ -106,11 +111,12 @@ typedef struct {
     float bg[3];              /* background colour added with the final transmittance */
     float stop_T;             /* early termination: stop after the segment that drives
                                  T below stop_T; 0 disables */
-    const void* snapshot;     /* NULL: Fourier mode.  Else device [28][leaf_stride] baked
-                                 values (row 0 sigma(t) before activation, row 1 + c*9 + j
-                                 the SH coefficient z_{c,j}); the camera's time is unused */
+    const void* snapshot;     /* NULL: Fourier mode.  Else device snapshot records
+                                 [leaf_stride] (see above) of one time; the camera's time
+                                 is unused */
     fpo_dtype snapshot_dtype; /* FPO_F32 or FPO_BF16 */
-    int64_t snapshot_cam_stride; /* elements between consecutive cameras' snapshots (0: shared) */
+    int64_t snapshot_cam_stride; /* leaf records between consecutive cameras' (or time
+                                    indices') snapshots; 0: all share one */
     int32_t flags;            /* reserved, 0 */
 } fpo_render_opts;
 
@@ -150,11 +156,11 @@ fpo_status fpo_camera_pack(const fpo_camera* cams, int32_t n_cams, float* table_
 /* Device calls                                                             */
 /* ---------------------------------------------------------------------- */
 
-/* Scatter caller-order coefficients into the F32 packed planes.
+/* Scatter caller-order coefficients into F32 leaf records.
  *   src  device [n_leaves][166] F32, caller order.
  *   perm device [n_leaves] int64 from fpo_build_tree.
- *   dst  device F32 packed planes with 42 planes of leaf_stride words; padding
- *        slots (q >= 166) and leaves >= n_leaves are written with zero. */
+ *   dst  device [leaf_stride][48] 16-byte words (F32 records); padding slots
+ *        (q >= 166) and slots >= n_leaves are written with zero. */
 fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
                            int64_t leaf_stride, float* dst, void* stream);
 
@@ -206,9 +212,9 @@ fpo_status fpo_trace_rays(const fpo_tree_view* tree, const float* o, const float
  *            (opts->snapshot must be NULL; the store must be FPO_F32).
  *   rgb_fwd  device [n_rays][3], the forward colours of these rays.
  *   grad_rgb device [n_rays][3], dL/d rgb.
- *   grad_coeffs device F32 packed planes shaped like the coefficient store
- *            (42 planes x leaf_stride words); gradients are ADDED (FP32 atomics,
- *            so the summation order, and the last bits, vary run to run).
+ *   grad_coeffs device F32 leaf records shaped like the coefficient store
+ *            ([leaf_stride][192] floats); gradients are ADDED (FP32 atomics, so
+ *            the summation order, and the last bits, vary run to run).
  * The early-termination decision is taken as in the forward pass and treated
  * as constant; the ReLU derivative at sigma = 0 is 0. */
 fpo_status fpo_render_backward(const fpo_tree_view* tree, const float* o, const float* d,
@@ -243,23 +249,20 @@ fpo_status fpo_adam_step(float* params, float* grad, float* m, float* v, int64_t
  * coefficients for FPO_BF16, max |k| / 448 for FPO_FP8_E4M3 (OCP E4M3FN),
  * 1 for an all-zero leaf; code = round-to-nearest-even(k / scale) with the
  * quotient formed in FP32 (IEEE division), FP8 saturating at +-448.
- *   coeffs    device F32 packed planes (42 planes x leaf_stride words).
- *   q_out     device packed planes of `dtype` (21 or 11 planes x leaf_stride
- *             words); slots q >= 166 and leaves >= n_leaves are zero.
+ *   coeffs    device F32 leaf records ([leaf_stride][48] words).
+ *   q_out     device leaf records of `dtype` ([leaf_stride][24] or [16] words);
+ *             slots q >= 166 and leaves >= n_leaves are zero.
  *   scale_out device [leaf_stride] F32 (1 for leaves >= n_leaves). */
 fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride, fpo_dtype dtype,
                         void* q_out, float* scale_out, void* stream);
 
 /* Evaluate Eq. 7 and Eq. 9 at n_t times for every leaf (a time bake), with
- * matrix-core (MFMA) contractions: [times x K] x [K x leaves].
+ * matrix-core (MFMA) contractions [times x K] x [K x leaves] in FP32.
  *   basis   device [n_t][FPO_BASIS_STRIDE] F32 (fpo_time_basis).
- *   out     device [n_t][28][leaf_stride] of out_dtype (F32 or BF16, RNE):
- *           row 0 = sigma(t) before activation, row 1 + c*9 + j = z_{c,j}(t),
- *           multiplied by the leaf scale for quantised stores; leaves >= n_leaves
- *           are not written.
- * Accuracy: operands are split into BF16 hi + lo parts and three partial
- * products are accumulated in FP32, so each term k_i b_i carries a relative
- * error below 2^-15 before the FP32 sum (plus BF16 output rounding). */
+ *   out     device [n_t][leaf_stride] snapshot records of out_dtype (F32 or
+ *           BF16, RNE), multiplied by the leaf scale for quantised stores;
+ *           slots >= n_leaves are not written.  Record t is a snapshot for
+ *           fpo_render / fpo_render_rays with snapshot_cam_stride = leaf_stride. */
 fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t, fpo_dtype out_dtype,
                           void* out, void* stream);
 

@@ -26,11 +26,12 @@ BASIS_STRIDE = 32
 CAMERA_FLOATS = 16
 MAX_DEPTH = 10
 COEFFS_PER_WORD = {FPO_F32: 4, FPO_BF16: 8, FPO_FP8_E4M3: 16}
+RECORD_WORDS = {FPO_F32: 48, FPO_BF16: 24, FPO_FP8_E4M3: 16}   # 16-byte words per leaf record
+SNAP_VALUES = 32
 
 
-def n_planes(dtype: int) -> int:
-    w = COEFFS_PER_WORD[dtype]
-    return (N_COEFF + w - 1) // w
+def record_words(dtype: int) -> int:
+    return RECORD_WORDS[dtype]
 
 
 class FpoError(RuntimeError):
@@ -196,16 +197,16 @@ def camera_pack(cams) -> np.ndarray:
 # device tree
 # ---------------------------------------------------------------------------
 class DeviceTree:
-    """A tree resident on the GPU: child table, packed coefficient planes and
-    (for quantised stores) per-leaf scales.  Coefficient planes are
-    [n_planes][leaf_stride][16 bytes]."""
+    """A tree resident on the GPU: child table, leaf records of coefficients
+    ([leaf_stride][record_words][16 bytes]) and, for quantised stores, per-leaf
+    scales."""
 
-    def __init__(self, children, n_nodes: int, max_depth: int, planes, scale, dtype: int,
+    def __init__(self, children, n_nodes: int, max_depth: int, coeffs, scale, dtype: int,
                  n_leaves: int, leaf_stride: int, perm: np.ndarray, layout: Layout):
         self.children = children
         self.n_nodes = int(n_nodes)
         self.max_depth = int(max_depth)
-        self.planes = planes
+        self.coeffs = coeffs
         self.scale = scale
         self.dtype = int(dtype)
         self.n_leaves = int(n_leaves)
@@ -223,14 +224,14 @@ class DeviceTree:
         stride = int(leaf_stride or n)
         src = torch.from_numpy(np.ascontiguousarray(coeffs, dtype=np.float32)).to(device)
         perm_d = torch.from_numpy(perm).to(device)
-        planes = torch.empty((n_planes(FPO_F32), stride, 4), dtype=torch.float32, device=device)
-        pack_coeffs(src, perm_d, n, stride, planes)
+        recs = torch.empty((stride, record_words(FPO_F32), 4), dtype=torch.float32, device=device)
+        pack_coeffs(src, perm_d, n, stride, recs)
         del src
-        return cls(torch.from_numpy(children).to(device), children.shape[0], max_depth, planes, None,
+        return cls(torch.from_numpy(children).to(device), children.shape[0], max_depth, recs, None,
                    FPO_F32, n, stride, perm, make_layout(period, sigma_scale))
 
-    def with_store(self, planes, scale, dtype: int) -> "DeviceTree":
-        return DeviceTree(self.children, self.n_nodes, self.max_depth, planes, scale, dtype,
+    def with_store(self, coeffs, scale, dtype: int) -> "DeviceTree":
+        return DeviceTree(self.children, self.n_nodes, self.max_depth, coeffs, scale, dtype,
                           self.n_leaves, self.leaf_stride, self.perm, self.layout)
 
     def view(self) -> TreeView:
@@ -238,7 +239,7 @@ class DeviceTree:
         v.children = self.children.data_ptr()
         v.n_nodes = self.n_nodes
         v.max_depth = self.max_depth
-        v.coeffs = None if self.planes is None else self.planes.data_ptr()
+        v.coeffs = None if self.coeffs is None else self.coeffs.data_ptr()
         v.leaf_scale = None if self.scale is None else self.scale.data_ptr()
         v.dtype = self.dtype
         v.n_leaves = self.n_leaves
@@ -312,15 +313,15 @@ def trace_rays(tree: DeviceTree, o, d, max_visits: int):
     return ids, t01, nv
 
 
-def render_backward(tree: DeviceTree, o, d, t_idx, basis, rgb_fwd, grad_rgb, grad_planes,
+def render_backward(tree: DeviceTree, o, d, t_idx, basis, rgb_fwd, grad_rgb, grad_coeffs,
                     opts: Optional[RenderOpts] = None):
-    """fpo_render_backward: adds dL/dk into grad_planes (F32 packed planes)."""
+    """fpo_render_backward: adds dL/dk into grad_coeffs (F32 leaf records)."""
     opts = opts or make_opts()
     tv = tree.view()
     _check(lib().fpo_render_backward(ctypes.byref(tv), _t_ptr(o), _t_ptr(d), _t_ptr(t_idx), _t_ptr(basis),
                                      int(basis.shape[0]), int(o.shape[0]), ctypes.byref(opts), _t_ptr(rgb_fwd),
-                                     _t_ptr(grad_rgb), _t_ptr(grad_planes), _stream()))
-    return grad_planes
+                                     _t_ptr(grad_rgb), _t_ptr(grad_coeffs), _stream()))
+    return grad_coeffs
 
 
 def l2_loss(rgb, images, image_idx, py, px, grad_rgb=None, loss=None):
@@ -348,21 +349,21 @@ def quantize(tree: DeviceTree, dtype: int) -> DeviceTree:
     import torch
     if tree.dtype != FPO_F32:
         raise ValueError("quantize needs an F32 tree")
-    dev = tree.planes.device
-    q = torch.zeros((n_planes(dtype), tree.leaf_stride, 4), dtype=torch.int32, device=dev)
+    dev = tree.coeffs.device
+    q = torch.zeros((tree.leaf_stride, record_words(dtype), 4), dtype=torch.int32, device=dev)
     scale = torch.empty((tree.leaf_stride,), dtype=torch.float32, device=dev)
-    _check(lib().fpo_quantize(_t_ptr(tree.planes), tree.n_leaves, tree.leaf_stride, int(dtype), _t_ptr(q),
+    _check(lib().fpo_quantize(_t_ptr(tree.coeffs), tree.n_leaves, tree.leaf_stride, int(dtype), _t_ptr(q),
                               _t_ptr(scale), _stream()))
     return tree.with_store(q, scale, dtype)
 
 
 def bake_times(tree: DeviceTree, basis, out_dtype: int = FPO_F32, out=None):
-    """fpo_bake_times -> out [n_t][28][leaf_stride] (float32 or bfloat16 tensor)."""
+    """fpo_bake_times -> out [n_t][leaf_stride][32] snapshot records (float32 or bfloat16)."""
     import torch
     n_t = int(basis.shape[0])
     if out is None:
         dt = torch.float32 if out_dtype == FPO_F32 else torch.bfloat16
-        out = torch.empty((n_t, N_BAKED, tree.leaf_stride), dtype=dt, device=basis.device)
+        out = torch.empty((n_t, tree.leaf_stride, SNAP_VALUES), dtype=dt, device=basis.device)
     tv = tree.view()
     _check(lib().fpo_bake_times(ctypes.byref(tv), _t_ptr(basis), n_t, int(out_dtype), _t_ptr(out), _stream()))
     return out

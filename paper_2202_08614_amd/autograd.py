@@ -14,13 +14,13 @@ from . import _lib
 
 
 class FPORender(torch.autograd.Function):
-    """rgb = render(planes) for given rays; planes are the F32 packed planes
+    """rgb = render(coeffs) for given rays; coeffs are the F32 leaf records
     of `tree` (passed explicitly so that autograd tracks them)."""
 
     @staticmethod
-    def forward(ctx, planes, tree: _lib.DeviceTree, o, d, t_idx, basis, opts: _lib.RenderOpts):
-        if planes.data_ptr() != tree.planes.data_ptr():
-            raise ValueError("planes must be the tree's coefficient store")
+    def forward(ctx, coeffs, tree: _lib.DeviceTree, o, d, t_idx, basis, opts: _lib.RenderOpts):
+        if coeffs.data_ptr() != tree.coeffs.data_ptr():
+            raise ValueError("coeffs must be the tree's coefficient store")
         rgb, _ = _lib.render_rays(tree, o, d, t_idx, basis, opts)
         ctx.save_for_backward(o, d, t_idx, basis, rgb)
         ctx.tree = tree
@@ -30,17 +30,17 @@ class FPORender(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_rgb):
         o, d, t_idx, basis, rgb = ctx.saved_tensors
-        grad = torch.zeros_like(ctx.tree.planes)
+        grad = torch.zeros_like(ctx.tree.coeffs)
         _lib.render_backward(ctx.tree, o, d, t_idx, basis, rgb, grad_rgb.contiguous(), grad, ctx.opts)
         return grad, None, None, None, None, None, None
 
 
 def render(tree: _lib.DeviceTree, o, d, t_idx, basis, opts: Optional[_lib.RenderOpts] = None):
-    return FPORender.apply(tree.planes, tree, o, d, t_idx, basis, opts or _lib.make_opts())
+    return FPORender.apply(tree.coeffs, tree, o, d, t_idx, basis, opts or _lib.make_opts())
 
 
 class Adam:
-    """Adam over a flat float tensor (the coefficient planes), one fused
+    """Adam over a flat float tensor (the coefficient records), one fused
     fpo_adam_step per step; the gradient buffer is cleared by the step."""
 
     def __init__(self, params: torch.Tensor, lr: float = 1e-2, betas=(0.9, 0.999), eps: float = 1e-8):

@@ -2,18 +2,17 @@
 // quantisation of the coefficient store, and the MFMA time bake.
 //
 // Bake (Eq. 7 and Eq. 9 evaluated at many times): for every leaf l and time t
-//     out[t][0][l]         = s_l * sum_{i<31} B[t][i] q_l[i]
-//     out[t][1 + m][l]     = s_l * sum_{i<5}  B[t][i] q_l[31 + 5 m + i],  m < 27
-// with B the FP32 basis of Eq. 8 and q_l the stored (dequantised up to the
-// scale s_l) coefficients.  Each 16 x 16 (times x leaves) output tile is a
-// v_mfma_f32_16x16x16_bf16 contraction.  BF16 operands carry only 8
-// significant bits, so every FP32 operand is split exactly into hi + lo BF16
-// parts (x = hi + lo + O(2^-16 x)) and the K dimension holds the three
-// products hi*hi + lo*hi + hi*lo: for the sigma row K = 3 x 32 = 96
-// (6 MFMAs of K = 16), for an SH row K = 3 x 5 = 15 (one MFMA, padded).
-// Stored BF16 and FP8 codes are exact in BF16, so their lo part is zero.
-// The kernel is bound by the output writes (n_t x 28 values per leaf), not by
-// the MFMA pipes.
+//     out[t][l][0]         = s_l * sum_{i<31} B[t][i] q_l[i]
+//     out[t][l][1 + m]     = s_l * sum_{i<5}  B[t][i] q_l[31 + 5 m + i],  m < 27
+// with B the FP32 basis of Eq. 8, q_l the stored coefficients and s_l the
+// leaf scale (1 for FP32 stores).  A wave takes 16 leaves; for each tile of
+// 16 times it forms every output row as a 16 x 16 (times x leaves) tile with
+// v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulate): the density row
+// contracts K = 32 (8 MFMAs), each of the 27 SH rows K = 8 (5 used, 2 MFMAs).
+// With all 28 rows of a tile in registers, each lane holds four complete
+// (time, leaf) records and writes them as whole 16-byte words, so the output
+// (the dominant traffic: n_t x 128 or 64 bytes per leaf) streams out in
+// full cache lines.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -61,105 +60,89 @@ __device__ inline uint32_t f32_to_e4m3_rne(float y)
     return code | sign;
 }
 
-// One thread per leaf: scale = max|k| (BF16) or max|k| / 448 (FP8), 1 for an
-// all-zero leaf; code = RNE(k / scale).  Reads the F32 packed planes, writes
-// the quantised packed planes and the scale.
+// One thread per leaf slot: scale = max|k| (BF16) or max|k| / 448 (FP8), 1 for
+// an all-zero leaf; code = RNE(k / scale).  Reads the F32 records, writes the
+// quantised records and the scale.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void quantize_kernel(const float4* src, int64_t n_leaves, int64_t stride,
                                                           uint4* dst, float* scale)
 {
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (l >= stride) return;
-    constexpr int kSrcWords = (FPO_N_COEFF + 3) / 4;     // 42
+    constexpr int kSrcR = Pack<FPO_F32>::R;
     constexpr int W = Pack<DT>::W;                        // 8 or 16 codes per word
-    constexpr int kDstWords = (FPO_N_COEFF + W - 1) / W;
+    constexpr int R = Pack<DT>::R;
+    uint4* out = dst + l * R;
     if (l >= n_leaves) {
-        for (int g = 0; g < kDstWords; ++g) dst[(int64_t)g * stride + l] = make_uint4(0, 0, 0, 0);
+        for (int g = 0; g < R; ++g) out[g] = make_uint4(0, 0, 0, 0);
         scale[l] = 1.0f;
         return;
     }
+    const float4* in = src + l * kSrcR;
+    float k[(FPO_N_COEFF + 3) / 4 * 4];
     float mx = 0.0f;
-    for (int g = 0; g < kSrcWords; ++g) {
-        const float4 w = src[(int64_t)g * stride + l];
+#pragma unroll
+    for (int g = 0; g < (FPO_N_COEFF + 3) / 4; ++g) {
+        const float4 w = in[g];
+        k[4 * g] = w.x; k[4 * g + 1] = w.y; k[4 * g + 2] = w.z; k[4 * g + 3] = w.w;
         mx = fmaxf(mx, fmaxf(fmaxf(fabsf(w.x), fabsf(w.y)), fmaxf(fabsf(w.z), fabsf(w.w))));
     }
     float s = (DT == FPO_BF16) ? mx : mx / 448.0f;
     if (mx == 0.0f) s = 1.0f;
     scale[l] = s;
-    for (int g = 0; g < kDstWords; ++g) {
+#pragma unroll
+    for (int g = 0; g < R; ++g) {
         uint32_t v[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int e = 0; e < W; ++e) {
             const int q = g * W + e;
-            float x = 0.0f;
-            if (q < FPO_N_COEFF) {
-                const float4 w = src[(int64_t)(q >> 2) * stride + l];
-                const float c[4] = {w.x, w.y, w.z, w.w};
-                x = c[q & 3];
-            }
-            const float y = x / s;
-            if (DT == FPO_BF16) {
+            if (q >= FPO_N_COEFF) continue;
+            const float y = k[q] / s;
+            if (DT == FPO_BF16)
                 v[e >> 1] |= f32_to_bf16_rne(y) << (16 * (e & 1));
-            } else {
+            else
                 v[e >> 2] |= f32_to_e4m3_rne(y) << (8 * (e & 3));
-            }
         }
-        dst[(int64_t)g * stride + l] = make_uint4(v[0], v[1], v[2], v[3]);
+        out[g] = make_uint4(v[0], v[1], v[2], v[3]);
     }
 }
 
 // ---------------------------------------------------------------------------
 // MFMA bake
 // ---------------------------------------------------------------------------
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// Exact split x = hi + lo (+ residual of relative size 2^-16): hi is x
-// truncated to BF16, lo the BF16 rounding of the remainder.
-__device__ inline void split_bf16(float x, uint16_t& hi, uint16_t& lo)
-{
-    const uint32_t hb = __float_as_uint(x) & 0xFFFF0000u;
-    hi = (uint16_t)(hb >> 16);
-    lo = (uint16_t)f32_to_bf16_rne(x - __uint_as_float(hb));
-}
 
 constexpr int kBakeLeaves = 16;           // leaves per wave (one MFMA N tile)
 constexpr int kBakeWaves = kBlock / kWave;
-constexpr int kKSig = 96;                 // 3 x 32
-constexpr int kKZ = 16;                   // 3 x 5, padded
+constexpr int kCoefPad = 169;             // LDS row stride (odd: spreads banks)
 
 struct BakeLaunch {
     TreeDev tree;
     const float* basis;    // [n_t][32]
     int32_t n_t;
-    int32_t dtype;         // coefficient store dtype
     int32_t out_bf16;
     int64_t n_leaves;
-    void* out;             // [n_t][28][stride]
+    void* out;             // [n_t][stride][32] records
 };
 
-// Coefficients of the wave's 16 leaves as BF16 hi / lo, [leaf][168].
 struct BakeLds {
-    uint16_t hi[kBakeWaves][kBakeLeaves][168];
-    uint16_t lo[kBakeWaves][kBakeLeaves][168];
-    uint16_t bhi[16][32];   // basis of the current 16-time tile
-    uint16_t blo[16][32];
+    float coef[kBakeWaves][kBakeLeaves][kCoefPad];   // decoded coefficients, [leaf][q]
+    float basis[16][33];                             // current 16-time tile
 };
 
 template <int DT>
 __device__ inline void stage_leaf_coeffs(const BakeLaunch& a, BakeLds& L, int wv, int ln, int64_t leaf0)
 {
     constexpr int W = Pack<DT>::W;
+    constexpr int R = Pack<DT>::R;
     constexpr int kWords = (FPO_N_COEFF + W - 1) / W;
-    // lane -> (leaf, word) pairs; 16 leaves x kWords words
     for (int idx = ln; idx < kBakeLeaves * kWords; idx += kWave) {
-        const int li = idx % kBakeLeaves;
-        const int g = idx / kBakeLeaves;
+        const int li = idx / kWords;
+        const int g = idx - li * kWords;
         const int64_t leaf = leaf0 + li;
         float v[W];
         if (leaf < a.n_leaves) {
-            const uint4 w = a.tree.planes[(int64_t)g * a.tree.stride + leaf];
-            Pack<DT>::unpack(w, v);
+            Pack<DT>::unpack(a.tree.recs[leaf * R + g], v);
         } else {
 #pragma unroll
             for (int e = 0; e < W; ++e) v[e] = 0.0f;
@@ -167,31 +150,8 @@ __device__ inline void stage_leaf_coeffs(const BakeLaunch& a, BakeLds& L, int wv
 #pragma unroll
         for (int e = 0; e < W; ++e) {
             const int q = g * W + e;
-            if (q < 168) {
-                uint16_t h, l;
-                split_bf16(q < FPO_N_COEFF ? v[e] : 0.0f, h, l);
-                L.hi[wv][li][q] = h;
-                L.lo[wv][li][q] = l;
-            }
+            if (q < kCoefPad) L.coef[wv][li][q] = q < FPO_N_COEFF ? v[e] : 0.0f;
         }
-    }
-}
-
-__device__ inline void store_tile(const BakeLaunch& a, const f32x4& acc, int row, int t0, int ln, int64_t leaf0,
-                                  float s)
-{
-    const int64_t leaf = leaf0 + (ln & 15);
-    if (leaf >= a.n_leaves) return;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int t = t0 + 4 * (ln >> 4) + r;
-        if (t >= a.n_t) continue;
-        const float v = acc[r] * s;
-        const int64_t off = ((int64_t)t * FPO_N_BAKED + row) * a.tree.stride + leaf;
-        if (a.out_bf16)
-            static_cast<uint16_t*>(a.out)[off] = (uint16_t)f32_to_bf16_rne(v);
-        else
-            static_cast<float*>(a.out)[off] = v;
     }
 }
 
@@ -203,61 +163,75 @@ __global__ __launch_bounds__(kBlock) void bake_kernel(BakeLaunch a)
     const int ln = threadIdx.x % kWave;
     const int64_t leaf0 = ((int64_t)blockIdx.x * kBakeWaves + wv) * kBakeLeaves;
     stage_leaf_coeffs<DT>(a, L, wv, ln, leaf0);
-    const int64_t my_leaf = leaf0 + (ln & 15);
-    float s = 1.0f;
-    if (DT != FPO_F32 && my_leaf < a.n_leaves) s = a.tree.scale[my_leaf];
-    const int n = ln & 15;      // MFMA row of A / column of B and D
-    const int kg = ln >> 4;     // k group: k = 4 kg .. 4 kg + 3
+    const int n = ln & 15;      // A row (time) / B and D column (leaf)
+    const int kq = ln >> 4;     // k index inside a K = 4 step; D rows 4 kq .. 4 kq + 3
+    const int64_t my_leaf = leaf0 + n;
+    const float s = (DT != FPO_F32 && my_leaf < a.n_leaves) ? a.tree.scale[my_leaf] : 1.0f;
 
     for (int t0 = 0; t0 < a.n_t; t0 += 16) {
         __syncthreads();
-        // basis tile for times t0 .. t0 + 15, split into hi / lo
         for (int idx = threadIdx.x; idx < 16 * 32; idx += kBlock) {
             const int tt = idx / 32, i = idx % 32;
-            const float v = (t0 + tt < a.n_t) ? a.basis[(int64_t)(t0 + tt) * FPO_BASIS_STRIDE + i] : 0.0f;
-            uint16_t h, l;
-            split_bf16(i < FPO_N_SIGMA ? v : 0.0f, h, l);
-            L.bhi[tt][i] = h;
-            L.blo[tt][i] = l;
+            L.basis[tt][i] = (t0 + tt < a.n_t && i < FPO_N_SIGMA)
+                                 ? a.basis[(int64_t)(t0 + tt) * FPO_BASIS_STRIDE + i] : 0.0f;
         }
         __syncthreads();
-
-        // sigma row: K = [hi | lo | hi] (basis) x [hi ; hi ; lo] (coefficients)
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        f32x4 acc[FPO_N_BAKED];
+        // density row: K = 32
+        acc[0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kk = 0; kk < kKSig / 16; ++kk) {
-            bf16x4 av, bv;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = kk * 16 + 4 * kg + e;       // 0 .. 95
-                const int part = k / 32, i = k % 32;
-                av[e] = (short)(part == 1 ? L.blo[n][i] : L.bhi[n][i]);
-                bv[e] = (short)(part == 2 ? L.lo[wv][n][i] : L.hi[wv][n][i]);
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        for (int kk = 0; kk < 8; ++kk) {
+            const int k = 4 * kk + kq;
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.basis[n][k], L.coef[wv][n][k], acc[0], 0, 0, 0);
         }
-        store_tile(a, acc, 0, t0, ln, leaf0, s);
-
-        // SH rows: K = 15 (+1 padding) per row
-        bf16x4 az;
+        // SH rows: K = 5 (padded to 8)
+        const float a0 = kq < FPO_N_SH_FOURIER ? L.basis[n][kq] : 0.0f;
+        const float a1 = kq + 4 < FPO_N_SH_FOURIER ? L.basis[n][kq + 4] : 0.0f;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int k = 4 * kg + e;                       // 0 .. 15
-            const int part = k / 5, i = k % 5;
-            az[e] = (short)(k >= 15 ? 0 : (part == 1 ? L.blo[n][i] : L.bhi[n][i]));
-        }
-        for (int m = 0; m < 27; ++m) {
-            bf16x4 bz;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = 4 * kg + e;
-                const int part = k / 5, i = k % 5;
-                const int q = FPO_N_SIGMA + FPO_N_SH_FOURIER * m + i;
-                bz[e] = (short)(k >= 15 ? 0 : (part == 2 ? L.lo[wv][n][q] : L.hi[wv][n][q]));
-            }
+        for (int m = 0; m < FPO_N_BAKED - 1; ++m) {
+            const int q = FPO_N_SIGMA + FPO_N_SH_FOURIER * m;
+            const float b0 = L.coef[wv][n][q + kq];
+            const float b1 = kq + 4 < FPO_N_SH_FOURIER ? L.coef[wv][n][q + kq + 4] : 0.0f;
             f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-            z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(az, bz, z, 0, 0, 0);
-            store_tile(a, z, 1 + m, t0, ln, leaf0, s);
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, z, 0, 0, 0);
+            acc[1 + m] = z;
+        }
+        // lane (kq, n) holds rows q of D[t = 4 kq + r][leaf n]: four whole records
+        if (my_leaf < a.n_leaves) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = t0 + 4 * kq + r;
+                if (t >= a.n_t) continue;
+                const int64_t rec = (int64_t)t * a.tree.stride + my_leaf;
+                if (a.out_bf16) {
+                    uint4* o = static_cast<uint4*>(a.out) + rec * 4;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        uint32_t u[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int q0 = 8 * w + 2 * e, q1 = q0 + 1;
+                            const float v0 = q0 < FPO_N_BAKED ? acc[q0][r] * s : 0.0f;
+                            const float v1 = q1 < FPO_N_BAKED ? acc[q1][r] * s : 0.0f;
+                            u[e] = f32_to_bf16_rne(v0) | (f32_to_bf16_rne(v1) << 16);
+                        }
+                        o[w] = make_uint4(u[0], u[1], u[2], u[3]);
+                    }
+                } else {
+                    float4* o = static_cast<float4*>(a.out) + rec * 8;
+#pragma unroll
+                    for (int w = 0; w < 8; ++w) {
+                        float v[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int q = 4 * w + e;
+                            v[e] = q < FPO_N_BAKED ? acc[q][r] * s : 0.0f;
+                        }
+                        o[w] = make_float4(v[0], v[1], v[2], v[3]);
+                    }
+                }
+            }
         }
     }
 }
@@ -303,7 +277,6 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
     a.tree = dev::tree_dev(tree);
     a.basis = basis;
     a.n_t = n_t;
-    a.dtype = tree->dtype;
     a.out_bf16 = out_dtype == FPO_BF16;
     a.n_leaves = tree->n_leaves;
     a.out = out;

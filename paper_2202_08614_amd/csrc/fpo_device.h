@@ -21,9 +21,9 @@ constexpr int kStackLevels = FPO_MAX_DEPTH;
 // Plain-old-data view of a tree, passed by value to kernels.
 struct TreeDev {
     const int32_t* children;
-    const uint4* planes;    // packed planes, one 16-byte word per (plane, leaf)
+    const uint4* recs;      // leaf records: R 16-byte words per leaf slot
     const float* scale;     // per-leaf scale for quantised stores
-    int64_t stride;         // words per plane (leaf_stride)
+    int64_t stride;         // leaf slots (leaf_stride)
     int32_t n_nodes;
     int32_t n_leaves;
     int32_t max_depth;
@@ -35,7 +35,7 @@ inline TreeDev tree_dev(const fpo_tree_view* t)
 {
     TreeDev d;
     d.children = t->children;
-    d.planes = static_cast<const uint4*>(t->coeffs);
+    d.recs = static_cast<const uint4*>(t->coeffs);
     d.scale = t->leaf_scale;
     d.stride = t->leaf_stride;
     d.n_nodes = (int32_t)t->n_nodes;
@@ -46,12 +46,15 @@ inline TreeDev tree_dev(const fpo_tree_view* t)
 }
 
 // --------------------------------------------------------------------------
-// Coefficient words.  W coefficients per 16-byte word.
+// Coefficient words.  W coefficients per 16-byte word; R words per leaf
+// record (a multiple of 128 bytes, so that a record starts a cache line and
+// the words holding the 31 density coefficients share one line).
 // --------------------------------------------------------------------------
 template <int DT> struct Pack;
 
 template <> struct Pack<FPO_F32> {
     static constexpr int W = 4;
+    static constexpr int R = 48;
     __device__ static inline void unpack(const uint4& w, float* o)
     {
         o[0] = __uint_as_float(w.x); o[1] = __uint_as_float(w.y);
@@ -61,6 +64,7 @@ template <> struct Pack<FPO_F32> {
 
 template <> struct Pack<FPO_BF16> {
     static constexpr int W = 8;
+    static constexpr int R = 24;
     __device__ static inline void unpack(const uint4& w, float* o)
     {
         const uint32_t v[4] = {w.x, w.y, w.z, w.w};
@@ -84,6 +88,7 @@ __device__ inline float e4m3_to_f32(uint32_t byte)
 
 template <> struct Pack<FPO_FP8_E4M3> {
     static constexpr int W = 16;
+    static constexpr int R = 16;
     __device__ static inline void unpack(const uint4& w, float* o)
     {
         const uint32_t v[4] = {w.x, w.y, w.z, w.w};
@@ -273,10 +278,10 @@ struct LeafEval {
     // quantised stores).  `k` keeps the unpacked values for colour().
     __device__ static inline float sigma(const TreeDev& T, int leaf, const float* b, float* k, float& scale)
     {
-        const uint4* P = T.planes + leaf;
+        const uint4* P = T.recs + (int64_t)leaf * Pack<DT>::R;
 #pragma unroll
         for (int g = 0; g < kSigmaWords; ++g) {
-            const uint4 w = P[(int64_t)g * T.stride];
+            const uint4 w = P[g];
             Pack<DT>::unpack(w, k + g * W);
         }
         float s = 0.0f;
@@ -290,7 +295,7 @@ struct LeafEval {
     __device__ static inline void colour(const TreeDev& T, int leaf, const float* b, const float* Y,
                                          const float* k, float scale, float* h)
     {
-        const uint4* P = T.planes + leaf;
+        const uint4* P = T.recs + (int64_t)leaf * Pack<DT>::R;
         float kz[(kWords - kSigmaWords + 1) * W];
         // coefficient q >= 31 lives at kz[q - 31 + off]
         constexpr int off = FPO_N_SIGMA - (kSigmaWords - 1) * W;   // index of q = 31 inside the last sigma word
@@ -298,7 +303,7 @@ struct LeafEval {
         for (int e = 0; e < W; ++e) kz[e] = k[(kSigmaWords - 1) * W + e];
 #pragma unroll
         for (int g = kSigmaWords; g < kWords; ++g) {
-            const uint4 w = P[(int64_t)g * T.stride];
+            const uint4 w = P[g];
             Pack<DT>::unpack(w, kz + (g - kSigmaWords + 1) * W);
         }
         h[0] = h[1] = h[2] = 0.0f;
@@ -318,14 +323,31 @@ struct LeafEval {
 
 __device__ inline float sigmoidf_(float h) { return __builtin_amdgcn_rcpf(1.0f + __expf(-h)); }
 
-// Snapshot reads: 28 baked values per leaf in planes [28][stride].
+// Snapshot records: 32 values per leaf slot (row 0 = sigma(t) before
+// activation, rows 1 + c*9 + j = z_{c,j}(t), rows 28..31 zero), F32 (8 words,
+// 128 bytes) or BF16 (4 words, 64 bytes).
 template <int SDT>
-__device__ inline float snap_load(const void* S, int64_t stride, int row, int leaf)
-{
-    if (SDT == FPO_F32) return static_cast<const float*>(S)[(int64_t)row * stride + leaf];
-    const uint16_t v = static_cast<const uint16_t*>(S)[(int64_t)row * stride + leaf];
-    return __uint_as_float((uint32_t)v << 16);
-}
+struct SnapEval {
+    static constexpr int W = Pack<SDT>::W;      // values per word: 4 or 8
+    static constexpr int R = 32 / W;            // words per record: 8 or 4
+    __device__ static inline float sigma(const void* S, int leaf, float* v)
+    {
+        const uint4 w = static_cast<const uint4*>(S)[(int64_t)leaf * R];
+        Pack<SDT>::unpack(w, v);
+        return v[0];
+    }
+    __device__ static inline void colour(const void* S, int leaf, const float* Y, float* v, float* h)
+    {
+        const uint4* P = static_cast<const uint4*>(S) + (int64_t)leaf * R;
+#pragma unroll
+        for (int g = 1; g < R; ++g) Pack<SDT>::unpack(P[g], v + g * W);
+        h[0] = h[1] = h[2] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < FPO_N_SH; ++j) h[c] = fmaf(v[1 + c * FPO_N_SH + j], Y[j], h[c]);
+    }
+};
 
 // --------------------------------------------------------------------------
 // Front-to-back compositing visitor.  MODE: a coefficient dtype (Fourier
@@ -338,7 +360,7 @@ template <int MODE>
 struct Shade {
     const TreeDev& T;
     const float* b;       // basis row (Fourier mode)
-    const void* snap;     // snapshot planes (snapshot mode)
+    const void* snap;     // snapshot records (snapshot mode)
     float Y[9];
     float Tr;             // transmittance
     float C[3];
@@ -350,15 +372,11 @@ struct Shade {
         float sraw, h[3];
         if constexpr (MODE >= 16) {
             constexpr int SDT = MODE - 16;
-            sraw = snap_load<SDT>(snap, T.stride, 0, leaf);
+            float v[32];
+            sraw = SnapEval<SDT>::sigma(snap, leaf, v);
             const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
             if (!(sig * delta > 0.0f)) return false;
-            h[0] = h[1] = h[2] = 0.0f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int j = 0; j < FPO_N_SH; ++j)
-                    h[c] = fmaf(snap_load<SDT>(snap, T.stride, 1 + c * FPO_N_SH + j, leaf), Y[j], h[c]);
+            SnapEval<SDT>::colour(snap, leaf, Y, v, h);
         } else {
             constexpr int W = LeafEval<MODE>::W;
             float k[LeafEval<MODE>::kSigmaWords * W];

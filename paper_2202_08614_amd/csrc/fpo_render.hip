@@ -94,7 +94,7 @@ struct RaysLaunch {
     const int32_t* t_idx;
     const float* basis;     // [n_t][32]
     const void* snap;
-    int64_t snap_stride;    // elements between consecutive time indices' snapshots
+    int64_t snap_stride;    // leaf records between consecutive time indices' snapshots
     int64_t n;
     int32_t n_t;
     float* rgb;
@@ -120,8 +120,8 @@ __global__ __launch_bounds__(kBlock) void render_rays_kernel(RaysLaunch a)
     }
     const void* snap = a.snap;
     if constexpr (MODE >= 16) {
-        const size_t esz = (MODE - 16) == FPO_F32 ? 4 : 2;
-        snap = static_cast<const char*>(a.snap) + (size_t)ti * (size_t)a.snap_stride * esz;
+        const size_t rec = (MODE - 16) == FPO_F32 ? 128 : 64;
+        snap = static_cast<const char*>(a.snap) + (size_t)ti * (size_t)a.snap_stride * rec;
     }
     Shade<MODE> sh{a.tree, b, snap};
     sh.Tr = 1.0f;
@@ -205,22 +205,23 @@ __global__ __launch_bounds__(kBlock) void camera_rays_kernel(const float* table,
     }
 }
 
-// dst word (g, slot) = coefficients 4g .. 4g+3 of leaf perm[slot].
+// dst word (slot, g) = coefficients 4g .. 4g+3 of leaf perm[slot] (F32
+// records of 48 words; padding words and slots >= n_leaves are zero).
 __global__ __launch_bounds__(kBlock) void pack_coeffs_kernel(const float* src, const int64_t* perm,
                                                              int64_t n_leaves, int64_t stride, float4* dst)
 {
+    constexpr int R = Pack<FPO_F32>::R;
     const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t n_planes = (FPO_N_COEFF + 3) / 4;
-    if (id >= n_planes * stride) return;
-    const int64_t g = id / stride;
-    const int64_t slot = id - g * stride;
+    if (id >= R * stride) return;
+    const int64_t slot = id / R;
+    const int g = (int)(id - slot * R);
     float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (slot < n_leaves) {
         const int64_t p = perm[slot];
         if (p >= 0 && p < n_leaves) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t q = 4 * g + e;
+                const int q = 4 * g + e;
                 if (q < FPO_N_COEFF) v[e] = src[p * FPO_N_COEFF + q];
             }
         }
@@ -279,7 +280,7 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
     for (int c = 0; c < 3; ++c) a.bg[c] = opts->bg[c];
     a.stop_T = opts->stop_T;
     const int mode = mode_of(tree, opts);
-    const size_t snap_esz = opts->snapshot_dtype == FPO_F32 ? 4 : 2;
+    const size_t snap_rec = opts->snapshot_dtype == FPO_F32 ? 128 : 64;   // bytes per leaf record
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int c0 = 0; c0 < n_cams; c0 += dev::kCamsPerLaunch) {
         const int nc = std::min(dev::kCamsPerLaunch, n_cams - c0);
@@ -289,7 +290,7 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
             camera_frame(cam, a.cam[i].frame);
             basis_row(cam.time, (double)tree->layout.period, tree->layout.n_sigma, a.cam[i].basis);
             a.cam[i].snap = opts->snapshot
-                ? static_cast<const char*>(opts->snapshot) + (size_t)(c0 + i) * (size_t)opts->snapshot_cam_stride * snap_esz
+                ? static_cast<const char*>(opts->snapshot) + (size_t)(c0 + i) * (size_t)opts->snapshot_cam_stride * snap_rec
                 : nullptr;
         }
         a.rgb = rgb_out + (int64_t)c0 * W * H * 3;
@@ -390,7 +391,7 @@ extern "C" fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int
 {
     if (!src || !perm || !dst) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_leaves < 1 || leaf_stride < n_leaves) return fail(FPO_E_INVALID, "bad n_leaves / leaf_stride");
-    const int64_t total = (int64_t)((FPO_N_COEFF + 3) / 4) * leaf_stride;
+    const int64_t total = (int64_t)dev::Pack<FPO_F32>::R * leaf_stride;
     if (total > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many leaves");
     const int64_t grid = (total + dev::kBlock - 1) / dev::kBlock;
     hipLaunchKernelGGL(dev::pack_coeffs_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,

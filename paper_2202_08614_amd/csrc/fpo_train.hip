@@ -12,7 +12,7 @@
 //     dL/dk^sigma_q     = s [sigma_raw > 0] dL/dsigma_i b_q,
 //     dL/dk^z_{c,j,i}   = dL/dh_{i,c} Y_j b_i.
 // The 166 coefficient gradients of each sample are scattered with FP32
-// atomics into planes laid out like the F32 coefficient store.
+// atomics into records laid out like the F32 coefficient store.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,7 +29,7 @@ namespace dev {
 struct BackwardVisitor {
     const TreeDev& T;
     const float* b;
-    float* grad;          // F32 packed planes: word (g, leaf) holds 4 floats
+    float* grad;          // F32 leaf records: 192 floats per leaf slot
     float Y[9];
     float Tr;
     float acc[3];         // accumulated colour sum_{j<=i} T_j alpha_j c_j
@@ -40,7 +40,7 @@ struct BackwardVisitor {
 
     __device__ inline void add(int q, int leaf, float v)
     {
-        float* p = grad + ((int64_t)(q >> 2) * T.stride + leaf) * 4 + (q & 3);
+        float* p = grad + (int64_t)leaf * (4 * Pack<FPO_F32>::R) + q;
         unsafeAtomicAdd(p, v);
     }
 

@@ -31,9 +31,9 @@ class FineTuner:
         self.batch = int(batch)
         self.gen = torch.Generator(device=dev)
         self.gen.manual_seed(seed)
-        self.grad = torch.zeros_like(tree.planes)
-        self.m = torch.zeros_like(tree.planes)
-        self.v = torch.zeros_like(tree.planes)
+        self.grad = torch.zeros_like(tree.coeffs)
+        self.m = torch.zeros_like(tree.coeffs)
+        self.v = torch.zeros_like(tree.coeffs)
         self.lr = float(lr)
         self.t = 0
         n = self.batch
@@ -70,7 +70,7 @@ class FineTuner:
                              self.opts)
         if with_adam:
             self.t += 1
-            _lib.adam_step(self.tree.planes, self.grad, self.m, self.v, self.t, lr=self.lr)
+            _lib.adam_step(self.tree.coeffs, self.grad, self.m, self.v, self.t, lr=self.lr)
 
     def train(self, n_steps: int) -> List[float]:
         losses = torch.zeros(n_steps, dtype=torch.float32, device=self.images.device)

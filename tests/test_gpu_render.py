@@ -213,9 +213,9 @@ def test_pack_coeffs_layout(dev):
     note("fpo_pack_coeffs")
     tree = _lib.DeviceTree.from_leaves(dijk, coeffs, 4, device=dev, leaf_stride=len(dijk) + 13)
     torch.cuda.synchronize()
-    planes = tree.planes.cpu().numpy()                 # [42][stride][4]
-    flat = planes.transpose(1, 0, 2).reshape(tree.leaf_stride, -1)   # [stride][168]
-    want = np.zeros((tree.leaf_stride, 168), np.float32)
+    recs = tree.coeffs.cpu().numpy()                   # [stride][48][4]
+    flat = recs.reshape(tree.leaf_stride, -1)          # [stride][192]
+    want = np.zeros((tree.leaf_stride, 192), np.float32)
     want[:len(dijk), :166] = coeffs[tree.perm]
     assert np.array_equal(flat, want)
 

@@ -16,9 +16,9 @@ def dev():
     return require_gpu()
 
 
-def _unpack(planes_np: np.ndarray, perm: np.ndarray, n: int) -> np.ndarray:
-    """[42][stride][4] packed planes -> [L][166] caller order."""
-    flat = planes_np.transpose(1, 0, 2).reshape(planes_np.shape[1], -1)[:n, :166]
+def _unpack(recs: np.ndarray, perm: np.ndarray, n: int) -> np.ndarray:
+    """[stride][48][4] F32 leaf records -> [L][166] caller order."""
+    flat = recs.reshape(recs.shape[0], -1)[:n, :166]
     out = np.zeros_like(flat)
     out[perm] = flat
     return out
@@ -53,7 +53,7 @@ def test_backward_matches_oracle_gradient(oracle_lib, dev, stop_T):
     opts = _lib.make_opts(stop_T=stop_T, bg=(0.2, 0.3, 0.4))
     note(f"backward vs oracle stop_T={stop_T}")
     rgb, _ = _lib.render_rays(tree, to(o), to(d), to(t_idx), basis, opts)
-    grad = torch.zeros_like(tree.planes)
+    grad = torch.zeros_like(tree.coeffs)
     _lib.render_backward(tree, to(o), to(d), to(t_idx), basis, rgb, to(g_rgb), grad, opts)
     torch.cuda.synchronize()
     got = _unpack(grad.cpu().numpy(), tree.perm, len(dijk))
@@ -81,7 +81,7 @@ def test_backward_matches_gpu_central_differences(oracle_lib, dev):
     opts = _lib.make_opts()
     note("backward vs GPU central differences")
     rgb, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, opts)
-    grad = torch.zeros_like(tree.planes)
+    grad = torch.zeros_like(tree.coeffs)
     _lib.render_backward(tree, o_d, d_d, t_d, basis, rgb, w_d, grad, opts)
     g = grad.cpu().numpy()
     rng = np.random.default_rng(2)
@@ -90,19 +90,19 @@ def test_backward_matches_gpu_central_differences(oracle_lib, dev):
     assert len(cand) >= 64
     pick = rng.choice(cand, 64, replace=False)
     h = 1e-3
-    planes = tree.planes.view(-1)
+    flat_coeffs = tree.coeffs.view(-1)
 
     def loss():
         r, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, opts)
         return float((r.double().cpu().numpy() * w).sum())
 
     for idx in pick:
-        k0 = float(planes[idx])
-        planes[idx] = k0 + h
+        k0 = float(flat_coeffs[idx])
+        flat_coeffs[idx] = k0 + h
         lp = loss()
-        planes[idx] = k0 - h
+        flat_coeffs[idx] = k0 - h
         lm = loss()
-        planes[idx] = k0
+        flat_coeffs[idx] = k0
         fd = (lp - lm) / (2 * h)
         an = float(g.reshape(-1)[idx])
         assert abs(fd - an) <= 2e-2 * abs(an) + 2e-3 * flat.max(), (idx, fd, an)
