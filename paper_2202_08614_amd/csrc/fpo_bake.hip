@@ -128,6 +128,7 @@ struct BakeLaunch {
 struct BakeLds {
     float coef[kBakeWaves][kBakeLeaves][kCoefPad];   // decoded coefficients, [leaf][q]
     float basis[16][33];                             // current 16-time tile
+    float4 out[kBakeWaves][4][kBakeLeaves][8];       // 4 times x 16 leaves records, for stores
 };
 
 template <int DT>
@@ -197,41 +198,51 @@ __global__ __launch_bounds__(kBlock) void bake_kernel(BakeLaunch a)
             z = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, z, 0, 0, 0);
             acc[1 + m] = z;
         }
-        // lane (kq, n) holds rows q of D[t = 4 kq + r][leaf n]: four whole records
-        if (my_leaf < a.n_leaves) {
+        // lane (kq, n) holds rows q of D[t = 4 kq + r][leaf n]: four whole
+        // records.  For each r, park them in LDS as [kq][leaf][word] and write
+        // out, per time, the 16 consecutive records of the wave (2 KB F32 /
+        // 1 KB BF16 contiguous) as full 16-byte words.
+        const int n_valid = (int)min<int64_t>(kBakeLeaves, a.n_leaves - leaf0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int t = t0 + 4 * kq + r;
-                if (t >= a.n_t) continue;
-                const int64_t rec = (int64_t)t * a.tree.stride + my_leaf;
-                if (a.out_bf16) {
-                    uint4* o = static_cast<uint4*>(a.out) + rec * 4;
+        for (int r = 0; r < 4; ++r) {
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        uint32_t u[4];
+            for (int w = 0; w < 8; ++w) {
+                float v[4];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int q0 = 8 * w + 2 * e, q1 = q0 + 1;
-                            const float v0 = q0 < FPO_N_BAKED ? acc[q0][r] * s : 0.0f;
-                            const float v1 = q1 < FPO_N_BAKED ? acc[q1][r] * s : 0.0f;
-                            u[e] = f32_to_bf16_rne(v0) | (f32_to_bf16_rne(v1) << 16);
+                for (int e = 0; e < 4; ++e) {
+                    const int q = 4 * w + e;
+                    v[e] = q < FPO_N_BAKED ? acc[q][r] * s : 0.0f;
+                }
+                L.out[wv][kq][n][w] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            // 4 times x 16 leaves x 8 words = 512 F32 words: 8 per lane
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+                const int idx = it * kWave + ln;           // [kq][leaf][w]
+                const int tq = idx >> 7, li = (idx >> 3) & 15, w = idx & 7;
+                const int t = t0 + 4 * tq + r;
+                if (t < a.n_t && li < n_valid) {
+                    const float4 v = L.out[wv][tq][li][w];
+                    const int64_t rec = (int64_t)t * a.tree.stride + leaf0 + li;
+                    if (a.out_bf16) {
+                        // two F32 words become one half of a BF16 word
+                        if ((w & 1) == 0) {
+                            const float4 u = L.out[wv][tq][li][w + 1];
+                            uint4 o4;
+                            o4.x = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
+                            o4.y = f32_to_bf16_rne(v.z) | (f32_to_bf16_rne(v.w) << 16);
+                            o4.z = f32_to_bf16_rne(u.x) | (f32_to_bf16_rne(u.y) << 16);
+                            o4.w = f32_to_bf16_rne(u.z) | (f32_to_bf16_rne(u.w) << 16);
+                            static_cast<uint4*>(a.out)[rec * 4 + (w >> 1)] = o4;
                         }
-                        o[w] = make_uint4(u[0], u[1], u[2], u[3]);
-                    }
-                } else {
-                    float4* o = static_cast<float4*>(a.out) + rec * 8;
-#pragma unroll
-                    for (int w = 0; w < 8; ++w) {
-                        float v[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int q = 4 * w + e;
-                            v[e] = q < FPO_N_BAKED ? acc[q][r] * s : 0.0f;
-                        }
-                        o[w] = make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+                        static_cast<float4*>(a.out)[rec * 8 + w] = v;
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }

@@ -222,12 +222,10 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             lo[a] = c[a] & ~(size - 1);
-            if (r.d[a] > 0.0f)
-                te[a] = ((float)(lo[a] + size) * invG - r.o[a]) * r.inv[a];
-            else if (r.d[a] < 0.0f)
-                te[a] = ((float)lo[a] * invG - r.o[a]) * r.inv[a];
-            else
-                te[a] = __builtin_inff();
+            // exit face of this axis: the cell's upper face when moving up, lower when down
+            const int face = r.d[a] > 0.0f ? lo[a] + size : lo[a];
+            const float tf = ((float)face * invG - r.o[a]) * r.inv[a];
+            te[a] = r.d[a] == 0.0f ? __builtin_inff() : tf;
         }
         int ax = 0;
         float t_exit = te[0];
@@ -241,15 +239,15 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
         int nc[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (a == ax) {
-                nc[a] = r.d[a] > 0.0f ? lo[a] + size : lo[a] - 1;
-            } else if (r.d[a] == 0.0f) {
-                nc[a] = c[a];
-            } else {
-                int v = (int)floorf(fmaf(t_exit, r.d[a], r.o[a]) * fG);
-                v = min(max(v, lo[a]), lo[a] + size - 1);
-                nc[a] = r.d[a] > 0.0f ? max(v, c[a]) : min(v, c[a]);
-            }
+            // other axes: lattice cell of the exit point, clamped into the cell
+            // just left and never moving against the ray
+            int v = (int)floorf(fmaf(t_exit, r.d[a], r.o[a]) * fG);
+            v = min(max(v, lo[a]), lo[a] + size - 1);
+            v = r.d[a] > 0.0f ? max(v, c[a]) : min(v, c[a]);
+            v = r.d[a] == 0.0f ? c[a] : v;
+            // exit axis: one lattice cell past the face
+            const int step = r.d[a] > 0.0f ? lo[a] + size : lo[a] - 1;
+            nc[a] = a == ax ? step : v;
         }
         if (nc[ax] < 0 || nc[ax] >= G) return;
         const unsigned diff = (unsigned)((c[0] ^ nc[0]) | (c[1] ^ nc[1]) | (c[2] ^ nc[2]));
