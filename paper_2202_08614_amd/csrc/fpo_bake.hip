@@ -199,7 +199,9 @@ __global__ __launch_bounds__(kBlock) void bake_kernel(BakeLaunch a)
             acc[1 + m] = z;
         }
         // lane (kq, n) holds rows q of D[t = 4 kq + r][leaf n]: four whole
-        // records.  For each r, park them in LDS as [kq][leaf][word] and write
+        // records.  For each r, park them in LDS as [kq][leaf][word] (word w
+        // of leaf n stored at slot w ^ (n & 7), so that the per-lane record
+        // writes and the row reads both spread over all 32 banks) and write
         // out, per time, the 16 consecutive records of the wave (2 KB F32 /
         // 1 KB BF16 contiguous) as full 16-byte words.
         const int n_valid = (int)min<int64_t>(kBakeLeaves, a.n_leaves - leaf0);
@@ -213,32 +215,39 @@ __global__ __launch_bounds__(kBlock) void bake_kernel(BakeLaunch a)
                     const int q = 4 * w + e;
                     v[e] = q < FPO_N_BAKED ? acc[q][r] * s : 0.0f;
                 }
-                L.out[wv][kq][n][w] = make_float4(v[0], v[1], v[2], v[3]);
+                L.out[wv][kq][n][w ^ (n & 7)] = make_float4(v[0], v[1], v[2], v[3]);
             }
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            // 4 times x 16 leaves x 8 words = 512 F32 words: 8 per lane
+            if (a.out_bf16) {
+                // 4 times x 16 leaves x 4 BF16 words = 256 words: 4 per lane
 #pragma unroll
-            for (int it = 0; it < 8; ++it) {
-                const int idx = it * kWave + ln;           // [kq][leaf][w]
-                const int tq = idx >> 7, li = (idx >> 3) & 15, w = idx & 7;
-                const int t = t0 + 4 * tq + r;
-                if (t < a.n_t && li < n_valid) {
-                    const float4 v = L.out[wv][tq][li][w];
-                    const int64_t rec = (int64_t)t * a.tree.stride + leaf0 + li;
-                    if (a.out_bf16) {
-                        // two F32 words become one half of a BF16 word
-                        if ((w & 1) == 0) {
-                            const float4 u = L.out[wv][tq][li][w + 1];
-                            uint4 o4;
-                            o4.x = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
-                            o4.y = f32_to_bf16_rne(v.z) | (f32_to_bf16_rne(v.w) << 16);
-                            o4.z = f32_to_bf16_rne(u.x) | (f32_to_bf16_rne(u.y) << 16);
-                            o4.w = f32_to_bf16_rne(u.z) | (f32_to_bf16_rne(u.w) << 16);
-                            static_cast<uint4*>(a.out)[rec * 4 + (w >> 1)] = o4;
-                        }
-                    } else {
-                        static_cast<float4*>(a.out)[rec * 8 + w] = v;
+                for (int it = 0; it < 4; ++it) {
+                    const int idx = it * kWave + ln;           // [tq][leaf][wo]
+                    const int tq = idx >> 6, li = (idx >> 2) & 15, wo = idx & 3;
+                    const int t = t0 + 4 * tq + r;
+                    if (t < a.n_t && li < n_valid) {
+                        const float4 v = L.out[wv][tq][li][(2 * wo) ^ (li & 7)];
+                        const float4 u = L.out[wv][tq][li][(2 * wo + 1) ^ (li & 7)];
+                        uint4 o4;
+                        o4.x = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
+                        o4.y = f32_to_bf16_rne(v.z) | (f32_to_bf16_rne(v.w) << 16);
+                        o4.z = f32_to_bf16_rne(u.x) | (f32_to_bf16_rne(u.y) << 16);
+                        o4.w = f32_to_bf16_rne(u.z) | (f32_to_bf16_rne(u.w) << 16);
+                        const int64_t rec = (int64_t)t * a.tree.stride + leaf0 + li;
+                        static_cast<uint4*>(a.out)[rec * 4 + wo] = o4;
+                    }
+                }
+            } else {
+                // 4 times x 16 leaves x 8 F32 words = 512 words: 8 per lane
+#pragma unroll
+                for (int it = 0; it < 8; ++it) {
+                    const int idx = it * kWave + ln;           // [tq][leaf][w]
+                    const int tq = idx >> 7, li = (idx >> 3) & 15, w = idx & 7;
+                    const int t = t0 + 4 * tq + r;
+                    if (t < a.n_t && li < n_valid) {
+                        const int64_t rec = (int64_t)t * a.tree.stride + leaf0 + li;
+                        static_cast<float4*>(a.out)[rec * 8 + w] = L.out[wv][tq][li][w ^ (li & 7)];
                     }
                 }
             }
@@ -247,10 +256,66 @@ __global__ __launch_bounds__(kBlock) void bake_kernel(BakeLaunch a)
     }
 }
 
+// Few time points (a per-frame decode): one thread per leaf, the 28 dot
+// products of Eq. 7 / Eq. 9 in FP32 FMAs, one output record per time.  With
+// n_t < 4 there is no dense contraction for the matrix cores to exploit; the
+// kernel streams the records in and the snapshots out.
+template <int DT, int OUT_BF16>
+__global__ __launch_bounds__(kBlock) void eval_times_kernel(TreeDev tree, const float* basis, int32_t n_t,
+                                                            int64_t n_leaves, void* out)
+{
+    constexpr int W = Pack<DT>::W;
+    constexpr int R = Pack<DT>::R;
+    constexpr int kWords = (FPO_N_COEFF + W - 1) / W;
+    const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n_leaves) return;
+    float k[kWords * W];
+    const uint4* rec = tree.recs + l * R;
+#pragma unroll
+    for (int g = 0; g < kWords; ++g) Pack<DT>::unpack(rec[g], k + g * W);
+    const float s = (DT == FPO_F32) ? 1.0f : tree.scale[l];
+    for (int t = 0; t < n_t; ++t) {
+        const float* b = basis + (int64_t)t * FPO_BASIS_STRIDE;
+        float v[32];
+        float sg = 0.0f;
+#pragma unroll
+        for (int i = 0; i < FPO_N_SIGMA; ++i) sg = fmaf(k[i], b[i], sg);
+        v[0] = sg * s;
+#pragma unroll
+        for (int m = 0; m < FPO_N_BAKED - 1; ++m) {
+            float z = 0.0f;
+#pragma unroll
+            for (int i = 0; i < FPO_N_SH_FOURIER; ++i) z = fmaf(k[FPO_N_SIGMA + FPO_N_SH_FOURIER * m + i], b[i], z);
+            v[1 + m] = z * s;
+        }
+        v[28] = v[29] = v[30] = v[31] = 0.0f;
+        const int64_t r = (int64_t)t * tree.stride + l;
+        if (OUT_BF16) {
+            uint4* o = static_cast<uint4*>(out) + r * 4;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                uint32_t u[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    u[e] = f32_to_bf16_rne(v[8 * w + 2 * e]) | (f32_to_bf16_rne(v[8 * w + 2 * e + 1]) << 16);
+                o[w] = make_uint4(u[0], u[1], u[2], u[3]);
+            }
+        } else {
+            float4* o = static_cast<float4*>(out) + r * 8;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) o[w] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+        }
+    }
+}
+
 }  // namespace dev
 }  // namespace fpo
 
 using namespace fpo;
+
+// Below this many time points the contraction is a matrix-vector product and
+// the streaming FMA kernel is used; from here on the MFMA tiles pay off.
+static constexpr int32_t kMfmaMinTimes = 4;
 
 extern "C" fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride, fpo_dtype dtype,
                                    void* q_out, float* scale_out, void* stream)
@@ -292,6 +357,21 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
     a.n_leaves = tree->n_leaves;
     a.out = out;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n_t < kMfmaMinTimes) {
+        const dev::TreeDev td = dev::tree_dev(tree);
+        const int64_t g1 = (tree->n_leaves + dev::kBlock - 1) / dev::kBlock;
+#define FPO_EVAL(DT, BF)                                                                                   \
+    hipLaunchKernelGGL((dev::eval_times_kernel<DT, BF>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td,  \
+                       basis, n_t, tree->n_leaves, out)
+        const bool bf = out_dtype == FPO_BF16;
+        switch (tree->dtype) {
+            case FPO_F32: if (bf) FPO_EVAL(FPO_F32, 1); else FPO_EVAL(FPO_F32, 0); break;
+            case FPO_BF16: if (bf) FPO_EVAL(FPO_BF16, 1); else FPO_EVAL(FPO_BF16, 0); break;
+            default: if (bf) FPO_EVAL(FPO_FP8_E4M3, 1); else FPO_EVAL(FPO_FP8_E4M3, 0); break;
+        }
+#undef FPO_EVAL
+        return launch_status("fpo_bake_times");
+    }
     switch (tree->dtype) {
         case FPO_F32:
             hipLaunchKernelGGL(dev::bake_kernel<FPO_F32>, dim3((unsigned)grid), dim3(dev::kBlock), 0, s, a);

@@ -89,8 +89,11 @@ def test_quantised_render_c1(oracle_lib, dev, dtype, kind, min_db):
     assert db >= min_db
 
 
+@pytest.mark.parametrize("n_times", [2, 37])
 @pytest.mark.parametrize("store", [_lib.FPO_F32, _lib.FPO_BF16, _lib.FPO_FP8_E4M3])
-def test_bake_matches_oracle(oracle_lib, dev, store):
+def test_bake_matches_oracle(oracle_lib, dev, store, n_times):
+    """Few times (streaming FMA kernel) and many times (MFMA tiles, 37 = three
+    16-time tiles with a ragged last one)."""
     import torch
     dijk = synth.random_tree_leaves(9, 6, p_split=0.6)
     k = synth.gaussian_coeffs(len(dijk), seed=9)
@@ -102,9 +105,9 @@ def test_bake_matches_oracle(oracle_lib, dev, store):
         k_eff = codec.dequantize(codes, scale, kind)
     else:
         k_eff = k.astype(np.float64)
-    times = [i * 60.0 / 37 + 0.3 for i in range(37)]          # ragged: 3 tiles of 16 times
+    times = [i * 60.0 / n_times + 0.3 for i in range(n_times)]
     basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
-    note(f"fpo_bake_times store={store}")
+    note(f"fpo_bake_times store={store} n_t={n_times}")
     out32 = _lib.bake_times(tree, basis, _lib.FPO_F32)
     out16 = _lib.bake_times(tree, basis, _lib.FPO_BF16)
     torch.cuda.synchronize()
