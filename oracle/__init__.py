@@ -80,6 +80,9 @@ def lib():
                                      _P, _P, _P, ctypes.c_int64, _P, _P, _P]
         L.or_render_grad.restype = ctypes.c_int32
         L.or_bake.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(_Params), _P, ctypes.c_int32, _P]
+        L.or_ray_labels.argtypes = [ctypes.c_void_p, _P, ctypes.POINTER(_Params), _P, ctypes.c_int32,
+                                    _P, _P, _P, ctypes.c_int64, _P]
+        L.or_ray_labels.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -234,4 +237,20 @@ def bake(coeffs: np.ndarray, params: _Params, times: Sequence[float]) -> np.ndar
     times = np.ascontiguousarray(times, dtype=np.float64)
     out = np.zeros((len(times), 28, c.shape[0]))
     lib().or_bake(_ptr(c), c.shape[0], ctypes.byref(params), _ptr(times), len(times), _ptr(out))
+    return out
+
+
+def ray_labels(tree: OracleTree, coeffs: np.ndarray, params: _Params, times: Sequence[float],
+               o: np.ndarray, d: np.ndarray, t_idx: np.ndarray) -> np.ndarray:
+    """Proposal labels [n][3] = (hit, s_in, s_out) from the plain walk."""
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    t_idx = np.ascontiguousarray(t_idx, dtype=np.int32)
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    out = np.zeros((o.shape[0], 3))
+    st = lib().or_ray_labels(tree._h, _ptr(c), ctypes.byref(params), _ptr(times), len(times),
+                             _ptr(o), _ptr(d), _ptr(t_idx), o.shape[0], _ptr(out))
+    if st != 0:
+        raise MemoryError("oracle labels failed")
     return out

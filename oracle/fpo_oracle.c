@@ -594,3 +594,59 @@ void or_bake(const double* coeffs, int64_t n_leaves, const or_params* p,
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Proposal labels: hit = some composited segment has sigma_eff delta > 0;   */
+/* s_in / s_out = where the first such segment starts / the last composited  */
+/* such segment ends, as fractions of the ray's chord [t_in, t_out] through  */
+/* the unit cube.  Early termination uses the nominal threshold tau.         */
+/* labels: [n][3] (hit, s_in, s_out); s_in = s_out = 0 when there is no hit. */
+/* ------------------------------------------------------------------------ */
+int32_t or_ray_labels(const or_tree* tr, const double* coeffs, const or_params* p,
+                      const double* times, int32_t n_t, const double* o, const double* d_in,
+                      const int32_t* t_idx, int64_t n, double* labels)
+{
+    const int32_t nc = or_ncoeff(p);
+    const int32_t nb = p->n_sigma > p->n_sh_fourier ? p->n_sigma : p->n_sh_fourier;
+    const int64_t cap = 3 * ((int64_t)1 << tr->max_depth) + 8;
+    int64_t* sl = (int64_t*)malloc(sizeof(int64_t) * cap);
+    double* s0 = (double*)malloc(sizeof(double) * cap);
+    double* s1 = (double*)malloc(sizeof(double) * cap);
+    double* basis = (double*)malloc(sizeof(double) * (size_t)(n_t > 0 ? n_t : 1) * nb);
+    if (!sl || !s0 || !s1 || !basis) { free(sl); free(s0); free(s1); free(basis); return 5; }
+    for (int32_t t = 0; t < n_t; ++t) or_basis(times[t], p->period, nb, basis + (int64_t)t * nb);
+    for (int64_t r = 0; r < n; ++r) {
+        double d[3] = {d_in[3 * r], d_in[3 * r + 1], d_in[3 * r + 2]};
+        or_normalize(d);
+        double* lab = labels + 3 * r;
+        lab[0] = lab[1] = lab[2] = 0.0;
+        double t_in, t_out;
+        if (!or_slab(o + 3 * r, d, &t_in, &t_out)) continue;
+        const double* b = basis + (int64_t)t_idx[r] * nb;
+        const int64_t nseg = or_trace(tr, o + 3 * r, d, cap, sl, s0, s1);
+        double T = 1.0;
+        int hit = 0;
+        double first = 0.0, last = 0.0;
+        for (int64_t s = 0; s < nseg; ++s) {
+            double sraw, z[27];
+            or_leaf_values(p, coeffs + sl[s] * nc, b, NULL, sl[s], tr->n_leaves, &sraw, z);
+            const double sigma = p->sigma_scale * (sraw > 0.0 ? sraw : 0.0);
+            const double delta = s1[s] - s0[s];
+            if (sigma * delta > 0.0) {
+                if (!hit) first = s0[s];
+                hit = 1;
+                last = s1[s];
+            }
+            T *= exp(-sigma * delta);
+            if (p->stop_T > 0.0 && T < p->stop_T) break;
+        }
+        if (hit) {
+            const double len = t_out - t_in;
+            lab[0] = 1.0;
+            lab[1] = (first - t_in) / len;
+            lab[2] = (last - t_in) / len;
+        }
+    }
+    free(sl); free(s0); free(s1); free(basis);
+    return 0;
+}
