@@ -70,6 +70,20 @@ typedef enum { FPO_F32 = 0, FPO_BF16 = 1, FPO_FP8_E4M3 = 2 } fpo_dtype;
 #define FPO_BASIS_STRIDE 32     /* floats per row of a device basis table */
 #define FPO_MAX_DEPTH 10
 
+/* Learned proposal and coarse occupancy (not in the paper; see the proposal
+ * section below). */
+#define FPO_MLP_N_IN 7             /* entry point (3), unit direction (3), t / T mod 1 */
+#define FPO_MLP_N_PE 84            /* 7 inputs x 6 frequencies x (sin, cos) */
+#define FPO_MLP_HIDDEN 64
+#define FPO_MLP_N_OUT 3            /* hit logit, s_in logit, s_out logit */
+#define FPO_MLP_N_PARAMS 9795      /* [85][64] + [65][64] + [65][3], biases as last rows */
+#define FPO_MLP_N_PARAMS_PADDED 9796
+#define FPO_MLP_PACKED_BYTES 23056 /* FP16 matrix-core fragments + FP32 biases */
+#define FPO_COARSE_RES 64
+#define FPO_COARSE_WORDS 8192      /* 64^3 bits */
+#define FPO_RENDER_SKIP_COARSE 1   /* fpo_render_opts.flags */
+#define FPO_RENDER_SKIP_PROPOSAL 2
+
 /* Fourier / SH sizes, period and density scale.  Only (31, 5, 2) is compiled. */
 typedef struct {
     int32_t n_sigma;       /* n1 = 31 */
@@ -117,7 +131,25 @@ typedef struct {
     fpo_dtype snapshot_dtype; /* FPO_F32 or FPO_BF16 */
     int64_t snapshot_cam_stride; /* leaf records between consecutive cameras' (or time
                                     indices') snapshots; 0: all share one */
-    int32_t flags;            /* reserved, 0 */
+    int32_t flags;            /* 0: plain traversal.  fpo_render only:
+                                 FPO_RENDER_SKIP_COARSE: each ray walks the octree only
+                                 between the first and last set cells of coarse_bits on
+                                 its chord;
+                                 FPO_RENDER_SKIP_PROPOSAL: the proposal network predicts
+                                 the first entry and last exit; the skipped prefix is
+                                 checked against coarse_bits before the walk (the walk
+                                 starts at the first set cell if the check fails), and the
+                                 skipped suffix is checked when the walk reaches it (the
+                                 walk goes on to the last set cell if that check fails).
+                                 Either way the image equals the plain render up to FP32
+                                 rounding of the segment ends. */
+    const uint32_t* coarse_bits; /* device [FPO_COARSE_WORDS] from fpo_coarse_occupancy of
+                                    this tree (skip modes) */
+    const void* proposal;     /* device FPO_MLP_PACKED_BYTES from fpo_mlp_pack
+                                 (FPO_RENDER_SKIP_PROPOSAL) */
+    void* workspace;          /* device scratch for skip modes, 8-byte aligned, at least
+                                 min(n_cams, 16) * W * H * 8 bytes */
+    int64_t workspace_bytes;
 } fpo_render_opts;
 
 /* ---------------------------------------------------------------------- */
@@ -265,6 +297,74 @@ fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stri
  *           fpo_render / fpo_render_rays with snapshot_cam_stride = leaf_stride. */
 fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t, fpo_dtype out_dtype,
                           void* out, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Learned proposal (not in the paper)                                      */
+/* ---------------------------------------------------------------------- */
+/* A small MLP predicts, per ray and time, whether the ray meets a
+ * contributing leaf and where the contributing part of its chord begins and
+ * ends; rays use it to skip empty space (fpo_render_opts.flags).  Every skip
+ * is checked against a dilated coarse occupancy grid, so the image does not
+ * depend on how good the prediction is, only the speed.
+ *
+ * Network: inputs x = (entry point into the unit cube, unit direction,
+ * t / T mod 1); positional encoding (sin 2^f pi x_c, cos 2^f pi x_c), f < 6,
+ * feature 12 c + 2 f + {0 sin, 1 cos}; 84 -> 64 -> 64 -> 3, ReLU on the hidden
+ * layers.  Parameters: FP32 [85][64], [65][64], [65][3] matrices laid end to
+ * end (input index major, bias as the last row), FPO_MLP_N_PARAMS floats
+ * (allocate FPO_MLP_N_PARAMS_PADDED for fpo_adam_step).  Training runs in
+ * FP32; inference uses FP16 weights and activations with FP32 accumulation
+ * on the matrix cores. */
+
+/* Coarse occupancy of a tree: bit (z * 64 + y) * 64 + x of bits_out is set
+ * iff a leaf overlaps coarse cell (x, y, z) of the 64^3 grid or one of its 26
+ * neighbours.  Host call; arguments as for fpo_build_tree.
+ *   bits_out host [FPO_COARSE_WORDS] uint32. */
+fpo_status fpo_coarse_occupancy(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
+                                uint32_t* bits_out);
+
+/* Training labels from the plain walk at each ray's time, with the early
+ * termination of opts->stop_T: hit = 1 if some segment has sigma_eff * delta
+ * > 0 before the walk stops; s_in / s_out = entry of the first and exit of
+ * the last such segment, as distances from the cube entry divided by the
+ * chord length in the cube (0 when hit = 0).  Also writes the network inputs.
+ *   o, d, t_idx, basis, n_t, n_rays: as for fpo_render_rays (Fourier mode).
+ *   tau      device [n_t] F32, t / T mod 1 of each basis row.
+ *   labels   device [n_rays][3] F32 (hit, s_in, s_out).
+ *   inputs   device [n_rays][FPO_MLP_N_IN] F32; a ray that misses the cube
+ *            gets its origin as entry point. */
+fpo_status fpo_ray_labels(const fpo_tree_view* tree, const float* o, const float* d, const int32_t* t_idx,
+                          const float* basis, const float* tau, int32_t n_t, int64_t n_rays,
+                          const fpo_render_opts* opts, float* labels, float* inputs, void* stream);
+
+/* FP32 forward pass (training precision).
+ *   params device [FPO_MLP_N_PARAMS] F32; inputs device [n][7]; out device [n][3]. */
+fpo_status fpo_mlp_forward(const float* params, const float* inputs, int64_t n, float* out, void* stream);
+
+/* Floats of workspace fpo_mlp_loss_grad needs for a batch of n rays. */
+int64_t fpo_mlp_workspace_floats(int64_t n);
+
+/* Loss and gradient of a batch, in FP32.  Per ray: binary cross-entropy of
+ * the hit logit against labels[.][0]; if labels[.][0] > 0.5, pinball losses
+ * rho_q(y - sigmoid(o)) = (y - sigmoid(o)) (q - [y < sigmoid(o)]) with
+ * q = 0.1 on s_in and q = 0.9 on s_out.  The batch loss is the mean over rays.
+ *   inputs, labels device [N][7], [N][3]; idx device [n] int32 rows of the
+ *            batch, or NULL for rows 0..n-1.
+ *   workspace device, fpo_mlp_workspace_floats(n) floats, 16-byte aligned.
+ *   grad     device [FPO_MLP_N_PARAMS] F32, gradients ADDED.
+ *   loss     device [1] F32, batch loss ADDED.
+ * Deterministic: fixed reduction order, no atomics. */
+fpo_status fpo_mlp_loss_grad(const float* params, const float* inputs, const float* labels, const int32_t* idx,
+                             int64_t n, float* workspace, float* grad, float* loss, void* stream);
+
+/* Inference weights from the FP32 parameters: FP16 (round to nearest even)
+ * matrix-core fragments and FP32 biases.
+ *   packed_out device FPO_MLP_PACKED_BYTES, 16-byte aligned. */
+fpo_status fpo_mlp_pack(const float* params, void* packed_out, void* stream);
+
+/* Inference as used inside fpo_render (FP16 weights and activations, FP32
+ * accumulation).  inputs device [n][7]; out device [n][3] logits. */
+fpo_status fpo_mlp_infer(const void* packed, const float* inputs, int64_t n, float* out, void* stream);
 
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* fpo_last_error(void);

@@ -118,3 +118,48 @@ def ray_inputs(o: np.ndarray, d: np.ndarray, t: np.ndarray, period: float = 60.0
     e = o + t_in[:, None] * d
     tau = np.mod(np.asarray(t, dtype=np.float64) / period, 1.0)
     return np.concatenate([e, d, tau[:, None]], axis=1)
+
+
+# Flat parameter vector: [85][64], [65][64], [65][3] row-major matrices end to
+# end (input index major), the last row of each the layer's bias.
+N_PARAMS = (N_PE + 1) * HIDDEN + (HIDDEN + 1) * HIDDEN + (HIDDEN + 1) * N_OUT   # 9795
+
+
+def to_flat(w) -> np.ndarray:
+    parts = [np.vstack([w["W1"], w["b1"][None]]), np.vstack([w["W2"], w["b2"][None]]),
+             np.vstack([w["W3"], w["b3"][None]])]
+    return np.concatenate([p.ravel() for p in parts])
+
+
+def from_flat(p: np.ndarray):
+    p = np.asarray(p, dtype=np.float64)
+    a = (N_PE + 1) * HIDDEN
+    b = a + (HIDDEN + 1) * HIDDEN
+    L1 = p[:a].reshape(N_PE + 1, HIDDEN)
+    L2 = p[a:b].reshape(HIDDEN + 1, HIDDEN)
+    L3 = p[b:b + (HIDDEN + 1) * N_OUT].reshape(HIDDEN + 1, N_OUT)
+    return {"W1": L1[:-1].copy(), "b1": L1[-1].copy(), "W2": L2[:-1].copy(), "b2": L2[-1].copy(),
+            "W3": L3[:-1].copy(), "b3": L3[-1].copy()}
+
+
+def _f16(x):
+    return np.asarray(x, dtype=np.float16).astype(np.float64)
+
+
+def forward_fp16(w, inputs: np.ndarray):
+    """Inference-precision forward: FP16 weights (round to nearest even), FP16
+    layer inputs (the encoding and each hidden activation after ReLU), biases
+    as given, exact accumulation."""
+    g = _f16(encode(inputs))
+    a1 = _f16(np.maximum(g @ _f16(w["W1"]) + w["b1"], 0.0))
+    a2 = _f16(np.maximum(a1 @ _f16(w["W2"]) + w["b2"], 0.0))
+    return a2 @ _f16(w["W3"]) + w["b3"]
+
+
+def magnitude(w, inputs: np.ndarray) -> np.ndarray:
+    """Per-output scale sum |terms| propagated through the layers with
+    absolute weights: the quantity FP rounding errors are proportional to."""
+    g = np.abs(encode(inputs))
+    m1 = g @ np.abs(w["W1"]) + np.abs(w["b1"])
+    m2 = m1 @ np.abs(w["W2"]) + np.abs(w["b2"])
+    return m2 @ np.abs(w["W3"]) + np.abs(w["b3"])

@@ -64,7 +64,9 @@ class CameraC(ctypes.Structure):
 class RenderOpts(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_float * 3), ("stop_T", ctypes.c_float),
                 ("snapshot", ctypes.c_void_p), ("snapshot_dtype", ctypes.c_int),
-                ("snapshot_cam_stride", ctypes.c_int64), ("flags", ctypes.c_int32)]
+                ("snapshot_cam_stride", ctypes.c_int64), ("flags", ctypes.c_int32),
+                ("coarse_bits", ctypes.c_void_p), ("proposal", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -91,7 +93,16 @@ _SIGS = {
                       ctypes.c_float, _I32, _P],
     "fpo_quantize": [_P, _I64, _I64, ctypes.c_int, _P, _P, _P],
     "fpo_bake_times": [ctypes.POINTER(TreeView), _P, _I32, ctypes.c_int, _P, _P],
+    "fpo_coarse_occupancy": [_P, _I64, _I32, _P],
+    "fpo_ray_labels": [ctypes.POINTER(TreeView), _P, _P, _P, _P, _P, _I32, _I64,
+                       ctypes.POINTER(RenderOpts), _P, _P, _P],
+    "fpo_mlp_forward": [_P, _P, _I64, _P, _P],
+    "fpo_mlp_loss_grad": [_P, _P, _P, _P, _I64, _P, _P, _P, _P],
+    "fpo_mlp_pack": [_P, _P, _P],
+    "fpo_mlp_infer": [_P, _P, _I64, _P, _P],
 }
+# functions with another return type
+_OTHER = {"fpo_mlp_workspace_floats": ([_I64], ctypes.c_int64)}
 
 
 def lib():
@@ -105,6 +116,10 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        for name, (args, res) in _OTHER.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
         L.fpo_last_error.argtypes = []
         L.fpo_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -112,7 +127,7 @@ def lib():
 
 
 def exported_symbols() -> Sequence[str]:
-    return list(_SIGS) + ["fpo_last_error"]
+    return list(_SIGS) + list(_OTHER) + ["fpo_last_error"]
 
 
 def _check(st: int):
@@ -151,15 +166,27 @@ def camera_struct(cams) -> ctypes.Array:
 
 
 def make_opts(bg=(0.0, 0.0, 0.0), stop_T: float = 0.0, snapshot=None, snapshot_dtype: int = FPO_F32,
-              snapshot_cam_stride: int = 0) -> RenderOpts:
+              snapshot_cam_stride: int = 0, flags: int = 0, coarse_bits=None, proposal=None,
+              workspace=None) -> RenderOpts:
+    """Render options.  Tensors passed here must outlive every call using them."""
     o = RenderOpts()
     o.bg[:] = [float(v) for v in bg]
     o.stop_T = float(stop_T)
     o.snapshot = None if snapshot is None else snapshot.data_ptr()
     o.snapshot_dtype = int(snapshot_dtype)
     o.snapshot_cam_stride = int(snapshot_cam_stride)
-    o.flags = 0
+    o.flags = int(flags)
+    o.coarse_bits = None if coarse_bits is None else coarse_bits.data_ptr()
+    o.proposal = None if proposal is None else proposal.data_ptr()
+    o.workspace = None if workspace is None else workspace.data_ptr()
+    o.workspace_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     return o
+
+
+def skip_workspace(n_cams: int, height: int, width: int, device):
+    """Scratch for the skip modes of fpo_render."""
+    import torch
+    return torch.empty((min(n_cams, 16) * height * width * 2,), dtype=torch.float32, device=device)
 
 
 # ---------------------------------------------------------------------------
@@ -366,4 +393,73 @@ def bake_times(tree: DeviceTree, basis, out_dtype: int = FPO_F32, out=None):
         out = torch.empty((n_t, tree.leaf_stride, SNAP_VALUES), dtype=dt, device=basis.device)
     tv = tree.view()
     _check(lib().fpo_bake_times(ctypes.byref(tv), _t_ptr(basis), n_t, int(out_dtype), _t_ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# learned proposal
+# ---------------------------------------------------------------------------
+MLP_N_IN = 7
+FPO_RENDER_SKIP_COARSE = 1
+FPO_RENDER_SKIP_PROPOSAL = 2
+MLP_N_PARAMS = 9795
+MLP_N_PARAMS_PADDED = 9796
+MLP_PACKED_BYTES = 23056
+COARSE_WORDS = 8192
+
+
+def coarse_occupancy(leaf_dijk: np.ndarray, max_depth: int) -> np.ndarray:
+    """fpo_coarse_occupancy -> uint32 [8192] (host)."""
+    dijk = np.ascontiguousarray(leaf_dijk, dtype=np.int32)
+    bits = np.zeros(COARSE_WORDS, np.uint32)
+    _check(lib().fpo_coarse_occupancy(_np_ptr(dijk), int(dijk.shape[0]), int(max_depth), _np_ptr(bits)))
+    return bits
+
+
+def ray_labels(tree: DeviceTree, o, d, t_idx, basis, tau, opts: Optional[RenderOpts] = None):
+    """fpo_ray_labels -> (labels [n][3], inputs [n][7])."""
+    import torch
+    opts = opts or make_opts()
+    n = int(o.shape[0])
+    labels = torch.empty((n, 3), dtype=torch.float32, device=o.device)
+    inputs = torch.empty((n, MLP_N_IN), dtype=torch.float32, device=o.device)
+    tv = tree.view()
+    _check(lib().fpo_ray_labels(ctypes.byref(tv), _t_ptr(o), _t_ptr(d), _t_ptr(t_idx), _t_ptr(basis), _t_ptr(tau),
+                                int(basis.shape[0]), n, ctypes.byref(opts), _t_ptr(labels), _t_ptr(inputs),
+                                _stream()))
+    return labels, inputs
+
+
+def mlp_forward(params, inputs, out=None):
+    import torch
+    n = int(inputs.shape[0])
+    out = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=inputs.device)
+    _check(lib().fpo_mlp_forward(_t_ptr(params), _t_ptr(inputs), n, _t_ptr(out), _stream()))
+    return out
+
+
+def mlp_workspace(n: int, device):
+    import torch
+    return torch.empty((int(lib().fpo_mlp_workspace_floats(int(n))),), dtype=torch.float32, device=device)
+
+
+def mlp_loss_grad(params, inputs, labels, grad, loss, workspace, idx=None, n: Optional[int] = None):
+    """fpo_mlp_loss_grad: adds the batch gradient into grad and the loss into loss[0]."""
+    n = int(idx.numel()) if idx is not None else (int(n) if n is not None else int(inputs.shape[0]))
+    _check(lib().fpo_mlp_loss_grad(_t_ptr(params), _t_ptr(inputs), _t_ptr(labels), _t_ptr(idx), n,
+                                   _t_ptr(workspace), _t_ptr(grad), _t_ptr(loss), _stream()))
+
+
+def mlp_pack(params, out=None):
+    import torch
+    out = out if out is not None else torch.empty((MLP_PACKED_BYTES,), dtype=torch.uint8, device=params.device)
+    _check(lib().fpo_mlp_pack(_t_ptr(params), _t_ptr(out), _stream()))
+    return out
+
+
+def mlp_infer(packed, inputs, out=None):
+    import torch
+    n = int(inputs.shape[0])
+    out = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=inputs.device)
+    _check(lib().fpo_mlp_infer(_t_ptr(packed), _t_ptr(inputs), n, _t_ptr(out), _stream()))
     return out

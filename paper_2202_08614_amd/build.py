@@ -21,6 +21,7 @@ SOURCES = [
     "fpo_render.hip",
     "fpo_train.hip",
     "fpo_bake.hip",
+    "fpo_proposal.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -180,10 +180,27 @@ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx, float d
 // walk is monotone and ends within 3G steps).  Exit-axis ties break x < y < z.
 //
 // Visitor: bool segment(int leaf, float t0, float t1) returns true to stop.
-// Distances are measured from the entry point r.o.
+// Distances are measured from the entry point r.o.  With a stop distance
+// t_end the walk consults stop.more() once a step ends at or past t_end.
 // --------------------------------------------------------------------------
+// Stop hook of the walk: called when a step's exit distance reaches t_end;
+// returns true (after possibly raising t_end) to keep walking.
+struct NoStop {
+    __device__ inline bool more(float, float&) { return false; }
+};
+
+template <class Visitor, class Stop>
+__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop);
+
 template <class Visitor>
 __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
+{
+    NoStop ns;
+    walk(T, r, stk, vis, __builtin_inff(), ns);
+}
+
+template <class Visitor, class Stop>
+__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop)
 {
     const int D = T.max_depth;
     const int G = 1 << D;
@@ -236,6 +253,7 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
             const int leaf = -ch - 1;
             if (leaf < T.n_leaves && vis.segment(leaf, t_cur, t_exit)) return;
         }
+        if (t_exit >= t_end && !stop.more(t_exit, t_end)) return;
         int nc[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {

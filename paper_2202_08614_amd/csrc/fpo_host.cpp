@@ -58,13 +58,24 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs)
     return FPO_OK;
 }
 
-fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree)
+fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip)
 {
     if (!opts) return fail(FPO_E_INVALID, "opts is NULL");
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(opts->bg[c])) return fail(FPO_E_INVALID, "opts->bg must be finite");
     if (!(opts->stop_T >= 0.0f && opts->stop_T < 1.0f)) return fail(FPO_E_INVALID, "opts->stop_T must be in [0, 1)");
-    if (opts->flags != 0) return fail(FPO_E_INVALID, "opts->flags must be 0");
+    if (opts->flags != 0) {
+        if (!allow_skip) return fail(FPO_E_INVALID, "opts->flags must be 0 for this call");
+        if (opts->flags != FPO_RENDER_SKIP_COARSE && opts->flags != FPO_RENDER_SKIP_PROPOSAL)
+            return fail(FPO_E_INVALID, "opts->flags must be 0, FPO_RENDER_SKIP_COARSE or FPO_RENDER_SKIP_PROPOSAL");
+        if (!opts->coarse_bits) return fail(FPO_E_INVALID, "skip modes need opts->coarse_bits");
+        if (opts->flags == FPO_RENDER_SKIP_PROPOSAL && !opts->proposal)
+            return fail(FPO_E_INVALID, "FPO_RENDER_SKIP_PROPOSAL needs opts->proposal");
+        if (!opts->workspace || (reinterpret_cast<uintptr_t>(opts->workspace) & 7) != 0)
+            return fail(FPO_E_INVALID, "skip modes need an 8-byte aligned opts->workspace");
+        if ((reinterpret_cast<uintptr_t>(opts->proposal) & 15) != 0)
+            return fail(FPO_E_INVALID, "opts->proposal must be 16-byte aligned");
+    }
     if (opts->snapshot) {
         if (opts->snapshot_dtype != FPO_F32 && opts->snapshot_dtype != FPO_BF16)
             return fail(FPO_E_INVALID, "snapshot_dtype must be F32 or BF16");
@@ -218,6 +229,59 @@ extern "C" fpo_status fpo_build_tree(const int32_t* leaf_dijk, int64_t n_leaves,
     } catch (const std::bad_alloc&) {
         return fail(FPO_E_INVALID, "out of host memory");
     }
+}
+
+extern "C" fpo_status fpo_coarse_occupancy(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
+                                           uint32_t* bits_out)
+{
+    if (!leaf_dijk || !bits_out) return fail(FPO_E_INVALID, "NULL argument");
+    if (n_leaves < 1) return fail(FPO_E_INVALID, "n_leaves must be >= 1");
+    if (max_depth < 1 || max_depth > FPO_MAX_DEPTH) return fail(FPO_E_INVALID, "max_depth must be in 1..10");
+    constexpr int N = FPO_COARSE_RES;   // 2^6 cells per axis
+    constexpr int kLog = 6;
+    for (int64_t l = 0; l < n_leaves; ++l) {
+        const int32_t d = leaf_dijk[4 * l];
+        if (d < 1 || d > max_depth) return fail(FPO_E_INVALID, "leaf " + std::to_string(l) + ": depth out of range");
+        const int64_t g = int64_t(1) << d;
+        for (int a = 1; a <= 3; ++a)
+            if (leaf_dijk[4 * l + a] < 0 || leaf_dijk[4 * l + a] >= g)
+                return fail(FPO_E_INVALID, "leaf " + std::to_string(l) + ": coordinate out of range");
+    }
+    std::vector<uint8_t> occ((size_t)N * N * N, 0);
+    for (int64_t l = 0; l < n_leaves; ++l) {
+        const int d = leaf_dijk[4 * l];
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t v = leaf_dijk[4 * l + 1 + a];
+            if (d >= kLog) {
+                lo[a] = hi[a] = (int)(v >> (d - kLog));
+            } else {
+                lo[a] = (int)(v << (kLog - d));
+                hi[a] = lo[a] + (1 << (kLog - d)) - 1;
+            }
+        }
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) occ[((size_t)z * N + y) * N + x] = 1;
+    }
+    std::memset(bits_out, 0, sizeof(uint32_t) * FPO_COARSE_WORDS);
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                bool any = false;
+                for (int dz = -1; dz <= 1 && !any; ++dz)
+                    for (int dy = -1; dy <= 1 && !any; ++dy)
+                        for (int dx = -1; dx <= 1 && !any; ++dx) {
+                            const int X = x + dx, Y = y + dy, Z = z + dz;
+                            if (X < 0 || Y < 0 || Z < 0 || X >= N || Y >= N || Z >= N) continue;
+                            any = occ[((size_t)Z * N + Y) * N + X] != 0;
+                        }
+                if (any) {
+                    const int idx = (z * N + y) * N + x;
+                    bits_out[idx >> 5] |= 1u << (idx & 31);
+                }
+            }
+    return FPO_OK;
 }
 
 extern "C" fpo_status fpo_time_basis(const double* times, int32_t n_t, const fpo_layout* layout, float* basis_out)

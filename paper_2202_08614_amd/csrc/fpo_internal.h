@@ -22,7 +22,8 @@ inline int n_planes(fpo_dtype dt)
 
 // Validate a tree view (host-visible fields only).
 fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs);
-fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree);
+// allow_skip: the call accepts the skip flags (fpo_render only).
+fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip = false);
 
 // Camera frame in FP64, rounded to FP32: eye, unit forward, right * tan_x, up' * tan_y.
 fpo_status camera_frame(const fpo_camera& cam, float out[12]);

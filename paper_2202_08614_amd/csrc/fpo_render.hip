@@ -8,12 +8,15 @@
 // the same leaves, share one L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 
 #include "fpo.h"
 #include "fpo_device.h"
 #include "fpo_internal.h"
+#include "fpo_proposal.h"
 
 namespace fpo {
 namespace dev {
@@ -31,11 +34,23 @@ struct CamLaunch {
     CamDev cam[kCamsPerLaunch];
     float* rgb;                      // [n_cams][H][W][3] of this launch
     float* Tout;                     // [n_cams][H][W] or null
+    const float2* skip;              // skip modes: [n_cams][H][W] (t_start, t_end) from the cube entry
+    const uint32_t* bits;            // coarse occupancy (suffix checks)
     int32_t W, H, bx_per_cam, blocks_per_cam, n_cams;
     float bg[3];
     float stop_T;
 };
 static_assert(sizeof(CamLaunch) <= 4096, "kernel argument block too large");
+
+// Skip pre-pass: per pixel, the part of the chord the render has to walk.
+struct SkipLaunch {
+    float frame[kCamsPerLaunch][12];
+    float tau[kCamsPerLaunch];       // t / T mod 1 of each camera
+    const uint32_t* bits;
+    const unsigned char* packed;     // proposal weights (MLP variant)
+    float2* skip;                    // [n_cams][H][W]
+    int32_t W, H, bx_per_cam, blocks_per_cam, n_cams;
+};
 
 // Block index -> logical tile, giving XCD x (blocks x, x+8, ...) the
 // contiguous range [x * per, (x + 1) * per).  gridDim.x is a multiple of 8.
@@ -45,7 +60,72 @@ __device__ inline int xcd_band(int bid, int nblocks)
     return (bid & 7) * per + (bid >> 3);
 }
 
-template <int MODE>
+// Skip pre-pass.  Coarse variant: the walk runs from the first to the last
+// set coarse cell on the chord (both found by scans, so both are proven).
+// Proposal variant: the MLP's entry guess is accepted if the coarse scan up to
+// it is clear, else the walk starts at the first set cell the scan met; a
+// predicted miss is accepted only if the whole chord is clear.  The predicted
+// exit is checked by the render when its walk gets there (VerifyTail).
+// (inf, inf) marks a ray with nothing to walk.
+template <bool MLP>
+__global__ __launch_bounds__(kBlock) void skip_prepass_kernel(SkipLaunch a)
+{
+    const int lin = xcd_band(blockIdx.x, gridDim.x);
+    if (lin >= a.n_cams * a.blocks_per_cam) return;   // whole blocks: every wave stays complete
+    const int ci = lin / a.blocks_per_cam;
+    const int tb = lin - ci * a.blocks_per_cam;
+    const int bx = tb % a.bx_per_cam;
+    const int by = tb / a.bx_per_cam;
+    const int wv = threadIdx.x >> 6;
+    const int ln = threadIdx.x & 63;
+    const int px = bx * 16 + (wv & 1) * 8 + (ln & 7);
+    const int py = by * 16 + (wv >> 1) * 8 + (ln >> 3);
+    const bool inside = px < a.W && py < a.H;
+    const float* fr = a.frame[ci];
+    const float sx = (float)(2 * px + 1 - a.W) / (float)a.W;
+    const float sy = (float)(a.H - 2 * py - 1) / (float)a.H;
+    const float dx = fr[3] + sx * fr[6] + sy * fr[9];
+    const float dy = fr[4] + sx * fr[7] + sy * fr[10];
+    const float dz = fr[5] + sx * fr[8] + sy * fr[11];
+    Ray r;
+    const bool ok = setup_ray(fr[0], fr[1], fr[2], dx, dy, dz, r) && inside;
+    float ts = __builtin_inff(), te = __builtin_inff();
+    float o3[3] = {0.0f, 0.0f, 0.0f};
+    if constexpr (MLP) {
+        float x[kMlpIn];
+        proposal_inputs(r, a.tau[ci], x);
+        if (!ok)
+            for (int c = 0; c < kMlpIn; ++c) x[c] = 0.0f;
+        mlp_infer_wave(a.packed, x, o3);     // wave-wide: every lane is still active here
+    }
+    if (ok) {
+        const float len = r.t_len;
+        if (!MLP || !(o3[0] > 0.0f)) {
+            const float f = coarse_scan(a.bits, r.o, r.d, len);
+            if (f < len) {
+                ts = f;
+                te = len;
+                if (!MLP) {
+                    float pe[3], nd[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        pe[c] = fmaf(len, r.d[c], r.o[c]);
+                        nd[c] = -r.d[c];
+                    }
+                    te = len - coarse_scan(a.bits, pe, nd, len - f);
+                }
+            }
+        } else {
+            const float s_in = sigmoidf_(o3[1]);
+            const float s_out = sigmoidf_(o3[2]);
+            ts = coarse_scan(a.bits, r.o, r.d, s_in * len);
+            te = fmaxf(s_out * len, ts);
+        }
+    }
+    if (inside) a.skip[((int64_t)ci * a.H + py) * a.W + px] = make_float2(ts, te);
+}
+
+template <int MODE, int SKIP>
 __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
 {
     __shared__ int s_stack[kStackLevels * kBlock];
@@ -77,11 +157,27 @@ __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
     sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
     sh.stop_T = a.stop_T;
     Ray r;
+    const int64_t pix = ((int64_t)ci * a.H + py) * a.W + px;
     if (setup_ray(cam.frame[0], cam.frame[1], cam.frame[2], dx, dy, dz, r)) {
         sh9(r.d[0], r.d[1], r.d[2], sh.Y);
-        walk(a.tree, r, s_stack + threadIdx.x, sh);
+        if constexpr (SKIP == 0) {
+            walk(a.tree, r, s_stack + threadIdx.x, sh);
+        } else {
+            const float2 se = a.skip[pix];
+            if (se.x < r.t_len) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r.o[c] = fmaf(se.x, r.d[c], r.o[c]);
+                r.t_len -= se.x;
+                if constexpr (SKIP == FPO_RENDER_SKIP_COARSE) {
+                    NoStop ns;
+                    walk(a.tree, r, s_stack + threadIdx.x, sh, se.y - se.x, ns);
+                } else {
+                    VerifyTail vt{a.bits, r, false};
+                    walk(a.tree, r, s_stack + threadIdx.x, sh, se.y - se.x, vt);
+                }
+            }
+        }
     }
-    const int64_t pix = ((int64_t)ci * a.H + py) * a.W + px;
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.rgb[pix * 3 + c] = fmaf(sh.Tr, a.bg[c], sh.C[c]);
     if (a.Tout) a.Tout[pix] = sh.Tr;
@@ -247,9 +343,14 @@ static int mode_of(const fpo_tree_view* t, const fpo_render_opts* o)
 using namespace fpo;
 
 template <int MODE>
-static void launch_cam(const dev::CamLaunch& a, int grid, hipStream_t s)
+static void launch_cam(const dev::CamLaunch& a, int grid, int skip, hipStream_t s)
 {
-    hipLaunchKernelGGL(dev::render_cam_kernel<MODE>, dim3(grid), dim3(dev::kBlock), 0, s, a);
+    if (skip == FPO_RENDER_SKIP_COARSE)
+        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, FPO_RENDER_SKIP_COARSE>), dim3(grid), dim3(dev::kBlock), 0, s, a);
+    else if (skip == FPO_RENDER_SKIP_PROPOSAL)
+        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, FPO_RENDER_SKIP_PROPOSAL>), dim3(grid), dim3(dev::kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, 0>), dim3(grid), dim3(dev::kBlock), 0, s, a);
 }
 
 extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
@@ -257,7 +358,7 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
 {
     fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr);
     if (st != FPO_OK) return st;
-    if ((st = check_opts(opts, tree)) != FPO_OK) return st;
+    if ((st = check_opts(opts, tree, true)) != FPO_OK) return st;
     if (!cams || n_cams < 1) return fail(FPO_E_INVALID, "cams is NULL or n_cams < 1");
     if (!rgb_out) return fail(FPO_E_INVALID, "rgb_out is NULL");
     const int W = cams[0].width, H = cams[0].height;
@@ -265,8 +366,15 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
         if (cams[i].width != W || cams[i].height != H)
             return fail(FPO_E_INVALID, "all cameras of one call must share width and height");
     if ((int64_t)W * H > (1ll << 30)) return fail(FPO_E_INVALID, "image too large");
+    const int skip = opts->flags;
+    if (skip != 0) {
+        const int64_t need = (int64_t)std::min(n_cams, dev::kCamsPerLaunch) * W * H * 8;
+        if (opts->workspace_bytes < need)
+            return fail(FPO_E_INVALID, "opts->workspace_bytes < min(n_cams, 16) * W * H * 8");
+    }
     // Validate every camera before launching anything.
     static thread_local dev::CamLaunch a;
+    static thread_local dev::SkipLaunch sk;
     std::memset(&a, 0, sizeof(a));
     for (int i = 0; i < n_cams; ++i) {
         float fr[12];
@@ -298,12 +406,36 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
         const int64_t total = (int64_t)nc * a.blocks_per_cam;
         if (total > INT32_MAX - 8) return fail(FPO_E_INVALID, "launch too large");
         const int grid = (int)((total + 7) / 8 * 8);
+        if (skip != 0) {
+            sk.n_cams = nc;
+            sk.W = W;
+            sk.H = H;
+            sk.bx_per_cam = a.bx_per_cam;
+            sk.blocks_per_cam = a.blocks_per_cam;
+            for (int i = 0; i < nc; ++i) {
+                for (int q = 0; q < 12; ++q) sk.frame[i][q] = a.cam[i].frame[q];
+                const double per = (double)tree->layout.period;
+                double tau = std::fmod(cams[c0 + i].time / per, 1.0);
+                if (tau < 0.0) tau += 1.0;
+                sk.tau[i] = (float)tau;
+            }
+            sk.bits = opts->coarse_bits;
+            sk.packed = static_cast<const unsigned char*>(opts->proposal);
+            sk.skip = static_cast<float2*>(opts->workspace);
+            a.skip = sk.skip;
+            a.bits = opts->coarse_bits;
+            if (skip == FPO_RENDER_SKIP_PROPOSAL)
+                hipLaunchKernelGGL(dev::skip_prepass_kernel<true>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
+            else
+                hipLaunchKernelGGL(dev::skip_prepass_kernel<false>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
+            if ((st = launch_status("fpo_render (skip pre-pass)")) != FPO_OK) return st;
+        }
         switch (mode) {
-            case FPO_F32: launch_cam<FPO_F32>(a, grid, s); break;
-            case FPO_BF16: launch_cam<FPO_BF16>(a, grid, s); break;
-            case FPO_FP8_E4M3: launch_cam<FPO_FP8_E4M3>(a, grid, s); break;
-            case dev::kSnapF32: launch_cam<dev::kSnapF32>(a, grid, s); break;
-            case dev::kSnapBF16: launch_cam<dev::kSnapBF16>(a, grid, s); break;
+            case FPO_F32: launch_cam<FPO_F32>(a, grid, skip, s); break;
+            case FPO_BF16: launch_cam<FPO_BF16>(a, grid, skip, s); break;
+            case FPO_FP8_E4M3: launch_cam<FPO_FP8_E4M3>(a, grid, skip, s); break;
+            case dev::kSnapF32: launch_cam<dev::kSnapF32>(a, grid, skip, s); break;
+            case dev::kSnapBF16: launch_cam<dev::kSnapBF16>(a, grid, skip, s); break;
             default: return fail(FPO_E_INVALID, "unknown render mode");
         }
         if ((st = launch_status("fpo_render")) != FPO_OK) return st;

@@ -303,3 +303,53 @@ def random_rays(n: int, seed: int, inside_frac: float = 0.2):
     d[inside] = rng.standard_normal((int(inside.sum()), 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     return o.astype(np.float32), d.astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# learned-proposal workload: depth-9 blob scene, training rays from random ring
+# cameras, test views = the 16 ring cameras x 30 times
+# --------------------------------------------------------------------------
+C5_N_TIMES = 3600     # training times: a grid of T / 3600 over the period
+
+
+def c5_time_grid() -> np.ndarray:
+    return (np.arange(C5_N_TIMES) + 0.5) * (PERIOD / C5_N_TIMES)
+
+
+def c5_train_cameras(n_cams: int = 4096, width: int = 1920, height: int = 1080,
+                     seed: int = RAY_SEED) -> List[Camera]:
+    """Ring cameras at azimuth U[0, 2 pi), elevation U[5, 25] deg, radius 1.5,
+    FOV 30 deg (their time is unused: each training ray draws its own)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 5))
+    az = rng.uniform(0.0, 2.0 * math.pi, n_cams)
+    el = np.radians(rng.uniform(5.0, 25.0, n_cams))
+    return [ring_camera(float(a), float(e), 1.5, 30.0, width, height, 0.0) for a, e in zip(az, el)]
+
+
+def c5_train_samples(n: int, n_cams: int, width: int = 1920, height: int = 1080, seed: int = RAY_SEED):
+    """(camera, row, column, time index) of n training rays, uniform."""
+    rng = np.random.Generator(np.random.PCG64(seed + 6))
+    cam = rng.integers(0, n_cams, size=n).astype(np.int32)
+    py = rng.integers(0, height, size=n).astype(np.int32)
+    px = rng.integers(0, width, size=n).astype(np.int32)
+    t_idx = rng.integers(0, C5_N_TIMES, size=n).astype(np.int32)
+    return cam, py, px, t_idx
+
+
+def c5_test_cameras(width: int = 1920, height: int = 1080) -> List[Camera]:
+    """The 16 C2 ring cameras at 30 times t = (j + 0.5) * 2."""
+    return c2_cameras(width, height, times=[(j + 0.5) * 2.0 for j in range(30)])
+
+
+def mlp_init(seed: int = 11) -> np.ndarray:
+    """He-normal proposal weights with zero biases, as the flat FP32 vector
+    ([85][64], [65][64], [65][3], bias rows last), padded to 9796."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for n_in, n_out in ((84, 64), (64, 64), (64, 3)):
+        w = rng.standard_normal((n_in, n_out)) * math.sqrt(2.0 / n_in)
+        parts.append(np.vstack([w, np.zeros((1, n_out))]).ravel())
+    p = np.zeros(9796, np.float32)
+    flat = np.concatenate(parts)
+    p[:flat.size] = flat
+    return p

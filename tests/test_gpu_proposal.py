@@ -1,0 +1,356 @@
+"""GPU parity of the learned proposal: the FP32 training kernels and the FP16
+matrix-core inference against the FP64 reference network, the labels against
+the oracle walk, skip-mode renders against plain renders and the oracle, and
+a short training run on the GPU with what the trained network gains."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2202_08614_amd import _lib, proposal, synth
+from tests.gpu_util import check_parity, conditioned_reference, note, perpendicular_pair, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def _inputs(n, seed):
+    """Network inputs shaped like real ones: a point of the unit cube, a unit
+    direction, tau in [0, 1)."""
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([rng.uniform(0, 1, (n, 3)), rng.standard_normal((n, 3)), rng.uniform(0, 1, (n, 1))], 1)
+    x[:, 3:6] /= np.linalg.norm(x[:, 3:6], axis=1, keepdims=True)
+    return x.astype(np.float32)
+
+
+def _labels(n, seed):
+    rng = np.random.default_rng(seed)
+    s = np.sort(rng.uniform(0, 1, (n, 2)), axis=1)
+    hit = rng.random(n) < 0.6
+    lab = np.stack([hit, np.where(hit, s[:, 0], 0), np.where(hit, s[:, 1], 0)], 1)
+    return lab.astype(np.float32)
+
+
+def _params(seed, bias_sd=0.2):
+    p = synth.mlp_init(seed)
+    rng = np.random.default_rng(seed + 100)
+    w = mlp.from_flat(p[:mlp.N_PARAMS])
+    for k in ("b1", "b2", "b3"):
+        w[k] = rng.standard_normal(w[k].shape) * bias_sd
+    flat = np.zeros(_lib.MLP_N_PARAMS_PADDED, np.float32)
+    flat[:mlp.N_PARAMS] = mlp.to_flat(w)
+    return flat
+
+
+def _w64(p):
+    return mlp.from_flat(p[:mlp.N_PARAMS].astype(np.float64))
+
+
+def test_mlp_forward_matches_oracle(dev):
+    import torch
+    p = _params(1)
+    x = _inputs(1000, 2)
+    note("fpo_mlp_forward n=1000")
+    out = _lib.mlp_forward(torch.from_numpy(p).to(dev), torch.from_numpy(x).to(dev))
+    torch.cuda.synchronize()
+    w = _w64(p)
+    want, _ = mlp.forward(w, x.astype(np.float64))
+    mag = mlp.magnitude(w, x.astype(np.float64))
+    err = np.abs(out.cpu().numpy() - want)
+    assert np.all(err <= 2.0 ** -16 * mag), float((err / mag).max())
+
+
+def test_mlp_loss_grad_matches_oracle(dev):
+    """Batch of 3000 rows picked through an index array (ragged last 64-ray
+    chunk, three 1024-ray partial sums), away from the ReLU and pinball kinks
+    so that FP32 and FP64 take the same branches."""
+    import torch
+    p = _params(3)
+    w = _w64(p)
+    X = _inputs(20000, 4)
+    Y = _labels(20000, 5)
+    o, cache = mlp.forward(w, X.astype(np.float64))
+    _, z1, _, z2, _ = cache
+    s = mlp.sigmoid(o[:, 1:])
+    u = np.abs(Y[:, 1:] - s)
+    ok = (np.abs(z1).min(1) > 1e-3) & (np.abs(z2).min(1) > 1e-3) & ((Y[:, 0] < 0.5) | (u.min(1) > 1e-3))
+    idx = np.nonzero(ok)[0][:3000].astype(np.int32)
+    assert len(idx) == 3000
+    np.random.default_rng(6).shuffle(idx)
+    Pd = torch.from_numpy(p).to(dev)
+    Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    grad = torch.zeros_like(Pd)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    ws = _lib.mlp_workspace(len(idx), dev)
+    note("fpo_mlp_loss_grad n=3000 (indexed)")
+    _lib.mlp_loss_grad(Pd, Xd, Yd, grad, loss, ws, idx=torch.from_numpy(idx).to(dev))
+    torch.cuda.synchronize()
+    xb, yb = X[idx].astype(np.float64), Y[idx].astype(np.float64)
+    ob, cb = mlp.forward(w, xb)
+    want_loss, g_out = mlp.loss_and_grad_out(ob, yb)
+    want = mlp.to_flat(mlp.backward(w, cb, g_out))
+    # scale of each gradient entry: sum over rays of |input| |delta|
+    gb, z1b, a1b, z2b, a2b = cb
+    d2 = np.abs(g_out) @ np.abs(w["W3"]).T
+    d1 = d2 @ np.abs(w["W2"]).T
+    ones = np.ones((len(idx), 1))
+    mag = np.concatenate([(np.hstack([np.abs(gb), ones]).T @ d1).ravel(),
+                          (np.hstack([a1b, ones]).T @ d2).ravel(),
+                          (np.hstack([a2b, ones]).T @ np.abs(g_out)).ravel()])
+    got = grad.cpu().numpy()[:mlp.N_PARAMS]
+    err = np.abs(got - want)
+    assert np.all(err <= 2.0 ** -14 * mag + 1e-12), float(np.max(err - 2.0 ** -14 * mag))
+    assert abs(float(loss.item()) - want_loss) <= 1e-5 * want_loss
+    assert got[mlp.N_PARAMS - 1] != 0.0
+    assert grad.cpu().numpy()[mlp.N_PARAMS] == 0.0      # the padding entry is never written
+
+
+def test_mlp_loss_grad_accumulates_deterministically(dev):
+    import torch
+    p = torch.from_numpy(_params(7)).to(dev)
+    X = torch.from_numpy(_inputs(2500, 8)).to(dev)
+    Y = torch.from_numpy(_labels(2500, 9)).to(dev)
+    ws = _lib.mlp_workspace(2500, dev)
+    g1 = torch.zeros_like(p)
+    g2 = torch.zeros_like(p)
+    l1 = torch.zeros(1, dtype=torch.float32, device=dev)
+    l2 = torch.zeros(1, dtype=torch.float32, device=dev)
+    note("fpo_mlp_loss_grad determinism")
+    _lib.mlp_loss_grad(p, X, Y, g1, l1, ws)
+    _lib.mlp_loss_grad(p, X, Y, g2, l2, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+    _lib.mlp_loss_grad(p, X, Y, g2, l2, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(g2, 2 * g1) and torch.equal(l2, 2 * l1)
+
+
+@pytest.mark.parametrize("n", [1000, 256, 7])
+def test_mlp_infer_matches_fp16_oracle(dev, n):
+    """Matrix-core FP16 inference against the reference network with FP16
+    weights and activations: within one FP16 rounding of every propagated
+    term; against the exact network within a few."""
+    import torch
+    p = _params(11)
+    x = _inputs(n, 12)
+    Pd = torch.from_numpy(p).to(dev)
+    note(f"fpo_mlp_pack + fpo_mlp_infer n={n}")
+    packed = _lib.mlp_pack(Pd)
+    out = _lib.mlp_infer(packed, torch.from_numpy(x).to(dev))
+    torch.cuda.synchronize()
+    w = _w64(p)
+    w["b1"], w["b2"], w["b3"] = (w[k].astype(np.float32).astype(np.float64) for k in ("b1", "b2", "b3"))
+    xe = x.astype(np.float64)
+    mag = mlp.magnitude(w, xe)
+    got = out.cpu().numpy()
+    assert np.all(np.abs(got - mlp.forward_fp16(w, xe)) <= 2.0 ** -9 * mag)
+    exact, _ = mlp.forward(w, xe)
+    assert np.all(np.abs(got - exact) <= 2.0 ** -7 * mag)
+    # packed biases are the FP32 parameters; weights the FP16 roundings
+    raw = packed.cpu().numpy()
+    b = raw[22528:].view(np.float32)
+    assert np.array_equal(b[:64], p[84 * 64:85 * 64]) and b[131] == 0.0
+    frag = raw[:22528].view(np.float16).reshape(44, 64, 4)
+    # fragment 0 (layer 1, rows 0..15, features 0..15): lane l holds A[l % 16][4 (l // 16) + e]
+    W1 = w["W1"]
+    for ln in (0, 17, 63):
+        for e in range(4):
+            assert frag[0, ln, e] == np.float16(W1[4 * (ln // 16) + e, ln % 16])
+
+
+@pytest.fixture(scope="module")
+def blob_scene():
+    dijk = synth.blob_leaves(7, 40000)
+    coeffs = synth.gaussian_coeffs(len(dijk), seed=77)
+    return dijk, coeffs
+
+
+def _label_exempt(oracle_lib, ot, k, p, times, o, d, t_idx):
+    """Rays whose labels are not fixed by an FP32 ray: labels that change
+    under sideways shifts of 2e-7, or an early-termination straddle."""
+    base = oracle_lib.ray_labels(ot, k, p, times, o, d, t_idx)
+    u, v = perpendicular_pair(d)
+    bad = np.zeros(len(o), bool)
+    for s, w in ((1, u), (-1, u), (1, v), (-1, v)):
+        alt = oracle_lib.ray_labels(ot, k, p, times, o + s * 2e-7 * w, d, t_idx)
+        bad |= alt[:, 0] != base[:, 0]
+        bad |= np.abs(alt[:, 1:] - base[:, 1:]).max(1) > 1e-5
+    r = oracle_lib.render_rays(ot, k, p, times, o, d, t_idx)
+    bad |= r["n_seg"][:, 0] != r["n_seg"][:, 1]
+    return base, bad
+
+
+@pytest.mark.parametrize("stop_T", [0.0, 1e-2])
+def test_labels_match_oracle(oracle_lib, dev, blob_scene, stop_T):
+    import torch
+    dijk, k = blob_scene
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev)
+    o, d = synth.random_rays(4000, 41, inside_frac=0.2)
+    times = [3.1, 22.2, 47.9]
+    t_idx = (np.arange(4000) % 3).astype(np.int32)
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    tau = torch.tensor([t / 60.0 for t in times], dtype=torch.float32, device=dev)
+    note(f"fpo_ray_labels stop_T={stop_T}")
+    lab, inp = _lib.ray_labels(tree, torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev),
+                               torch.from_numpy(t_idx).to(dev), basis, tau, _lib.make_opts(stop_T=stop_T))
+    torch.cuda.synchronize()
+    lab, inp = lab.cpu().numpy(), inp.cpu().numpy()
+    ot = oracle_lib.OracleTree(dijk, 7)
+    p = oracle_lib.make_params(stop_T=stop_T)
+    o64, d64 = o.astype(np.float64), d.astype(np.float64)
+    want, exempt = _label_exempt(oracle_lib, ot, k, p, times, o64, d64, t_idx)
+    assert exempt.mean() < 0.01
+    keep = ~exempt
+    assert np.array_equal(lab[keep, 0], want[keep, 0])
+    assert np.abs(lab[keep, 1:] - want[keep, 1:]).max() <= 2e-5
+    assert 0.05 < want[:, 0].mean() < 0.9
+    ref_inp = mlp.ray_inputs(o64, d64, np.array(times)[t_idx])
+    dn = d64 / np.linalg.norm(d64, axis=1, keepdims=True)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1, t2 = (0.0 - o64) / dn, (1.0 - o64) / dn
+    lo = np.max(np.where(dn == 0, -np.inf, np.minimum(t1, t2)), axis=1)
+    hi = np.min(np.where(dn == 0, np.inf, np.maximum(t1, t2)), axis=1)
+    chord = np.maximum(lo, 0.0) < hi - 1e-4
+    assert chord.mean() > 0.5
+    assert np.abs(inp - ref_inp)[chord].max() <= 1e-5
+
+
+def _skip_renders(tree, cams, bits, packed, stop_T):
+    import torch
+    ws = _lib.skip_workspace(len(cams), cams[0].height, cams[0].width, tree.children.device)
+    out = {}
+    out["plain"], _ = _lib.render(tree, cams, _lib.make_opts(stop_T=stop_T))
+    out["coarse"], _ = _lib.render(tree, cams, _lib.make_opts(stop_T=stop_T, flags=_lib.FPO_RENDER_SKIP_COARSE,
+                                                             coarse_bits=bits, workspace=ws))
+    for name, pk in packed.items():
+        out[name], _ = _lib.render(tree, cams, _lib.make_opts(stop_T=stop_T, flags=_lib.FPO_RENDER_SKIP_PROPOSAL,
+                                                             coarse_bits=bits, proposal=pk, workspace=ws))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _assert_same_image(oracle_lib, dijk, depth, k, cams, img, plain, stop_T, tol=2e-5):
+    """A skip render equals the plain one to tol except at rays whose colour
+    FP32 does not fix (face ties); those few are checked against the
+    conditioned oracle like any parity case."""
+    diff = np.abs(img - plain).max(-1)                      # [n][H][W]
+    bad = np.argwhere(diff > tol)
+    assert len(bad) <= max(2, 1e-4 * diff.size), f"{len(bad)} pixels differ from the plain render"
+    if len(bad) == 0:
+        return
+    ot = oracle_lib.OracleTree(dijk, depth)
+    p = oracle_lib.make_params(stop_T=stop_T)
+    for c in np.unique(bad[:, 0]):
+        sel = bad[bad[:, 0] == c]
+        cam = cams[int(c)]
+        o, d = oracle_lib.camera_rays(cam)
+        rows = sel[:, 1] * cam.width + sel[:, 2]
+        ref = conditioned_reference(oracle_lib, ot, k, p, [cam.time], o[rows], d[rows],
+                                    np.zeros(len(rows), np.int32))
+        check_parity(img[c].reshape(-1, 3)[rows], ref, 1e-4, max_exempt_frac=1.0)
+        print(f"[skip] camera {c}: {len(rows)} tie pixels checked against the oracle")
+
+
+def _forced(seed, b3):
+    """A network whose outputs are the constants b3 (W3 = 0)."""
+    p = _params(seed, bias_sd=0.0)
+    k3 = 85 * 64 + 65 * 64                 # start of the [65][3] output layer
+    p[k3:k3 + 64 * 3] = 0.0
+    p[k3 + 64 * 3:k3 + 65 * 3] = b3
+    return p
+
+
+def test_skip_renders_equal_plain_and_oracle(oracle_lib, dev, blob_scene):
+    """Coarse skipping and proposal skipping with an untrained network and with
+    networks forced to every failure (a miss predicted for every ray, an entry
+    past the exit, an exit at the entry) give the plain image; one of them is
+    also checked against the oracle with early termination."""
+    import torch
+    dijk, k = blob_scene
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev)
+    bits = torch.from_numpy(_lib.coarse_occupancy(dijk, 7).view(np.int32)).to(dev)
+    nets = {"untrained": _params(21), "miss": _forced(22, [-20.0, 0.0, 0.0]),
+            "overshoot": _forced(23, [20.0, 20.0, 20.0]), "short": _forced(24, [20.0, -20.0, -20.0])}
+    packed = {}
+    for name, p in nets.items():
+        packed[name] = _lib.mlp_pack(torch.from_numpy(p).to(dev))
+    cams = [synth.ring_camera(0.3 + 1.1 * j, math.radians(5 + 7 * j), 1.5, 30.0, 72, 40, 7.0 + 13.0 * j)
+            for j in range(3)]
+    note("skip renders stop_T=0")
+    imgs = _skip_renders(tree, cams, bits, packed, 0.0)
+    for name, im in imgs.items():
+        _assert_same_image(oracle_lib, dijk, 7, k, cams, im, imgs["plain"], 0.0)
+    assert imgs["plain"].max() > 0.05
+    note("skip renders stop_T=1e-3 vs oracle")
+    imgs = _skip_renders(tree, cams, bits, packed, 1e-3)
+    ot = oracle_lib.OracleTree(dijk, 7)
+    p = oracle_lib.make_params(stop_T=1e-3)
+    for c, cam in enumerate(cams[:2]):
+        o, d = oracle_lib.camera_rays(cam)
+        ref = conditioned_reference(oracle_lib, ot, k, p, [cam.time], o, d, np.zeros(len(o), np.int32))
+        for name in ("coarse", "untrained", "overshoot"):
+            check_parity(imgs[name][c].reshape(-1, 3), ref, 1e-4)
+
+
+def test_proposal_training_and_gain(oracle_lib, dev, blob_scene):
+    """Train the proposal on the GPU from plain-walk labels, check that it
+    learned (loss and hit accuracy), that its render still equals the plain
+    one, and report what it gains over plain traversal and over coarse-only
+    skipping (printed; the gain itself is measured by the benchmark)."""
+    import torch
+    dijk, k = blob_scene
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev)
+    note("proposal training set (200k rays)")
+    labels, inputs = proposal.training_set(tree, 200_000, n_cams=512, stop_T=1e-3, width=480, height=270)
+    torch.cuda.synchronize()
+    hit_rate = float(labels[:, 0].mean())
+    assert 0.05 < hit_rate < 0.95
+    prop = proposal.Proposal(dev, seed=5)
+    ev_idx = torch.arange(150_000, 200_000, device=dev)
+
+    def accuracy():
+        out = _lib.mlp_infer(prop.packed(), inputs[ev_idx])
+        return float(((out[:, 0] > 0) == (labels[ev_idx, 0] > 0.5)).float().mean())
+
+    acc0 = accuracy()
+    note("proposal training 600 steps")
+    hist = prop.train(inputs[:150_000], labels[:150_000], steps=600, batch=8192, lr=3e-3, log_every=100)
+    torch.cuda.synchronize()
+    acc1 = accuracy()
+    print(f"[proposal] loss per 100 steps {['%.4f' % v for v in hist]}, hit accuracy {acc0:.3f} -> {acc1:.3f}")
+    assert hist[-1] < 0.7 * hist[0]
+    assert acc1 > max(acc0, 0.85)
+    # trained network: same image as plain traversal
+    bits = torch.from_numpy(_lib.coarse_occupancy(dijk, 7).view(np.int32)).to(dev)
+    cams = [synth.ring_camera(2 * math.pi * j / 16, math.radians(15), 1.5, 30.0, 480, 270, 1.0 + 2.0 * j)
+            for j in range(16)]
+    packed = {"trained": prop.packed()}
+    note("trained proposal render")
+    imgs = _skip_renders(tree, cams, bits, packed, 0.0)
+    _assert_same_image(oracle_lib, dijk, 7, k, cams, imgs["trained"], imgs["plain"], 0.0)
+    _assert_same_image(oracle_lib, dijk, 7, k, cams, imgs["coarse"], imgs["plain"], 0.0)
+    # timing: median of 5 after a warm-up
+    ws = _lib.skip_workspace(len(cams), 270, 480, dev)
+    modes = {"plain": _lib.make_opts(stop_T=1e-3),
+             "coarse": _lib.make_opts(stop_T=1e-3, flags=_lib.FPO_RENDER_SKIP_COARSE, coarse_bits=bits, workspace=ws),
+             "proposal": _lib.make_opts(stop_T=1e-3, flags=_lib.FPO_RENDER_SKIP_PROPOSAL, coarse_bits=bits,
+                                        proposal=packed["trained"], workspace=ws)}
+    times = {}
+    rgb = torch.empty((16, 270, 480, 3), dtype=torch.float32, device=dev)
+    for name, opts in modes.items():
+        _lib.render(tree, cams, opts, rgb=rgb)
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _lib.render(tree, cams, opts, rgb=rgb)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        times[name] = float(np.median(ts))
+    print("[proposal] 16 x 480x270 render ms: " + ", ".join(f"{n} {1e3 * t:.3f}" for n, t in times.items()))

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_functions():
     src = open(os.path.join(ROOT, "include", "fpo.h")).read()
-    return sorted(set(re.findall(r"^(?:fpo_status|const char\*)\s+(fpo_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:fpo_status|const char\*|int64_t)\s+(fpo_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -163,3 +163,60 @@ def test_device_calls_reject_bad_arguments_without_launching():
     opts.stop_T = 1.5
     st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
     assert st == _lib.FPO_E_INVALID and b"stop_T" in L.fpo_last_error()
+
+
+def test_coarse_occupancy_matches_oracle():
+    """fpo_coarse_occupancy is bit-exact against the oracle's definition, with
+    leaves finer and coarser than the 64^3 grid."""
+    from oracle import occupancy
+    for seed, depth in ((2, 7), (5, 9)):
+        dijk = synth.random_tree_leaves(seed, depth, p_split=0.55)
+        got = _lib.coarse_occupancy(dijk, depth)
+        want = occupancy.to_words(occupancy.dilated(dijk))
+        assert np.array_equal(got, want)
+    mixed = np.array([[2, 1, 0, 3], [4, 0, 15, 7], [8, 255, 128, 3], [6, 63, 63, 63]], np.int32)
+    assert np.array_equal(_lib.coarse_occupancy(mixed, 8), occupancy.to_words(occupancy.dilated(mixed)))
+    with pytest.raises(_lib.FpoError):
+        _lib.coarse_occupancy(np.array([[3, 8, 0, 0]], np.int32), 5)
+    with pytest.raises(_lib.FpoError):
+        _lib.coarse_occupancy(np.array([[6, 0, 0, 0]], np.int32), 5)
+
+
+def test_skip_and_proposal_calls_validate_on_host():
+    L = _lib.lib()
+    view = _lib.TreeView()
+    view.children = 16
+    view.n_nodes = 1
+    view.max_depth = 3
+    view.n_leaves = 1
+    view.leaf_stride = 1
+    view.coeffs = 16
+    view.layout = _lib.make_layout()
+    cams = _lib.camera_struct([synth.ring_camera(0, 0, 1.5, 30, 4, 4, 0)])
+    opts = _lib.make_opts()
+    opts.flags = 3
+    st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_INVALID and b"flags" in L.fpo_last_error()
+    opts.flags = 1
+    st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_INVALID and b"coarse_bits" in L.fpo_last_error()
+    opts.coarse_bits = 64
+    opts.workspace = 64
+    opts.workspace_bytes = 4 * 4 * 8 - 8
+    st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_INVALID and b"workspace_bytes" in L.fpo_last_error()
+    opts.flags = 2
+    st = L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_INVALID and b"proposal" in L.fpo_last_error()
+    # skip flags belong to fpo_render only
+    rays = ctypes.c_void_p(64)
+    st = L.fpo_render_rays(ctypes.byref(view), rays, rays, rays, rays, 1, 1, ctypes.byref(opts), rays, None, None)
+    assert st == _lib.FPO_E_INVALID and b"flags" in L.fpo_last_error()
+    assert L.fpo_mlp_loss_grad(rays, rays, rays, None, 0, rays, rays, rays, None) == _lib.FPO_E_INVALID
+    assert L.fpo_mlp_loss_grad(rays, rays, rays, None, 5, ctypes.c_void_p(8), rays, rays, None) == _lib.FPO_E_INVALID
+    assert L.fpo_mlp_pack(rays, ctypes.c_void_p(8), None) == _lib.FPO_E_INVALID
+    assert L.fpo_mlp_infer(None, rays, 4, rays, None) == _lib.FPO_E_INVALID
+    assert L.fpo_mlp_infer(rays, rays, 0, rays, None) == _lib.FPO_OK
+    # workspace: feature rows for 64-ray chunks plus one partial per 1024 rays
+    assert L.fpo_mlp_workspace_floats(1) == 344 * 64 + 9796
+    assert L.fpo_mlp_workspace_floats(3000) == 344 * 3008 + 3 * 9796

@@ -114,3 +114,57 @@ def test_labels_match_brute_force(oracle_lib):
             assert abs(lab[r, 2] - (last - t_in) / (hi - t_in)) < 1e-12
             assert np.allclose(inp[0, :3], o[r] + t_in * dd)
     assert n_hit > 10
+
+
+def test_flat_layout_round_trip_and_order():
+    w = mlp.init_weights(5)
+    w["b1"] = np.arange(64.0)
+    p = mlp.to_flat(w)
+    assert p.shape == (9795,)
+    # row-major [85][64]: W1[k][j] at k*64 + j, b1 on row 84
+    assert p[3 * 64 + 7] == w["W1"][3, 7]
+    assert np.array_equal(p[84 * 64:85 * 64], np.arange(64.0))
+    assert p[85 * 64 + 65 * 64 + 10 * 3 + 2] == w["W3"][10, 2]
+    back = mlp.from_flat(p)
+    for k in w:
+        assert np.array_equal(back[k], w[k])
+
+
+def test_fp16_forward_within_rounding_bound():
+    """FP16 inference differs from the exact network by at most a few FP16
+    roundings (2^-11 relative) of each propagated term; a transposed or
+    misplaced operand would be off by O(magnitude)."""
+    w = mlp.init_weights(8)
+    for k in ("b1", "b2", "b3"):
+        w[k] = np.random.default_rng(9).standard_normal(w[k].shape) * 0.2
+    inp, _ = _batch(500, 10)
+    exact, _ = mlp.forward(w, inp)
+    half = mlp.forward_fp16(w, inp)
+    mag = mlp.magnitude(w, inp)
+    err = np.abs(half - exact)
+    assert np.all(err <= 2.0 ** -8 * mag)
+    assert err.max() > 0          # the rounding is really applied
+
+
+def test_coarse_occupancy_against_box_overlap(oracle_lib):
+    """The index-range definition against a continuous box-overlap test: cell
+    (x, y, z) is set iff some leaf box meets the open block of the cell and its
+    neighbours, [(x-1)/64, (x+2)/64) per axis."""
+    from oracle import occupancy
+    rng = np.random.default_rng(3)
+    dijk = synth.random_tree_leaves(17, 7, p_split=0.5)[:300]
+    dijk = np.vstack([dijk, [[3, 1, 6, 2]], [[2, 0, 0, 3]]])          # coarser-than-grid leaves
+    grid = occupancy.dilated(dijk)
+    lo = dijk[:, 1:4] / 2.0 ** dijk[:, :1]
+    hi = (dijk[:, 1:4] + 1) / 2.0 ** dijk[:, :1]
+    cells = rng.integers(0, 64, (3000, 3))
+    cells = np.vstack([cells, np.argwhere(grid)[:, ::-1][rng.integers(0, grid.sum(), 500)]])
+    for x, y, z in cells:
+        blo = (np.array([x, y, z]) - 1) / 64.0
+        bhi = (np.array([x, y, z]) + 2) / 64.0
+        want = np.any(np.all((lo < bhi) & (blo < hi), axis=1))
+        assert grid[z, y, x] == want, (x, y, z)
+    assert 0 < grid.sum() < 64 ** 3
+    words = occupancy.to_words(grid)
+    idx = (5 * 64 + 9) * 64 + 33
+    assert ((words[idx >> 5] >> (idx & 31)) & 1) == grid[5, 9, 33]
