@@ -164,6 +164,138 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5):
     return res
 
 
+def proposal_leg(dev, sc, tree, oracle_mod, n_train: int = 4_000_000, train_steps: int = 1500,
+                 batch: int = 16384, oracle_rays: int = 20000):
+    """Learned proposal on the 2M-leaf scene: label 4M rays from random ring
+    cameras / pixels / times with the plain walk, train the MLP on the GPU,
+    then render the 16 ring cameras x 30 times at 1920x1080 with plain
+    traversal, coarse-occupancy skipping and proposal skipping, for the FP32
+    and BF16 coefficient stores and for the decode path (one IDFT pass per
+    time into F32 snapshot records, then snapshot renders)."""
+    import torch
+    from paper_2202_08614_amd import _lib, proposal, synth
+    res = {}
+    cams = synth.c5_test_cameras()
+    W, H = cams[0].width, cams[0].height
+    n_times, per = 30, 16
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    bits = torch.from_numpy(_lib.coarse_occupancy(sc.leaf_dijk, sc.max_depth).view(np.int32)).to(dev)
+    res["coarse_cells_set_frac"] = round(float(np.unpackbits(bits.cpu().numpy().view(np.uint8)).mean()), 4)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    labels, inputs = proposal.training_set(tree, n_train, n_cams=4096, stop_T=sc.stop_T)
+    ev[1].record(stream)
+    prop = proposal.Proposal(dev, seed=11)
+    n_fit = n_train - 100_000
+    ev[2].record(stream)
+    hist = prop.train(inputs[:n_fit], labels[:n_fit], steps=train_steps, batch=batch, lr=2e-3,
+                      log_every=max(1, train_steps // 5))
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    packed = prop.packed()
+    held = slice(n_fit, n_train)
+    out = _lib.mlp_infer(packed, inputs[held])
+    lab = labels[held]
+    hit_acc = float(((out[:, 0] > 0) == (lab[:, 0] > 0.5)).float().mean())
+    s_in = torch.sigmoid(out[:, 1]); s_out = torch.sigmoid(out[:, 2])
+    hit = lab[:, 0] > 0.5
+    res["train"] = {
+        "labelled_rays": n_train, "label_ms": round(ev[0].elapsed_time(ev[1]), 2),
+        "steps": train_steps, "batch": batch, "train_ms": round(ev[2].elapsed_time(ev[3]), 2),
+        "loss_history": [round(v, 5) for v in hist],
+        "heldout_hit_accuracy": round(hit_acc, 4),
+        "heldout_entry_before_label_frac": round(float((s_in[hit] <= lab[hit, 1]).float().mean()), 4),
+        "heldout_exit_after_label_frac": round(float((s_out[hit] >= lab[hit, 2]).float().mean()), 4),
+        "heldout_entry_mae": round(float((s_in[hit] - lab[hit, 1]).abs().mean()), 4),
+    }
+    log(f"proposal trained in {time.time() - t0:.1f}s: {res['train']}")
+    del labels, inputs
+
+    tree16 = _lib.quantize(tree, _lib.FPO_BF16)
+    grid_t = [(j + 0.5) * 2.0 for j in range(n_times)]
+    basis = torch.from_numpy(_lib.time_basis(grid_t)).to(dev)
+    snap = torch.empty((1, tree.leaf_stride, _lib.SNAP_VALUES), dtype=torch.float32, device=dev)
+    ws = _lib.skip_workspace(per, H, W, dev)
+    skip = {"plain": dict(), "coarse": dict(flags=_lib.FPO_RENDER_SKIP_COARSE, coarse_bits=bits, workspace=ws),
+            "proposal": dict(flags=_lib.FPO_RENDER_SKIP_PROPOSAL, coarse_bits=bits, proposal=packed, workspace=ws)}
+    modes = []
+    for store, tr in (("f32", tree), ("bf16", tree16)):
+        for sk in skip:
+            modes.append((f"fourier_{store}_{sk}", tr, False, sk))
+    for sk in skip:
+        modes.append((f"decode_bf16_{sk}", tree16, True, sk))
+    frames = torch.empty((per, H, W, 3), dtype=torch.float32, device=dev)
+    # quality sample: uniform over the 480 frames
+    rng = np.random.default_rng(7)
+    ci = rng.integers(0, len(cams), oracle_rays)
+    py = rng.integers(0, H, oracle_rays)
+    px = rng.integers(0, W, oracle_rays)
+
+    def run(tr, decode, sk, sample=False):
+        opts = _lib.make_opts(stop_T=sc.stop_T, **skip[sk],
+                              **(dict(snapshot=snap, snapshot_dtype=_lib.FPO_F32, snapshot_cam_stride=0) if decode else {}))
+        got = np.zeros((oracle_rays, 3)) if sample else None
+        for j in range(n_times):
+            if decode:
+                _lib.bake_times(tr, basis[j:j + 1], _lib.FPO_F32, out=snap)
+            _lib.render(tr, cams[j * per:(j + 1) * per], opts, rgb=frames)
+            if sample:
+                sel = np.nonzero((ci >= j * per) & (ci < (j + 1) * per))[0]
+                if len(sel):
+                    idx = [torch.from_numpy(a[sel]).to(dev) for a in (ci - j * per, py, px)]
+                    got[sel] = frames[idx[0], idx[1], idx[2]].cpu().numpy()
+        return got
+
+    o = np.zeros((oracle_rays, 3)); d = np.zeros((oracle_rays, 3))
+    for cam_i in np.unique(ci):
+        sel = np.nonzero(ci == cam_i)[0]
+        o[sel], d[sel] = oracle_mod.camera_rays(cams[cam_i], px[sel], py[sel])
+    ot = oracle_mod.OracleTree(sc.leaf_dijk, sc.max_depth)
+    p = oracle_mod.make_params(stop_T=sc.stop_T, band=1e-3)
+    ref = oracle_mod.render_rays(ot, sc.coeffs, p, [c.time for c in cams], o, d, ci.astype(np.int32),
+                                 n_threads=len(os.sched_getaffinity(0)))
+    table = {}
+    samples = {}
+    for name, tr, decode, sk in modes:
+        run(tr, decode, sk)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run(tr, decode, sk)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        got = run(tr, decode, sk, sample=True)
+        samples[name] = got
+        err = np.minimum(np.abs(got - ref["rgb"][:, 0]).max(1), np.abs(got - ref["rgb"][:, 1]).max(1))
+        mse = float(np.mean(np.min([((got - ref["rgb"][:, i]) ** 2).mean(1) for i in range(2)], axis=0)))
+        table[name] = {"ms_480_frames": round(ms, 3), "fps_1080p": round(len(cams) / (ms * 1e-3), 1),
+                       "psnr_vs_oracle_db": round(10 * np.log10(1.0 / mse), 2) if mse > 0 else None,
+                       "max_abs_err_vs_oracle": float(err.max())}
+        log(f"proposal leg {name}: {table[name]}")
+    for name in table:
+        base = name.rsplit("_", 1)[0] + "_plain"
+        table[name]["max_abs_diff_vs_plain_same_store"] = float(np.abs(samples[name] - samples[base]).max())
+    res["renders"] = table
+    f = lambda n: table[n]["fps_1080p"]
+    res["gain"] = {
+        "proposal_vs_plain_fourier_f32": round(f("fourier_f32_proposal") / f("fourier_f32_plain"), 3),
+        "proposal_vs_coarse_fourier_f32": round(f("fourier_f32_proposal") / f("fourier_f32_coarse"), 3),
+        "proposal_vs_plain_decode_bf16": round(f("decode_bf16_proposal") / f("decode_bf16_plain"), 3),
+        "best_bf16_proposal_vs_plain_fourier_f32": round(max(f("fourier_bf16_proposal"), f("decode_bf16_proposal"))
+                                                         / f("fourier_f32_plain"), 3),
+    }
+    res["workload"] = ("C5: 2.0M-leaf depth-9 scene; 4M training rays from random ring cameras (az U[0,2pi), "
+                       "el U[5,25] deg), random 1080p pixels, times on a 3600-step grid; test 16 ring cameras x 30 "
+                       "times t=(j+0.5)*2 at 1920x1080, early termination T<1e-3")
+    log(f"proposal gain: {res['gain']}")
+    del tree16, snap, ws, frames
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +306,8 @@ def main():
     ap.add_argument("--no-finetune", action="store_true")
     ap.add_argument("--no-bake", action="store_true")
     ap.add_argument("--ft-steps", type=int, default=40)
+    ap.add_argument("--no-proposal", action="store_true")
+    ap.add_argument("--only-proposal", action="store_true", help="run only the learned-proposal leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprof byte counters)")
     args = ap.parse_args()
@@ -201,6 +335,10 @@ def main():
     torch.cuda.synchronize()
     log(f"tree: {tree.n_nodes} nodes uploaded")
 
+    if args.only_proposal:
+        import oracle
+        print(json.dumps({"proposal": proposal_leg(dev, sc, tree, oracle)}), flush=True)
+        return
     cams = sc.cameras
     n_t = 10
     per = 16
@@ -346,6 +484,7 @@ def main():
     del frames
     bake = None if args.no_bake else bake_leg(dev, sc, tree, oracle)
     ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
+    prop = None if args.no_proposal else proposal_leg(dev, sc, tree, oracle)
 
     out = {
         "metric": METRIC,
@@ -397,6 +536,7 @@ def main():
         },
         "bake": bake,
         "finetune": ft,
+        "proposal": prop,
         "paper_context": "100 fps at 800x800 (64 Mrays/s) on one RTX 3090, the paper's own scenes",
     }
     print(json.dumps(out), flush=True)

@@ -136,11 +136,10 @@ typedef struct {
                                  between the first and last set cells of coarse_bits on
                                  its chord;
                                  FPO_RENDER_SKIP_PROPOSAL: the proposal network predicts
-                                 the first entry and last exit; the skipped prefix is
-                                 checked against coarse_bits before the walk (the walk
-                                 starts at the first set cell if the check fails), and the
-                                 skipped suffix is checked when the walk reaches it (the
-                                 walk goes on to the last set cell if that check fails).
+                                 the first entry and last exit; the skipped prefix and
+                                 suffix are checked against coarse_bits before the walk
+                                 (where a check fails, the walk starts at the first or
+                                 ends at the last set cell instead).
                                  Either way the image equals the plain render up to FP32
                                  rounding of the segment ends. */
     const uint32_t* coarse_bits; /* device [FPO_COARSE_WORDS] from fpo_coarse_occupancy of

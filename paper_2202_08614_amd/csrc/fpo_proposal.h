@@ -91,33 +91,6 @@ __device__ inline float coarse_scan(const uint32_t* __restrict__ bits, const flo
     return t_max;
 }
 
-// Stop hook for the walk: when the walk reaches the predicted exit, scan the
-// rest of the chord backwards from the cube exit; stop if it is clear, else
-// walk on to the exit of the last set cell.
-struct VerifyTail {
-    const uint32_t* bits;
-    const Ray& r;     // the walk's ray: r.o its start, r.t_len its length to the cube exit
-    bool done;
-
-    __device__ inline bool more(float t_exit, float& t_end)
-    {
-        if (done) return false;
-        done = true;
-        const float span = r.t_len - t_exit;
-        if (!(span > 0.0f)) return false;
-        float pe[3], nd[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            pe[c] = fmaf(r.t_len, r.d[c], r.o[c]);
-            nd[c] = -r.d[c];
-        }
-        const float u = coarse_scan(bits, pe, nd, span);
-        if (u >= span) return false;
-        t_end = r.t_len - u;
-        return true;
-    }
-};
-
 // Inputs of one ray: entry point, unit direction, tau.
 __device__ inline void proposal_inputs(const Ray& r, float tau, float* x)
 {
@@ -146,13 +119,13 @@ __device__ inline f16x4 relu_h(f32x4 v)
 // this lane's 7 inputs; out receives this lane's 3 outputs.  Features are the
 // rows (M) of each product and the wave's 64 rays its columns (N), so each
 // layer's accumulator tile is, lane for lane, the next layer's B operand.
-__device__ inline void mlp_infer_wave(const unsigned char* __restrict__ packed, const float* x, float* out)
+// F: the 44 fragments ([fragment][lane]); bias: the 132 FP32 biases (either
+// may point to global memory or to an LDS copy).
+__device__ inline void mlp_infer_wave(const uint2* F, const float* bias, const float* x, float* out)
 {
     const int ln = threadIdx.x & 63;
     const int q = ln >> 4;
     const int j = ln & 15;
-    const uint2* F = reinterpret_cast<const uint2*>(packed);
-    const float* bias = reinterpret_cast<const float*>(packed + kPackedBias);
 
     // inputs of the rays 16 nt + j this lane supplies B-operand values for
     float xin[4][kMlpIn];

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void mlp_infer_kernel(const unsigned char* 
 #pragma unroll
     for (int c = 0; c < kMlpIn; ++c) x[c] = live ? X[r * kMlpIn + c] : 0.0f;
     float o[3];
-    mlp_infer_wave(packed, x, o);
+    mlp_infer_wave(reinterpret_cast<const uint2*>(packed), reinterpret_cast<const float*>(packed + kPackedBias), x, o);
     if (live)
 #pragma unroll
         for (int e = 0; e < 3; ++e) out[r * 3 + e] = o[e];

@@ -60,72 +60,101 @@ __device__ inline int xcd_band(int bid, int nblocks)
     return (bid & 7) * per + (bid >> 3);
 }
 
-// Skip pre-pass.  Coarse variant: the walk runs from the first to the last
-// set coarse cell on the chord (both found by scans, so both are proven).
-// Proposal variant: the MLP's entry guess is accepted if the coarse scan up to
-// it is clear, else the walk starts at the first set cell the scan met; a
-// predicted miss is accepted only if the whole chord is clear.  The predicted
-// exit is checked by the render when its walk gets there (VerifyTail).
-// (inf, inf) marks a ray with nothing to walk.
+// Skip pre-pass: per pixel, a part of the chord [t_start, t_end] outside
+// which the ray provably meets no leaf.  Coarse variant: the first and last
+// set coarse cells on the chord (a forward and a backward scan).  Proposal
+// variant: the network's entry guess is accepted if the scan up to it is
+// clear, else the walk starts at the first set cell that scan met; its exit
+// guess is accepted if the backward scan from the cube exit down to it is
+// clear, else the walk ends at the exit of the last set cell; a predicted
+// miss is checked like the coarse variant.  (inf, inf) marks a ray with
+// nothing to walk.
+//
+// The proposal variant keeps the network's fragments in LDS and loops over
+// tiles (grid-stride, XCD-banded), so each block reads the weights once.
 template <bool MLP>
 __global__ __launch_bounds__(kBlock) void skip_prepass_kernel(SkipLaunch a)
 {
-    const int lin = xcd_band(blockIdx.x, gridDim.x);
-    if (lin >= a.n_cams * a.blocks_per_cam) return;   // whole blocks: every wave stays complete
-    const int ci = lin / a.blocks_per_cam;
-    const int tb = lin - ci * a.blocks_per_cam;
-    const int bx = tb % a.bx_per_cam;
-    const int by = tb / a.bx_per_cam;
-    const int wv = threadIdx.x >> 6;
-    const int ln = threadIdx.x & 63;
-    const int px = bx * 16 + (wv & 1) * 8 + (ln & 7);
-    const int py = by * 16 + (wv >> 1) * 8 + (ln >> 3);
-    const bool inside = px < a.W && py < a.H;
-    const float* fr = a.frame[ci];
-    const float sx = (float)(2 * px + 1 - a.W) / (float)a.W;
-    const float sy = (float)(a.H - 2 * py - 1) / (float)a.H;
-    const float dx = fr[3] + sx * fr[6] + sy * fr[9];
-    const float dy = fr[4] + sx * fr[7] + sy * fr[10];
-    const float dz = fr[5] + sx * fr[8] + sy * fr[11];
-    Ray r;
-    const bool ok = setup_ray(fr[0], fr[1], fr[2], dx, dy, dz, r) && inside;
-    float ts = __builtin_inff(), te = __builtin_inff();
-    float o3[3] = {0.0f, 0.0f, 0.0f};
+    __shared__ uint2 s_frag[MLP ? kFrags * 64 : 1];
+    __shared__ float s_bias[MLP ? 132 : 1];
     if constexpr (MLP) {
-        float x[kMlpIn];
-        proposal_inputs(r, a.tau[ci], x);
-        if (!ok)
-            for (int c = 0; c < kMlpIn; ++c) x[c] = 0.0f;
-        mlp_infer_wave(a.packed, x, o3);     // wave-wide: every lane is still active here
+        const uint2* F = reinterpret_cast<const uint2*>(a.packed);
+        for (int i = threadIdx.x; i < kFrags * 64; i += kBlock) s_frag[i] = F[i];
+        if (threadIdx.x < 132) s_bias[threadIdx.x] = reinterpret_cast<const float*>(a.packed + kPackedBias)[threadIdx.x];
+        __syncthreads();
     }
-    if (ok) {
-        const float len = r.t_len;
-        if (!MLP || !(o3[0] > 0.0f)) {
-            const float f = coarse_scan(a.bits, r.o, r.d, len);
-            if (f < len) {
-                ts = f;
-                te = len;
-                if (!MLP) {
-                    float pe[3], nd[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        pe[c] = fmaf(len, r.d[c], r.o[c]);
-                        nd[c] = -r.d[c];
-                    }
-                    te = len - coarse_scan(a.bits, pe, nd, len - f);
-                }
-            }
-        } else {
-            const float s_in = sigmoidf_(o3[1]);
-            const float s_out = sigmoidf_(o3[2]);
-            ts = coarse_scan(a.bits, r.o, r.d, s_in * len);
-            te = fmaxf(s_out * len, ts);
+    const int total = a.n_cams * a.blocks_per_cam;
+    const int padded = (total + 7) / 8 * 8;
+    for (int it = blockIdx.x; it < padded; it += gridDim.x) {
+        const int lin = xcd_band(it, padded);
+        if (lin >= total) continue;                     // whole blocks: every wave stays complete
+        const int ci = lin / a.blocks_per_cam;
+        const int tb = lin - ci * a.blocks_per_cam;
+        const int bx = tb % a.bx_per_cam;
+        const int by = tb / a.bx_per_cam;
+        const int wv = threadIdx.x >> 6;
+        const int ln = threadIdx.x & 63;
+        const int px = bx * 16 + (wv & 1) * 8 + (ln & 7);
+        const int py = by * 16 + (wv >> 1) * 8 + (ln >> 3);
+        const bool inside = px < a.W && py < a.H;
+        const float* fr = a.frame[ci];
+        const float sx = (float)(2 * px + 1 - a.W) / (float)a.W;
+        const float sy = (float)(a.H - 2 * py - 1) / (float)a.H;
+        const float dx = fr[3] + sx * fr[6] + sy * fr[9];
+        const float dy = fr[4] + sx * fr[7] + sy * fr[10];
+        const float dz = fr[5] + sx * fr[8] + sy * fr[11];
+        Ray r;
+        const bool ok = setup_ray(fr[0], fr[1], fr[2], dx, dy, dz, r) && inside;
+        float ts = __builtin_inff(), te = __builtin_inff();
+        float o3[3] = {0.0f, 0.0f, 0.0f};
+        if constexpr (MLP) {
+            float x[kMlpIn];
+            proposal_inputs(r, a.tau[ci], x);
+            if (!ok)
+                for (int c = 0; c < kMlpIn; ++c) x[c] = 0.0f;
+            mlp_infer_wave(s_frag, s_bias, x, o3);      // wave-wide: every lane is active here
         }
+        if (ok) {
+            const float len = r.t_len;
+            if (!MLP || !(o3[0] > 0.0f)) {
+                const float f = coarse_scan(a.bits, r.o, r.d, len);
+                if (f < len) {
+                    ts = f;
+                    te = len;
+                    if (!MLP) {
+                        float pe[3], nd[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            pe[c] = fmaf(len, r.d[c], r.o[c]);
+                            nd[c] = -r.d[c];
+                        }
+                        te = len - coarse_scan(a.bits, pe, nd, len - f);
+                    }
+                }
+            } else {
+                // entry: accept the guess if the chord up to it is clear;
+                // exit: accept the guess if the chord after it is clear, else
+                // take the exit of the last set cell
+                const float s_in = sigmoidf_(o3[1]);
+                const float s_out = sigmoidf_(o3[2]);
+                ts = coarse_scan(a.bits, r.o, r.d, s_in * len);
+                const float span = len - fmaxf(s_out * len, ts);
+                float pe[3], nd[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    pe[c] = fmaf(len, r.d[c], r.o[c]);
+                    nd[c] = -r.d[c];
+                }
+                te = span > 0.0f ? len - coarse_scan(a.bits, pe, nd, span) : len;
+            }
+        }
+        if (inside) a.skip[((int64_t)ci * a.H + py) * a.W + px] = make_float2(ts, te);
     }
-    if (inside) a.skip[((int64_t)ci * a.H + py) * a.W + px] = make_float2(ts, te);
 }
 
-template <int MODE, int SKIP>
+// SKIP: walk only the proven part [t_start, t_end] of each chord that the
+// skip pre-pass left in a.skip.
+template <int MODE, bool SKIP>
 __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
 {
     __shared__ int s_stack[kStackLevels * kBlock];
@@ -160,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
     const int64_t pix = ((int64_t)ci * a.H + py) * a.W + px;
     if (setup_ray(cam.frame[0], cam.frame[1], cam.frame[2], dx, dy, dz, r)) {
         sh9(r.d[0], r.d[1], r.d[2], sh.Y);
-        if constexpr (SKIP == 0) {
+        if constexpr (!SKIP) {
             walk(a.tree, r, s_stack + threadIdx.x, sh);
         } else {
             const float2 se = a.skip[pix];
@@ -168,13 +197,8 @@ __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) r.o[c] = fmaf(se.x, r.d[c], r.o[c]);
                 r.t_len -= se.x;
-                if constexpr (SKIP == FPO_RENDER_SKIP_COARSE) {
-                    NoStop ns;
-                    walk(a.tree, r, s_stack + threadIdx.x, sh, se.y - se.x, ns);
-                } else {
-                    VerifyTail vt{a.bits, r, false};
-                    walk(a.tree, r, s_stack + threadIdx.x, sh, se.y - se.x, vt);
-                }
+                NoStop ns;
+                walk(a.tree, r, s_stack + threadIdx.x, sh, se.y - se.x, ns);
             }
         }
     }
@@ -345,12 +369,10 @@ using namespace fpo;
 template <int MODE>
 static void launch_cam(const dev::CamLaunch& a, int grid, int skip, hipStream_t s)
 {
-    if (skip == FPO_RENDER_SKIP_COARSE)
-        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, FPO_RENDER_SKIP_COARSE>), dim3(grid), dim3(dev::kBlock), 0, s, a);
-    else if (skip == FPO_RENDER_SKIP_PROPOSAL)
-        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, FPO_RENDER_SKIP_PROPOSAL>), dim3(grid), dim3(dev::kBlock), 0, s, a);
+    if (skip != 0)
+        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, true>), dim3(grid), dim3(dev::kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, 0>), dim3(grid), dim3(dev::kBlock), 0, s, a);
+        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, false>), dim3(grid), dim3(dev::kBlock), 0, s, a);
 }
 
 extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
@@ -425,7 +447,7 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
             a.skip = sk.skip;
             a.bits = opts->coarse_bits;
             if (skip == FPO_RENDER_SKIP_PROPOSAL)
-                hipLaunchKernelGGL(dev::skip_prepass_kernel<true>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
+                hipLaunchKernelGGL(dev::skip_prepass_kernel<true>, dim3(std::min(grid, 1024)), dim3(dev::kBlock), 0, s, sk);
             else
                 hipLaunchKernelGGL(dev::skip_prepass_kernel<false>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
             if ((st = launch_status("fpo_render (skip pre-pass)")) != FPO_OK) return st;
