@@ -49,6 +49,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# HBM traffic of the render kernels, measured with rocprofv3 --pmc (FETCH_SIZE,
+# WRITE_SIZE) and scaled by the counters' reading on a plain copy; valid only
+# for the sources it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
+RENDER_SOURCES = ["include/fpo.h", "paper_2202_08614_amd/csrc/fpo_device.h", "paper_2202_08614_amd/csrc/fpo_render.hip",
+                  "paper_2202_08614_amd/csrc/fpo_proposal.h", "paper_2202_08614_amd/csrc/fpo_internal.h"]
+
+
+def render_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in RENDER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch of `kernel_key` from the committed counter
+    summary, or None if there is none for the current sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != render_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel_key)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
 def bake_leg(dev, sc, tree, oracle_mod, n_t: int = 64, reps: int = 5):
     """Precision + MFMA bake on the 2M-leaf scene: quantise to BF16, bake 64
     times with fpo_bake_times into BF16 snapshots (7.2 GB), render 64 views at
@@ -301,7 +332,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=300000, help="rays rendered by the oracle for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=2000000,
+                    help="rays rendered by the oracle (quality check and CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-finetune", action="store_true")
     ap.add_argument("--no-bake", action="store_true")
@@ -469,10 +501,13 @@ def main():
         flop_ray = FLOP_PER_RAY + FLOP_SIGMA * (seg - opq).mean() + FLOP_OPAQUE * opq.mean()
         gather_ray = BYTES_SIGMA_WORDS * (seg - opq).mean() + BYTES_LEAF * opq.mean()
         kernel = "render_cam_kernel<F32> (per-sample IDFT)"
+        kernel_key = "render_cam_kernel<0, false>"
     else:
         flop_ray = FLOP_PER_RAY + FLOP_SNAP_SIGMA * (seg - opq).mean() + FLOP_SNAP_OPAQUE * opq.mean()
         gather_ray = 16 * (seg - opq).mean() + 128 * opq.mean()
         kernel = "render_cam_kernel<snapshot F32> (after a per-leaf IDFT pass)"
+        kernel_key = "render_cam_kernel<16, false>"
+    traffic = measured_traffic(kernel_key)
     flop_launch = flop_ray * rays_launch
     achieved_tflops = flop_launch / (launch_ms * 1e-3) / 1e12
     gather_gbps = gather_ray * rays_launch / (launch_ms * 1e-3) / 1e9
@@ -519,7 +554,8 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": kernel,
             "launch_ms": round(launch_ms, 4),
             "flop_per_launch": flop_launch,

@@ -135,7 +135,7 @@ struct Ray {
     float t_len;    // length inside the cube
 };
 
-__device__ inline bool setup_ray(float ox, float oy, float oz, float dx, float dy, float dz, Ray& r)
+__host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx, float dy, float dz, Ray& r)
 {
     const float n2 = dx * dx + dy * dy + dz * dz;
     if (!(n2 > 0.0f)) return false;
@@ -170,80 +170,84 @@ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx, float d
 // --------------------------------------------------------------------------
 // Sparse octree walk.
 //
-// The walk keeps the ray's current cell on the finest lattice (G = 2^D cells
-// per axis) and the chain of internal nodes above it (a per-lane stack in
-// LDS).  Each step descends from the deepest node that still contains the
-// cell to the leaf or empty child holding it, reports the leaf segment
-// [t_cur, t_exit), and steps to the neighbouring cell across the exit face:
-// the exit axis moves by one lattice cell past the face, the other axes are
-// re-derived from the exit point and clamped into the cell just left (so the
-// walk is monotone and ends within 3G steps).  Exit-axis ties break x < y < z.
+// Every axis the ray runs down is mirrored (lattice coordinate x -> G - x,
+// octant bit flipped), so that in the walk's frame all direction components
+// are >= 0 and a cell is always left through its upper faces.  The walk keeps
+// the chain of internal nodes above the current cell (a per-lane stack in
+// LDS) and the cell's corner on the finest lattice (G = 2^D cells per axis).
+// One iteration:
+//   - descend while the current slot holds an internal node, taking the child
+//     whose half the ray is in at t_cur on each axis (t_cur against the time
+//     the ray crosses the node's centre plane);
+//   - report a leaf segment [t_cur, t_exit), t_exit the first upper face the
+//     ray reaches (ties x < y < z);
+//   - step to the neighbouring slot of the same size across that face (the
+//     other coordinates are unchanged) and pop to the deepest node that still
+//     contains it, found from the highest bit the step changed.
+// Each step moves the exit axis forward by a whole slot and never moves any
+// axis back, so the walk ends within 3G steps.  Rays parallel to an axis use a
+// tiny direction instead of zero: their crossing times on that axis exceed
+// any chord.
 //
 // Visitor: bool segment(int leaf, float t0, float t1) returns true to stop.
 // Distances are measured from the entry point r.o.  With a stop distance
 // t_end the walk consults stop.more() once a step ends at or past t_end.
 // --------------------------------------------------------------------------
-// Stop hook of the walk: called when a step's exit distance reaches t_end;
-// returns true (after possibly raising t_end) to keep walking.
 struct NoStop {
-    __device__ inline bool more(float, float&) { return false; }
+    __host__ __device__ inline bool more(float, float&) { return false; }
 };
 
 template <class Visitor, class Stop>
-__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop);
-
-template <class Visitor>
-__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
-{
-    NoStop ns;
-    walk(T, r, stk, vis, __builtin_inff(), ns);
-}
-
-template <class Visitor, class Stop>
-__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop)
+__host__ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop)
 {
     const int D = T.max_depth;
     const int G = 1 << D;
     const float fG = (float)G;
-    const float invG = 1.0f / fG;
-    int c[3];
+    int mirror = 0;
+    float xf[3], k[3];   // entry point in (mirrored) lattice units; time per lattice unit
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int v = (int)floorf(r.o[a] * fG);
-        c[a] = min(max(v, 0), G - 1);
+        const bool neg = r.d[a] < 0.0f;
+        mirror |= (neg ? 1 : 0) << a;
+        const float da = fmaxf(fabsf(r.d[a]), 1e-20f);
+        k[a] = 1.0f / (da * fG);
+        const float p = r.o[a] * fG;
+        xf[a] = neg ? fG - p : p;
     }
     int lvl = 0;
     int node = 0;
     stk[0] = 0;
     float t_cur = 0.0f;
+    int pos[3];          // corner of the current slot (a child of stk[lvl]), mirrored lattice
+    {
+        const int S = G >> 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) pos[a] = ((float)S - xf[a]) * k[a] <= t_cur ? S : 0;
+    }
     const int max_steps = 3 * G + 4;
     for (int it = 0; it < max_steps; ++it) {
         int ch;
+        int csh;
         for (;;) {
-            const int sh = D - 1 - lvl;
-            const int oct = ((c[0] >> sh) & 1) | (((c[1] >> sh) & 1) << 1) | (((c[2] >> sh) & 1) << 2);
+            csh = D - 1 - lvl;
+            const int oct = (((pos[0] >> csh) & 1) | (((pos[1] >> csh) & 1) << 1) | (((pos[2] >> csh) & 1) << 2)) ^ mirror;
             ch = T.children[node * 8 + oct];
             if (ch > 0 && ch < T.n_nodes && lvl < D - 1) {
                 ++lvl;
                 node = ch;
                 stk[lvl * kBlock] = node;
+                const int S = 1 << (csh - 1);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pos[a] += ((float)(pos[a] + S) - xf[a]) * k[a] <= t_cur ? S : 0;
                 continue;
             }
             if (ch > 0) ch = 0;   // malformed table: treat as empty
             break;
         }
-        const int csh = D - 1 - lvl;
         const int size = 1 << csh;
-        int lo[3];
         float te[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = c[a] & ~(size - 1);
-            // exit face of this axis: the cell's upper face when moving up, lower when down
-            const int face = r.d[a] > 0.0f ? lo[a] + size : lo[a];
-            const float tf = ((float)face * invG - r.o[a]) * r.inv[a];
-            te[a] = r.d[a] == 0.0f ? __builtin_inff() : tf;
-        }
+        for (int a = 0; a < 3; ++a) te[a] = ((float)(pos[a] + size) - xf[a]) * k[a];
         int ax = 0;
         float t_exit = te[0];
         if (te[1] < t_exit) { t_exit = te[1]; ax = 1; }
@@ -254,30 +258,29 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
             if (leaf < T.n_leaves && vis.segment(leaf, t_cur, t_exit)) return;
         }
         if (t_exit >= t_end && !stop.more(t_exit, t_end)) return;
-        int nc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            // other axes: lattice cell of the exit point, clamped into the cell
-            // just left and never moving against the ray
-            int v = (int)floorf(fmaf(t_exit, r.d[a], r.o[a]) * fG);
-            v = min(max(v, lo[a]), lo[a] + size - 1);
-            v = r.d[a] > 0.0f ? max(v, c[a]) : min(v, c[a]);
-            v = r.d[a] == 0.0f ? c[a] : v;
-            // exit axis: one lattice cell past the face
-            const int step = r.d[a] > 0.0f ? lo[a] + size : lo[a] - 1;
-            nc[a] = a == ax ? step : v;
-        }
-        if (nc[ax] < 0 || nc[ax] >= G) return;
-        const unsigned diff = (unsigned)((c[0] ^ nc[0]) | (c[1] ^ nc[1]) | (c[2] ^ nc[2]));
-        const int h = 31 - __builtin_clz(diff);
-        const int keep = D - 1 - h;     // deepest stack level still containing the new cell
+        const int old = ax == 0 ? pos[0] : ax == 1 ? pos[1] : pos[2];
+        const int nw = old + size;
+        if (nw >= G) return;
+        const int h = 31 - __builtin_clz((unsigned)(old ^ nw));
+        const int keep = D - 1 - h;     // deepest stack level whose node contains the new slot
+        pos[0] = ax == 0 ? nw : pos[0];
+        pos[1] = ax == 1 ? nw : pos[1];
+        pos[2] = ax == 2 ? nw : pos[2];
         if (keep < lvl) {
             lvl = keep;
             node = stk[lvl * kBlock];
+            const int m = ~((1 << h) - 1);
+            pos[0] &= m; pos[1] &= m; pos[2] &= m;
         }
-        c[0] = nc[0]; c[1] = nc[1]; c[2] = nc[2];
         t_cur = t_exit;
     }
+}
+
+template <class Visitor>
+__host__ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
+{
+    NoStop ns;
+    walk(T, r, stk, vis, __builtin_inff(), ns);
 }
 
 // --------------------------------------------------------------------------
