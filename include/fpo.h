@@ -81,6 +81,8 @@ typedef enum { FPO_F32 = 0, FPO_BF16 = 1, FPO_FP8_E4M3 = 2 } fpo_dtype;
 #define FPO_MLP_PACKED_BYTES 23056 /* FP16 matrix-core fragments + FP32 biases */
 #define FPO_COARSE_RES 64
 #define FPO_COARSE_WORDS 8192      /* 64^3 bits */
+#define FPO_MAX_FRAMES 256         /* frames per fpo_dft_frames call */
+#define FPO_PRUNE_SIGMA 1e-3f      /* Sec. 3: leaves below this density are dropped */
 #define FPO_RENDER_SKIP_COARSE 1   /* fpo_render_opts.flags */
 #define FPO_RENDER_SKIP_PROPOSAL 2
 
@@ -296,6 +298,63 @@ fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stri
  *           fpo_render / fpo_render_rays with snapshot_cam_stride = leaf_stride. */
 fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t, fpo_dtype out_dtype,
                           void* out, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Building a Fourier PlenOctree from per-frame PlenOctrees (Sec. 4.2)      */
+/* ---------------------------------------------------------------------- */
+/* Frames t = 0 .. T-1 sit at times t of Eq. 8 with period T (the basis is
+ * T-periodic, so this is the paper's t = 1 .. T).  Per-frame values travel
+ * as snapshot records (see above): 32 F32 values per leaf, value 0 = sigma,
+ * 1 + c*9 + j = z_{c,j}, 28..31 zero.  Every tree involved (frames and
+ * union) is built with the same max_depth. */
+
+/* Leaves of the union of per-frame octree structures (Sec. 4.2: the union
+ * has equal or deeper leaves than every frame).  A cell is a union leaf if no
+ * given cell lies strictly inside it, some given cell covers it (itself or an
+ * ancestor), and its parent is split.  Host call.
+ *   leaf_dijk host [n_cells][4] (depth, i, j, k): the leaves of all frames,
+ *             concatenated (duplicates allowed).
+ *   union_out host [cap][4], Morton order, or NULL to query the count.
+ * FPO_E_INVALID as for fpo_build_tree's range checks; FPO_E_CAPACITY if
+ * cap < count (the count is still written). */
+fpo_status fpo_union_leaves(const int32_t* leaf_dijk, int64_t n_cells, int32_t max_depth,
+                            int32_t* union_out, int64_t cap, int64_t* n_union_out);
+
+/* One frame's values on the union leaves (Sec. 4.2: a leaf divided in the
+ * union copies the value of the frame leaf it lies in; a union leaf the
+ * frame leaves empty gets zeros).
+ *   frame_tree   the frame's own tree (fpo_build_tree of its leaves); only
+ *                children, n_nodes, max_depth and n_leaves are read.
+ *   frame_perm   device [frame leaves] int64, the perm of that build.
+ *   frame_values device [frame leaves][32] F32 snapshot records, caller order.
+ *   union_cells  device [n_union][4] int32 (depth, i, j, k) of the union
+ *                leaves in the union tree's slot order.
+ *   out          device [n_union][32] F32 snapshot records.
+ *   n_bad        device [1] int32, incremented for every union cell that does
+ *                not refine the frame (the frame is split below it); such
+ *                cells get zeros. */
+fpo_status fpo_frame_values(const fpo_tree_view* frame_tree, const int64_t* frame_perm,
+                            const float* frame_values, const int32_t* union_cells, int64_t n_union,
+                            float* out, int32_t* n_bad, void* stream);
+
+/* Per-leaf DFT of Eq. 10-12: k_i = c_i sum_{t<T} x(t) IDFT_i(t) for the
+ * density (i < 31) and every SH coefficient (i < 5), with c_0 = 1/T and
+ * c_i = 2/T for i >= 1 (the least-squares projection onto Eq. 8, exact for
+ * band-limited values), or the printed c_i = 1/T for every i if literal.
+ *   frames      device [n_frames][leaf_stride][32] F32 snapshot records,
+ *               16-byte aligned; 1 <= n_frames <= FPO_MAX_FRAMES.
+ *   coeffs_out  device F32 leaf records ([leaf_stride][48] words), slots
+ *               < n_leaves written (padding zero).
+ *   sigma_max_out device [leaf_stride] F32 max_t sigma(t), or NULL (for
+ *               pruning). */
+fpo_status fpo_dft_frames(const float* frames, int32_t n_frames, int64_t n_leaves, int64_t leaf_stride,
+                          int32_t literal, float* coeffs_out, float* sigma_max_out, void* stream);
+
+/* Leaves to keep after fusion (Sec. 3: leaves with sigma < 1e-3 are
+ * filtered out): indices l with sigma_max[l] >= threshold, ascending.  Host.
+ *   keep_out host [n_leaves] int64; n_keep_out receives the count. */
+fpo_status fpo_prune_leaves(const float* sigma_max, int64_t n_leaves, float threshold, int64_t* keep_out,
+                            int64_t* n_keep_out);
 
 /* ---------------------------------------------------------------------- */
 /* Learned proposal (not in the paper)                                      */

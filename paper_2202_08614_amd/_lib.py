@@ -100,6 +100,10 @@ _SIGS = {
     "fpo_mlp_loss_grad": [_P, _P, _P, _P, _I64, _P, _P, _P, _P],
     "fpo_mlp_pack": [_P, _P, _P],
     "fpo_mlp_infer": [_P, _P, _I64, _P, _P],
+    "fpo_union_leaves": [_P, _I64, _I32, _P, _I64, _P],
+    "fpo_frame_values": [ctypes.POINTER(TreeView), _P, _P, _P, _I64, _P, _P, _P],
+    "fpo_dft_frames": [_P, _I32, _I64, _I64, _I32, _P, _P, _P],
+    "fpo_prune_leaves": [_P, _I64, ctypes.c_float, _P, _P],
 }
 # functions with another return type
 _OTHER = {"fpo_mlp_workspace_floats": ([_I64], ctypes.c_int64)}
@@ -463,3 +467,72 @@ def mlp_infer(packed, inputs, out=None):
     out = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=inputs.device)
     _check(lib().fpo_mlp_infer(_t_ptr(packed), _t_ptr(inputs), n, _t_ptr(out), _stream()))
     return out
+
+
+# ---------------------------------------------------------------------------
+# building an FPO from per-frame octrees
+# ---------------------------------------------------------------------------
+MAX_FRAMES = 256
+PRUNE_SIGMA = 1e-3
+
+
+def union_leaves(cells: np.ndarray, max_depth: int) -> np.ndarray:
+    """fpo_union_leaves -> [n_union][4] int32 (Morton order)."""
+    c = np.ascontiguousarray(cells, dtype=np.int32)
+    n = ctypes.c_int64(0)
+    _check(lib().fpo_union_leaves(_np_ptr(c), int(c.shape[0]), int(max_depth), None, 0, ctypes.byref(n)))
+    out = np.zeros((n.value, 4), dtype=np.int32)
+    _check(lib().fpo_union_leaves(_np_ptr(c), int(c.shape[0]), int(max_depth), _np_ptr(out), n.value,
+                                  ctypes.byref(n)))
+    return out
+
+
+class FrameTree:
+    """Structure of one frame's octree on the device (no coefficients)."""
+
+    def __init__(self, leaf_dijk: np.ndarray, max_depth: int, device):
+        import torch
+        children, perm = build_tree(leaf_dijk, max_depth)
+        self.children = torch.from_numpy(children).to(device)
+        self.perm = torch.from_numpy(perm).to(device)
+        self.n_nodes = children.shape[0]
+        self.n_leaves = int(leaf_dijk.shape[0])
+        self.max_depth = int(max_depth)
+
+    def view(self) -> TreeView:
+        v = TreeView()
+        v.children = self.children.data_ptr()
+        v.n_nodes = self.n_nodes
+        v.max_depth = self.max_depth
+        v.n_leaves = self.n_leaves
+        v.leaf_stride = self.n_leaves
+        v.layout = make_layout()
+        return v
+
+
+def frame_values(frame: FrameTree, values, union_cells_slot, out, n_bad):
+    """fpo_frame_values: values [n_f][32] (caller order) onto the union slots."""
+    tv = frame.view()
+    _check(lib().fpo_frame_values(ctypes.byref(tv), _t_ptr(frame.perm), _t_ptr(values), _t_ptr(union_cells_slot),
+                                  int(union_cells_slot.shape[0]), _t_ptr(out), _t_ptr(n_bad), _stream()))
+
+
+def dft_frames(frames, n_leaves: int, literal: bool = False, coeffs=None, sigma_max=None):
+    """fpo_dft_frames: frames [T][stride][32] -> (F32 records [stride][48][4], sigma_max [stride])."""
+    import torch
+    T, stride = int(frames.shape[0]), int(frames.shape[1])
+    if coeffs is None:
+        coeffs = torch.zeros((stride, record_words(FPO_F32), 4), dtype=torch.float32, device=frames.device)
+    if sigma_max is None:
+        sigma_max = torch.zeros((stride,), dtype=torch.float32, device=frames.device)
+    _check(lib().fpo_dft_frames(_t_ptr(frames), T, int(n_leaves), stride, 1 if literal else 0, _t_ptr(coeffs),
+                                _t_ptr(sigma_max), _stream()))
+    return coeffs, sigma_max
+
+
+def prune_leaves(sigma_max: np.ndarray, threshold: float = PRUNE_SIGMA) -> np.ndarray:
+    sm = np.ascontiguousarray(sigma_max, dtype=np.float32)
+    keep = np.zeros(sm.shape[0], dtype=np.int64)
+    n = ctypes.c_int64(0)
+    _check(lib().fpo_prune_leaves(_np_ptr(sm), int(sm.shape[0]), float(threshold), _np_ptr(keep), ctypes.byref(n)))
+    return keep[:n.value]

@@ -22,6 +22,7 @@ SOURCES = [
     "fpo_train.hip",
     "fpo_bake.hip",
     "fpo_proposal.hip",
+    "fpo_construct.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

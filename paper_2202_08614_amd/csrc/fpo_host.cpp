@@ -231,6 +231,99 @@ extern "C" fpo_status fpo_build_tree(const int32_t* leaf_dijk, int64_t n_leaves,
     }
 }
 
+// Union leaves over Morton-sorted cells: a cell with no cell strictly inside
+// it is a union leaf if some cell covers it (itself or an ancestor); else it
+// splits into its eight children.
+namespace {
+struct Cell {
+    uint64_t code;   // Morton code of the min corner on the finest lattice
+    int32_t depth;
+};
+
+void union_rec(const std::vector<Cell>& cs, size_t a, size_t b, int d, uint64_t code, int D, bool covered,
+               std::vector<Cell>& out)
+{
+    // cs[a, b): cells with code in [code, code + 8^(D-d)) and depth >= d
+    while (a < b && cs[a].depth == d && cs[a].code == code) {
+        covered = true;
+        ++a;
+    }
+    if (a == b) {
+        if (covered && d > 0) out.push_back({code, d});
+        return;
+    }
+    const uint64_t child = uint64_t(1) << (3 * (D - d - 1));
+    size_t lo = a;
+    for (int o = 0; o < 8; ++o) {
+        const uint64_t end = code + (uint64_t)(o + 1) * child;
+        size_t hi = lo;
+        while (hi < b && cs[hi].code < end) ++hi;
+        union_rec(cs, lo, hi, d + 1, code + (uint64_t)o * child, D, covered, out);
+        lo = hi;
+    }
+}
+
+uint64_t compact3(uint64_t v)
+{
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> (3 * b)) & 1ull) << b;
+    return r;
+}
+}  // namespace
+
+extern "C" fpo_status fpo_union_leaves(const int32_t* leaf_dijk, int64_t n_cells, int32_t max_depth,
+                                       int32_t* union_out, int64_t cap, int64_t* n_union_out)
+{
+    try {
+        if (!leaf_dijk || !n_union_out) return fail(FPO_E_INVALID, "NULL argument");
+        if (n_cells < 1) return fail(FPO_E_INVALID, "n_cells must be >= 1");
+        if (max_depth < 1 || max_depth > FPO_MAX_DEPTH) return fail(FPO_E_INVALID, "max_depth must be in 1..10");
+        const int D = max_depth;
+        std::vector<Cell> cs((size_t)n_cells);
+        for (int64_t l = 0; l < n_cells; ++l) {
+            const int32_t d = leaf_dijk[4 * l], i = leaf_dijk[4 * l + 1], j = leaf_dijk[4 * l + 2],
+                          k = leaf_dijk[4 * l + 3];
+            if (d < 1 || d > D) return fail(FPO_E_INVALID, "cell " + std::to_string(l) + ": depth out of range");
+            const int64_t g = int64_t(1) << d;
+            if (i < 0 || j < 0 || k < 0 || i >= g || j >= g || k >= g)
+                return fail(FPO_E_INVALID, "cell " + std::to_string(l) + ": coordinate out of range");
+            const int sh = D - d;
+            cs[(size_t)l] = {spread3((uint64_t)i << sh) | (spread3((uint64_t)j << sh) << 1) | (spread3((uint64_t)k << sh) << 2), d};
+        }
+        std::sort(cs.begin(), cs.end(), [](const Cell& x, const Cell& y) {
+            return x.code < y.code || (x.code == y.code && x.depth < y.depth);
+        });
+        std::vector<Cell> out;
+        union_rec(cs, 0, cs.size(), 0, 0, D, false, out);
+        *n_union_out = (int64_t)out.size();
+        if (!union_out) return FPO_OK;
+        if (cap < (int64_t)out.size()) return fail(FPO_E_CAPACITY, "union_out holds fewer than n_union rows");
+        for (size_t u = 0; u < out.size(); ++u) {
+            const int sh = D - out[u].depth;
+            union_out[4 * u] = out[u].depth;
+            union_out[4 * u + 1] = (int32_t)(compact3(out[u].code) >> sh);
+            union_out[4 * u + 2] = (int32_t)(compact3(out[u].code >> 1) >> sh);
+            union_out[4 * u + 3] = (int32_t)(compact3(out[u].code >> 2) >> sh);
+        }
+        return FPO_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(FPO_E_INVALID, "out of host memory");
+    }
+}
+
+extern "C" fpo_status fpo_prune_leaves(const float* sigma_max, int64_t n_leaves, float threshold, int64_t* keep_out,
+                                       int64_t* n_keep_out)
+{
+    if (!sigma_max || !keep_out || !n_keep_out) return fail(FPO_E_INVALID, "NULL argument");
+    if (n_leaves < 0) return fail(FPO_E_INVALID, "n_leaves < 0");
+    if (!std::isfinite(threshold)) return fail(FPO_E_INVALID, "threshold must be finite");
+    int64_t n = 0;
+    for (int64_t l = 0; l < n_leaves; ++l)
+        if (sigma_max[l] >= threshold) keep_out[n++] = l;
+    *n_keep_out = n;
+    return FPO_OK;
+}
+
 extern "C" fpo_status fpo_coarse_occupancy(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
                                            uint32_t* bits_out)
 {

@@ -353,3 +353,41 @@ def mlp_init(seed: int = 11) -> np.ndarray:
     flat = np.concatenate(parts)
     p[:flat.size] = flat
     return p
+
+
+# --------------------------------------------------------------------------
+# per-frame PlenOctrees (inputs of the FPO construction): the blob sampled at
+# every frame, standing in for the per-frame fusion results
+# --------------------------------------------------------------------------
+def blob_frame_leaves(depth: int, n_union: int, n_frames: int = 60, seed: int = GEOMETRY_SEED,
+                      merge_every: int = 4) -> List[np.ndarray]:
+    """Frame t holds the cells of the union iso set (`blob_leaves`) whose
+    density at t exceeds the same iso level; where all eight children of a
+    parent are present, frame t keeps the parent instead for one in
+    `merge_every` (parent, frame) pairs, so frames differ in depth and the
+    union splits their coarser leaves."""
+    params = blob_params(seed)
+    M = blob_max_field(depth, params, n_frames=n_frames).reshape(-1)
+    k = M.size - n_union
+    iso = np.partition(M, k)[k]
+    cells = blob_leaves(depth, n_union, seed, n_frames)
+    g = 1 << depth
+    x = (cells[:, 1:4].astype(np.float64) + 0.5) / g
+    out = []
+    for t in range(n_frames):
+        mu = 0.5 + params.A * np.sin(2.0 * math.pi * params.f[:, None] * t / PERIOD + params.phi)
+        rho = np.zeros(len(cells))
+        for gi in range(len(params.a)):
+            r2 = ((x - mu[gi]) ** 2).sum(1)
+            rho += params.a[gi] * np.exp(-r2 / (2.0 * params.w[gi] ** 2))
+        sel = cells[rho >= iso]
+        par = sel[:, 1:4] >> 1
+        key = (par[:, 0].astype(np.int64) * g + par[:, 1]) * g + par[:, 2]
+        uk, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+        h = (uk * 2654435761 + t * 40503) % merge_every
+        full = (cnt[inv] == 8) & (h[inv] == 0)
+        keep = sel[~full]
+        pk = np.unique(key[full])
+        pi = np.stack([np.full(len(pk), depth - 1), pk // (g * g), (pk // g) % g, pk % g], axis=1)
+        out.append(np.concatenate([keep, pi.astype(np.int32)]).astype(np.int32))
+    return out

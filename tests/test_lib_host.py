@@ -220,3 +220,28 @@ def test_skip_and_proposal_calls_validate_on_host():
     # workspace: feature rows for 64-ray chunks plus one partial per 1024 rays
     assert L.fpo_mlp_workspace_floats(1) == 344 * 64 + 9796
     assert L.fpo_mlp_workspace_floats(3000) == 344 * 3008 + 3 * 9796
+
+
+def test_union_leaves_match_oracle():
+    from oracle import dft
+    rng = np.random.default_rng(0)
+    for seed, depth in ((1, 4), (2, 6)):
+        frames = []
+        for f in range(6):
+            leaves = synth.random_tree_leaves(seed * 10 + f, depth, p_split=0.5)
+            frames.append(leaves[rng.random(len(leaves)) < 0.8])
+        got = _lib.union_leaves(np.concatenate(frames), depth + 1)
+        want = dft.union_leaves(frames)
+        assert set(map(tuple, got.tolist())) == set(want) and len(got) == len(want)
+    # duplicates and a leaf inside another are fine for the union
+    cells = np.array([[1, 0, 0, 0], [1, 0, 0, 0], [3, 1, 2, 3]], np.int32)
+    u = _lib.union_leaves(cells, 3)
+    assert set(map(tuple, u.tolist())) == set(dft.union_leaves([cells[:1], cells[1:]]))
+    with pytest.raises(_lib.FpoError):
+        _lib.union_leaves(np.array([[4, 0, 0, 0]], np.int32), 3)
+
+
+def test_prune_leaves():
+    sm = np.array([0.0, 2e-3, 1e-3, 5e-4, 7.0], np.float32)
+    assert list(_lib.prune_leaves(sm)) == [1, 2, 4]
+    assert list(_lib.prune_leaves(sm, 10.0)) == []
