@@ -81,7 +81,7 @@ typedef enum { FPO_F32 = 0, FPO_BF16 = 1, FPO_FP8_E4M3 = 2 } fpo_dtype;
 #define FPO_MLP_PACKED_BYTES 23056 /* FP16 matrix-core fragments + FP32 biases */
 #define FPO_COARSE_RES 64
 #define FPO_COARSE_WORDS 8192      /* 64^3 bits */
-#define FPO_MAX_FRAMES 256         /* frames per fpo_dft_frames call */
+#define FPO_MAX_FRAMES 120         /* frames per fpo_dft_frames call (LDS: basis + staged records < 64 KB) */
 #define FPO_PRUNE_SIGMA 1e-3f      /* Sec. 3: leaves below this density are dropped */
 #define FPO_RENDER_SKIP_COARSE 1   /* fpo_render_opts.flags */
 #define FPO_RENDER_SKIP_PROPOSAL 2

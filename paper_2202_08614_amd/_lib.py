@@ -472,7 +472,7 @@ def mlp_infer(packed, inputs, out=None):
 # ---------------------------------------------------------------------------
 # building an FPO from per-frame octrees
 # ---------------------------------------------------------------------------
-MAX_FRAMES = 256
+MAX_FRAMES = 120
 PRUNE_SIGMA = 1e-3
 
 

@@ -12,8 +12,10 @@
 // nine SH coefficients x 5 Fourier terms), so every wave runs one uniform code
 // path.  The weighted basis c_i IDFT_i(t) of all frames sits in LDS (c_0 = 1/T,
 // c_i = 2/T, or 1/T for every i with the printed weights), computed from exact
-// integer phases (i t mod 2T) with sinpi / cospi.  The kernel streams T
-// records per leaf and is bound by HBM reads.
+// integer phases (i t mod 2T) with sinpi / cospi.  The 64 records of a tile are
+// contiguous in every frame: the block stages 4 frames of them at a time into
+// LDS with whole-line loads, then each wave reads its values from there.  The
+// kernel streams T records per leaf and is bound by HBM reads.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -74,7 +76,6 @@ __global__ __launch_bounds__(kBlock) void frame_values_kernel(TreeDev ft, const 
     }
 }
 
-constexpr int kMaxFrames = FPO_MAX_FRAMES;
 
 struct DftLaunch {
     const float* frames;     // [T][stride][32]
@@ -85,10 +86,16 @@ struct DftLaunch {
     int32_t literal;
 };
 
+constexpr int kDftFrames = 4;     // frames staged per LDS pass
+constexpr int kRecPad = 33;       // LDS floats per staged record (32 + 1 against bank conflicts)
+
 __global__ __launch_bounds__(256) void dft_kernel(DftLaunch a)
 {
-    __shared__ float B[kMaxFrames][FPO_N_SIGMA + 1];
+    // dynamic LDS: basis [T][32] then the staged records [kDftFrames][64 * kRecPad]
+    extern __shared__ float lds[];
     const int T = a.T;
+    float (*B)[FPO_N_SIGMA + 1] = reinterpret_cast<float (*)[FPO_N_SIGMA + 1]>(lds);
+    float (*X)[64 * kRecPad] = reinterpret_cast<float (*)[64 * kRecPad]>(lds + T * (FPO_N_SIGMA + 1));
     for (int e = threadIdx.x; e < T * FPO_N_SIGMA; e += 256) {
         const int t = e / FPO_N_SIGMA, i = e % FPO_N_SIGMA;
         // Eq. 8 at t: cos(i pi t / T) (even i), sin((i + 1) pi t / T) (odd i), exact phase
@@ -100,60 +107,63 @@ __global__ __launch_bounds__(256) void dft_kernel(DftLaunch a)
         B[t][i] = c * v;
     }
     __syncthreads();
-    const int g = threadIdx.x >> 6;
+    const int g = threadIdx.x >> 6;          // wave: output group
+    const int ll = threadIdx.x & 63;         // leaf within the tile
+    const int q0 = 9 * (g - 1);              // SH coefficients q0 .. q0 + 8 (g >= 1), record values 1 + q
     const int64_t n_tiles = (a.n_leaves + 63) / 64;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t l = tile * 64 + (threadIdx.x & 63);
-        if (l >= a.n_leaves) continue;
-        float* out = a.coeffs + l * 192;
-        if (g == 0) {
-            float acc[FPO_N_SIGMA];
+        const int64_t l0 = tile * 64;
+        const int64_t l = l0 + ll;
+        const int nl = (int)min<int64_t>(64, a.n_leaves - l0);
+        float acc[45];
 #pragma unroll
-            for (int i = 0; i < FPO_N_SIGMA; ++i) acc[i] = 0.0f;
-            float smax = -__builtin_inff();
-#pragma unroll 4
-            for (int t = 0; t < T; ++t) {
-                const float s = a.frames[((int64_t)t * a.stride + l) * 32];
-                smax = fmaxf(smax, s);
-#pragma unroll
-                for (int i = 0; i < FPO_N_SIGMA; ++i) acc[i] = fmaf(s, B[t][i], acc[i]);
+        for (int e = 0; e < 45; ++e) acc[e] = 0.0f;
+        float smax = -__builtin_inff();
+        for (int t0 = 0; t0 < T; t0 += kDftFrames) {
+            const int nf = min(kDftFrames, T - t0);
+            // stage nf frames x 64 records: 512 float4 per frame, coalesced
+            for (int e = threadIdx.x; e < nf * 512; e += 256) {
+                const int f = e >> 9, w = e & 511;
+                const int rl = w >> 3, rw = w & 7;
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (rl < nl)
+                    v = reinterpret_cast<const float4*>(a.frames + ((int64_t)(t0 + f) * a.stride + l0) * 32)[w];
+                float* d = &X[f][rl * kRecPad + rw * 4];
+                d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
             }
+            __syncthreads();
+            for (int f = 0; f < nf; ++f) {
+                const float* r = &X[f][ll * kRecPad];
+                const float* bt = B[t0 + f];
+                if (g == 0) {
+                    const float s = r[0];
+                    smax = fmaxf(smax, s);
 #pragma unroll
-            for (int i = 0; i < FPO_N_SIGMA; ++i) out[i] = acc[i];
-            if (a.sigma_max) a.sigma_max[l] = smax;
-        } else {
-            // SH coefficients q = 9 (g - 1) .. + 8, record values 1 + q
-            const int q0 = 9 * (g - 1);
-            const int w0 = (1 + q0) >> 2;               // first float4 word holding them
-            const int off = (1 + q0) & 3;
-            float acc[9][FPO_N_SH_FOURIER];
+                    for (int i = 0; i < FPO_N_SIGMA; ++i) acc[i] = fmaf(s, bt[i], acc[i]);
+                } else {
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
+                    for (int q = 0; q < 9; ++q) {
+                        const float z = r[1 + q0 + q];
 #pragma unroll
-                for (int i = 0; i < FPO_N_SH_FOURIER; ++i) acc[q][i] = 0.0f;
-#pragma unroll 2
-            for (int t = 0; t < T; ++t) {
-                const float4* rec = reinterpret_cast<const float4*>(a.frames + ((int64_t)t * a.stride + l) * 32);
-                float v[12];
-#pragma unroll
-                for (int w = 0; w < 3; ++w) {
-                    const float4 x = rec[w0 + w];
-                    v[4 * w] = x.x; v[4 * w + 1] = x.y; v[4 * w + 2] = x.z; v[4 * w + 3] = x.w;
-                }
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const float z = off == 1 ? v[q + 1] : off == 2 ? v[q + 2] : off == 3 ? v[q + 3] : v[q];
-#pragma unroll
-                    for (int i = 0; i < FPO_N_SH_FOURIER; ++i) acc[q][i] = fmaf(z, B[t][i], acc[q][i]);
+                        for (int i = 0; i < FPO_N_SH_FOURIER; ++i) acc[q * 5 + i] = fmaf(z, bt[i], acc[q * 5 + i]);
+                    }
                 }
             }
-            float* o = out + FPO_N_SIGMA + q0 * FPO_N_SH_FOURIER;
+            __syncthreads();
+        }
+        if (ll < nl) {
+            float* out = a.coeffs + l * 192;
+            if (g == 0) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
+                for (int i = 0; i < FPO_N_SIGMA; ++i) out[i] = acc[i];
+                if (a.sigma_max) a.sigma_max[l] = smax;
+            } else {
+                float* o = out + FPO_N_SIGMA + q0 * FPO_N_SH_FOURIER;
 #pragma unroll
-                for (int i = 0; i < FPO_N_SH_FOURIER; ++i) o[q * FPO_N_SH_FOURIER + i] = acc[q][i];
-            if (g == 3)
-                for (int e = FPO_N_COEFF; e < 192; ++e) out[e] = 0.0f;
+                for (int e = 0; e < 45; ++e) o[e] = acc[e];
+                if (g == 3)
+                    for (int e = FPO_N_COEFF; e < 192; ++e) out[e] = 0.0f;
+            }
         }
     }
 }
@@ -200,6 +210,7 @@ extern "C" fpo_status fpo_dft_frames(const float* frames, int32_t n_frames, int6
     a.literal = literal ? 1 : 0;
     const int64_t tiles = (n_leaves + 63) / 64;
     const unsigned grid = (unsigned)std::min<int64_t>(tiles, 4096);
-    hipLaunchKernelGGL(dev::dft_kernel, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream), a);
+    const size_t lds = sizeof(float) * ((size_t)n_frames * (FPO_N_SIGMA + 1) + (size_t)dev::kDftFrames * 64 * dev::kRecPad);
+    hipLaunchKernelGGL(dev::dft_kernel, dim3(grid), dim3(256), lds, static_cast<hipStream_t>(stream), a);
     return launch_status("fpo_dft_frames");
 }

@@ -371,15 +371,17 @@ def blob_frame_leaves(depth: int, n_union: int, n_frames: int = 60, seed: int = 
     k = M.size - n_union
     iso = np.partition(M, k)[k]
     cells = blob_leaves(depth, n_union, seed, n_frames)
+    import torch  # CPU only, as in blob_max_field
     g = 1 << depth
-    x = (cells[:, 1:4].astype(np.float64) + 0.5) / g
+    x = torch.from_numpy((cells[:, 1:4].astype(np.float32) + 0.5) / g)
+    inv_w = torch.from_numpy((1.0 / (2.0 * params.w ** 2)).astype(np.float32))
+    amp = torch.from_numpy(params.a.astype(np.float32))
     out = []
     for t in range(n_frames):
         mu = 0.5 + params.A * np.sin(2.0 * math.pi * params.f[:, None] * t / PERIOD + params.phi)
-        rho = np.zeros(len(cells))
-        for gi in range(len(params.a)):
-            r2 = ((x - mu[gi]) ** 2).sum(1)
-            rho += params.a[gi] * np.exp(-r2 / (2.0 * params.w[gi] ** 2))
+        mu_t = torch.from_numpy(mu.astype(np.float32))                      # [G][3]
+        r2 = ((x[:, None, :] - mu_t[None]) ** 2).sum(-1)                    # [n][G]
+        rho = (torch.exp(-r2 * inv_w[None]) * amp[None]).sum(-1).numpy()
         sel = cells[rho >= iso]
         par = sel[:, 1:4] >> 1
         key = (par[:, 0].astype(np.int64) * g + par[:, 1]) * g + par[:, 2]
