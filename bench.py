@@ -588,6 +588,21 @@ def main():
         modes[mo] = {"ms_per_step": round(ms, 4), "Mrays_s": round(rays_step / (ms * 1e-3) / 1e6, 2),
                      "fps_1080p": round(len(cams) / (ms * 1e-3), 2), "render_launch_ms": round(r_ms, 4),
                      "bake_launch_ms": None if b_ms is None else round(b_ms, 4), **qual[mo]}
+    # Storage without the DFT (per-frame PlenOctrees, the paper's Table 5 rows b/c) against the
+    # FPO: a per-frame store renders each frame time with the snapshot render alone, the FPO
+    # adds one IDFT pass per time point (decode) or evaluates the IDFT per segment (fourier).
+    L = sc.n_leaves
+    dec_ms, dec_r, dec_b = timing["decode"]
+    four_ms, four_r, _ = timing["fourier"]
+    per_frame = {
+        "frames": 60, "leaves": L,
+        "fpo_bytes": {"f32": L * 664, "bf16": L * (332 + 4), "fp8": L * (166 + 4)},
+        "per_frame_bytes": {"f32": 60 * L * 28 * 4, "bf16": 60 * L * 28 * 2},
+        "fps_1080p": {"per_frame_snapshot_render": round(per / (dec_r * 1e-3), 1),
+                      "fpo_decode": round(per / ((dec_r + dec_b) * 1e-3), 1),
+                      "fpo_fourier": round(per / (four_r * 1e-3), 1)},
+        "note": "per-frame store renders only frame times; the FPO renders any t (Eq. 8 is T-periodic and smooth)",
+    }
     del frames
     bake = None if args.no_bake else bake_leg(dev, sc, tree, oracle)
     ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
@@ -646,6 +661,7 @@ def main():
             "sample": f"{m} rays drawn uniformly from the step's 160 frames, FP64 C oracle",
         },
         "bake": bake,
+        "per_frame_storage": per_frame,
         "finetune": ft,
         "proposal": prop,
         "construct": cons,
