@@ -190,12 +190,20 @@ fpo_status fpo_camera_pack(const fpo_camera* cams, int32_t n_cams, float* table_
 /* ---------------------------------------------------------------------- */
 
 /* Scatter caller-order coefficients into F32 leaf records.
- *   src  device [n_leaves][166] F32, caller order.
- *   perm device [n_leaves] int64 from fpo_build_tree.
- *   dst  device [leaf_stride][48] 16-byte words (F32 records); padding slots
- *        (q >= 166) and slots >= n_leaves are written with zero. */
+ *   src    device [n_leaves][n1 + 27 n2] F32, caller order (166 per leaf for
+ *          the default layout).
+ *   perm   device [n_leaves] int64 from fpo_build_tree.
+ *   layout NULL for (31, 5); else n1 in {11, 21, 31}, n2 in {5, 11} (Table 3's
+ *          Fourier dimensions).  Records of other layouts hold
+ *          ceil((n1 + 27 n2) / 4) words rounded up to a multiple of 8.
+ *   dst    device [leaf_stride][R] 16-byte words (F32 records, R = 48 for the
+ *          default layout); padding slots and slots >= n_leaves are written
+ *          with zero.
+ * Layouts other than (31, 5) are accepted by fpo_render (F32 store, Fourier
+ * mode, no skip) and fpo_bake_times (F32 output) only; every other call
+ * returns FPO_E_UNSUPPORTED for them. */
 fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
-                           int64_t leaf_stride, float* dst, void* stream);
+                           int64_t leaf_stride, const fpo_layout* layout, float* dst, void* stream);
 
 /* Render n_cams pinhole views (Sec. 4.1: per pixel, traverse the octree,
  * invert the leaf's coefficients at the camera's time with Eq. 7-9, colour

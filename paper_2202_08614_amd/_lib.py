@@ -79,7 +79,7 @@ _SIGS = {
     "fpo_build_tree": [_P, _I64, _I32, _P, _I64, _P, _P],
     "fpo_time_basis": [_P, _I32, ctypes.POINTER(Layout), _P],
     "fpo_camera_pack": [ctypes.POINTER(CameraC), _I32, _P],
-    "fpo_pack_coeffs": [_P, _P, _I64, _I64, _P, _P],
+    "fpo_pack_coeffs": [_P, _P, _I64, _I64, ctypes.POINTER(Layout), _P, _P],
     "fpo_render": [ctypes.POINTER(TreeView), ctypes.POINTER(CameraC), _I32,
                    ctypes.POINTER(RenderOpts), _P, _P, _P],
     "fpo_camera_rays": [_P, _I32, _P, _P, _P, _I64, _P, _P, _P],
@@ -152,8 +152,14 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def make_layout(period: float = 60.0, sigma_scale: float = 64.0) -> Layout:
-    return Layout(N_SIGMA, N_SH_FOURIER, SH_DEGREE, float(period), float(sigma_scale))
+def make_layout(period: float = 60.0, sigma_scale: float = 64.0, n_sigma: int = N_SIGMA,
+                n_sh_fourier: int = N_SH_FOURIER) -> Layout:
+    return Layout(int(n_sigma), int(n_sh_fourier), SH_DEGREE, float(period), float(sigma_scale))
+
+
+def layout_record_words(n_sigma: int, n_sh_fourier: int) -> int:
+    """16-byte words of an F32 record for the layout (n1, n2)."""
+    return ((n_sigma + 27 * n_sh_fourier + 3) // 4 + 7) // 8 * 8
 
 
 def camera_struct(cams) -> ctypes.Array:
@@ -248,18 +254,21 @@ class DeviceTree:
     @classmethod
     def from_leaves(cls, leaf_dijk: np.ndarray, coeffs: np.ndarray, max_depth: int,
                     device="cuda", period: float = 60.0, sigma_scale: float = 64.0,
-                    leaf_stride: Optional[int] = None) -> "DeviceTree":
+                    leaf_stride: Optional[int] = None, n_sigma: int = N_SIGMA,
+                    n_sh_fourier: int = N_SH_FOURIER) -> "DeviceTree":
         import torch
         children, perm = build_tree(leaf_dijk, max_depth)
         n = int(leaf_dijk.shape[0])
         stride = int(leaf_stride or n)
+        layout = make_layout(period, sigma_scale, n_sigma, n_sh_fourier)
         src = torch.from_numpy(np.ascontiguousarray(coeffs, dtype=np.float32)).to(device)
         perm_d = torch.from_numpy(perm).to(device)
-        recs = torch.empty((stride, record_words(FPO_F32), 4), dtype=torch.float32, device=device)
-        pack_coeffs(src, perm_d, n, stride, recs)
+        recs = torch.empty((stride, layout_record_words(n_sigma, n_sh_fourier), 4), dtype=torch.float32,
+                           device=device)
+        pack_coeffs(src, perm_d, n, stride, recs, layout)
         del src
         return cls(torch.from_numpy(children).to(device), children.shape[0], max_depth, recs, None,
-                   FPO_F32, n, stride, perm, make_layout(period, sigma_scale))
+                   FPO_F32, n, stride, perm, layout)
 
     def with_store(self, coeffs, scale, dtype: int) -> "DeviceTree":
         return DeviceTree(self.children, self.n_nodes, self.max_depth, coeffs, scale, dtype,
@@ -282,9 +291,9 @@ class DeviceTree:
 # ---------------------------------------------------------------------------
 # device calls
 # ---------------------------------------------------------------------------
-def pack_coeffs(src, perm, n_leaves: int, leaf_stride: int, dst):
-    _check(lib().fpo_pack_coeffs(_t_ptr(src), _t_ptr(perm), int(n_leaves), int(leaf_stride), _t_ptr(dst),
-                                 _stream()))
+def pack_coeffs(src, perm, n_leaves: int, leaf_stride: int, dst, layout: Optional[Layout] = None):
+    _check(lib().fpo_pack_coeffs(_t_ptr(src), _t_ptr(perm), int(n_leaves), int(leaf_stride),
+                                 None if layout is None else ctypes.byref(layout), _t_ptr(dst), _stream()))
 
 
 def render(tree: DeviceTree, cams, opts: Optional[RenderOpts] = None, rgb=None, T=None, want_T: bool = False):

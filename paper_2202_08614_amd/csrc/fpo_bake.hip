@@ -308,6 +308,42 @@ __global__ __launch_bounds__(kBlock) void eval_times_kernel(TreeDev tree, const 
     }
 }
 
+// Per-time evaluation for the other coefficient layouts (F32 store, n1 density
+// and n2 SH Fourier terms): the record is streamed word by word and every
+// coefficient q goes to its one output (sigma for q < n1, else z_m with
+// m = (q - n1) / n2 and basis index (q - n1) % n2), so no layout needs its
+// whole record in registers.
+template <int N1, int N2>
+__global__ __launch_bounds__(kBlock) void eval_times_layout_kernel(TreeDev tree, const float* basis, int32_t n_t,
+                                                                   int64_t n_leaves, float* out)
+{
+    using RC = Rec<FPO_F32, N1, N2>;
+    constexpr int kWords = (RC::kCoeff + 3) / 4;
+    const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n_leaves) return;
+    const uint4* rec = tree.recs + l * RC::R;
+    for (int t = 0; t < n_t; ++t) {
+        const float* b = basis + (int64_t)t * FPO_BASIS_STRIDE;
+        float v[32];
+#pragma unroll
+        for (int e = 0; e < 32; ++e) v[e] = 0.0f;
+#pragma unroll
+        for (int g = 0; g < kWords; ++g) {
+            float k[4];
+            Pack<FPO_F32>::unpack(rec[g], k);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int q = 4 * g + e;
+                if (q < N1) v[0] = fmaf(k[e], b[q], v[0]);
+                else if (q < RC::kCoeff) v[1 + (q - N1) / N2] = fmaf(k[e], b[(q - N1) % N2], v[1 + (q - N1) / N2]);
+            }
+        }
+        float4* o = reinterpret_cast<float4*>(out) + ((int64_t)t * tree.stride + l) * 8;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) o[w] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+    }
+}
+
 }  // namespace dev
 }  // namespace fpo
 
@@ -340,11 +376,27 @@ extern "C" fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_
 extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t,
                                      fpo_dtype out_dtype, void* out, void* stream)
 {
-    fpo_status st = check_tree(tree, true);
+    fpo_status st = check_tree(tree, true, true);
     if (st != FPO_OK) return st;
     if (!basis || !out) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
     if (out_dtype != FPO_F32 && out_dtype != FPO_BF16) return fail(FPO_E_INVALID, "out_dtype must be F32 or BF16");
+    if (!default_layout(tree->layout)) {
+        if (tree->dtype != FPO_F32 || out_dtype != FPO_F32)
+            return fail(FPO_E_UNSUPPORTED, "layouts other than (31, 5) bake F32 stores into F32 snapshots only");
+        const dev::TreeDev td = dev::tree_dev(tree);
+        const int64_t g1 = (tree->n_leaves + dev::kBlock - 1) / dev::kBlock;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        float* o = static_cast<float*>(out);
+        switch (tree->layout.n_sigma * 100 + tree->layout.n_sh_fourier) {
+#define FPO_EVL(A, B) case A * 100 + B: \
+            hipLaunchKernelGGL((dev::eval_times_layout_kernel<A, B>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td, basis, n_t, tree->n_leaves, o); break
+            FPO_EVL(11, 5); FPO_EVL(21, 5); FPO_EVL(11, 11); FPO_EVL(21, 11); FPO_EVL(31, 11);
+#undef FPO_EVL
+            default: return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
+        }
+        return launch_status("fpo_bake_times");
+    }
     const int64_t per_block = (int64_t)dev::kBakeWaves * dev::kBakeLeaves;
     const int64_t grid = (tree->n_leaves + per_block - 1) / per_block;
     if (grid > INT32_MAX) return fail(FPO_E_INVALID, "too many leaves");

@@ -283,21 +283,35 @@ __host__ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, V
     walk(T, r, stk, vis, __builtin_inff(), ns);
 }
 
+// Record geometry of a coefficient layout (n1 density terms, n2 terms per SH
+// coefficient): words per record rounded up to whole 128-byte lines.  The
+// default layout (31, 5) gives Pack<DT>::R.
+template <int DT, int N1, int N2>
+struct Rec {
+    static constexpr int W = Pack<DT>::W;
+    static constexpr int kCoeff = N1 + 3 * FPO_N_SH * N2;
+    static constexpr int R = ((kCoeff + W - 1) / W + 7) / 8 * 8;
+};
+static_assert(Rec<FPO_F32, FPO_N_SIGMA, FPO_N_SH_FOURIER>::R == Pack<FPO_F32>::R, "F32 record");
+static_assert(Rec<FPO_BF16, FPO_N_SIGMA, FPO_N_SH_FOURIER>::R == Pack<FPO_BF16>::R, "BF16 record");
+static_assert(Rec<FPO_FP8_E4M3, FPO_N_SIGMA, FPO_N_SH_FOURIER>::R == Pack<FPO_FP8_E4M3>::R, "FP8 record");
+
 // --------------------------------------------------------------------------
-// Leaf evaluation at time t (Eq. 7 and Eq. 9): sigma_raw = sum_i k^sigma_i b_i
-// and h_c = sum_j z_{c,j} Y_j with z_{c,j} = sum_{i<5} k^z_{c,j,i} b_i.
+// Leaf evaluation at time t (Eq. 7 and Eq. 9): sigma_raw = sum_{i<n1} k^sigma_i
+// b_i and h_c = sum_j z_{c,j} Y_j with z_{c,j} = sum_{i<n2} k^z_{c,j,i} b_i.
 // ----------------------------------------------------------------------------
-template <int DT>
+template <int DT, int N1 = FPO_N_SIGMA, int N2 = FPO_N_SH_FOURIER>
 struct LeafEval {
     static constexpr int W = Pack<DT>::W;
-    static constexpr int kSigmaWords = (FPO_N_SIGMA + 1 + W - 1) / W;   // words holding q < 32
-    static constexpr int kWords = (FPO_N_COEFF + W - 1) / W;
+    static constexpr int R = Rec<DT, N1, N2>::R;
+    static constexpr int kSigmaWords = (N1 + 1 + W - 1) / W;   // words holding q <= n1
+    static constexpr int kWords = (Rec<DT, N1, N2>::kCoeff + W - 1) / W;
 
-    // Loads the words holding q < 32 and returns sigma_raw (scaled for
+    // Loads the words holding q <= n1 and returns sigma_raw (scaled for
     // quantised stores).  `k` keeps the unpacked values for colour().
     __device__ static inline float sigma(const TreeDev& T, int leaf, const float* b, float* k, float& scale)
     {
-        const uint4* P = T.recs + (int64_t)leaf * Pack<DT>::R;
+        const uint4* P = T.recs + (int64_t)leaf * R;
 #pragma unroll
         for (int g = 0; g < kSigmaWords; ++g) {
             const uint4 w = P[g];
@@ -305,7 +319,7 @@ struct LeafEval {
         }
         float s = 0.0f;
 #pragma unroll
-        for (int q = 0; q < FPO_N_SIGMA; ++q) s = fmaf(k[q], b[q], s);
+        for (int q = 0; q < N1; ++q) s = fmaf(k[q], b[q], s);
         scale = (DT == FPO_F32) ? 1.0f : T.scale[leaf];
         return s * scale;
     }
@@ -314,10 +328,10 @@ struct LeafEval {
     __device__ static inline void colour(const TreeDev& T, int leaf, const float* b, const float* Y,
                                          const float* k, float scale, float* h)
     {
-        const uint4* P = T.recs + (int64_t)leaf * Pack<DT>::R;
+        const uint4* P = T.recs + (int64_t)leaf * R;
         float kz[(kWords - kSigmaWords + 1) * W];
-        // coefficient q >= 31 lives at kz[q - 31 + off]
-        constexpr int off = FPO_N_SIGMA - (kSigmaWords - 1) * W;   // index of q = 31 inside the last sigma word
+        // coefficient q >= n1 lives at kz[q - n1 + off]
+        constexpr int off = N1 - (kSigmaWords - 1) * W;   // index of q = n1 inside the last sigma word
 #pragma unroll
         for (int e = 0; e < W; ++e) kz[e] = k[(kSigmaWords - 1) * W + e];
 #pragma unroll
@@ -330,10 +344,10 @@ struct LeafEval {
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int j = 0; j < FPO_N_SH; ++j) {
-                const int base = off + (c * FPO_N_SH + j) * FPO_N_SH_FOURIER;
+                const int base = off + (c * FPO_N_SH + j) * N2;
                 float z = 0.0f;
 #pragma unroll
-                for (int i = 0; i < FPO_N_SH_FOURIER; ++i) z = fmaf(kz[base + i], b[i], z);
+                for (int i = 0; i < N2; ++i) z = fmaf(kz[base + i], b[i], z);
                 h[c] = fmaf(z, Y[j], h[c]);
             }
         h[0] *= scale; h[1] *= scale; h[2] *= scale;
@@ -375,7 +389,7 @@ struct SnapEval {
 constexpr int kSnapF32 = 16 + FPO_F32;
 constexpr int kSnapBF16 = 16 + FPO_BF16;
 
-template <int MODE>
+template <int MODE, int N1 = FPO_N_SIGMA, int N2 = FPO_N_SH_FOURIER>
 struct Shade {
     const TreeDev& T;
     const float* b;       // basis row (Fourier mode)
@@ -397,13 +411,13 @@ struct Shade {
             if (!(sig * delta > 0.0f)) return false;
             SnapEval<SDT>::colour(snap, leaf, Y, v, h);
         } else {
-            constexpr int W = LeafEval<MODE>::W;
-            float k[LeafEval<MODE>::kSigmaWords * W];
+            using E = LeafEval<MODE, N1, N2>;
+            float k[E::kSigmaWords * E::W];
             float scale;
-            sraw = LeafEval<MODE>::sigma(T, leaf, b, k, scale);
+            sraw = E::sigma(T, leaf, b, k, scale);
             const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
             if (!(sig * delta > 0.0f)) return false;   // transparent: contributes nothing
-            LeafEval<MODE>::colour(T, leaf, b, Y, k, scale, h);
+            E::colour(T, leaf, b, Y, k, scale, h);
         }
         const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
         const float e = __expf(-sig * delta);

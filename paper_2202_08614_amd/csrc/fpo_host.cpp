@@ -31,7 +31,7 @@ fpo_status launch_status(const char* what)
     return FPO_OK;
 }
 
-fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs)
+fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_layouts)
 {
     if (!tree) return fail(FPO_E_INVALID, "tree is NULL");
     if (!tree->children) return fail(FPO_E_INVALID, "tree->children is NULL");
@@ -43,8 +43,10 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs)
         return fail(FPO_E_INVALID, "tree->n_leaves out of range");
     if (tree->leaf_stride < tree->n_leaves) return fail(FPO_E_INVALID, "leaf_stride < n_leaves");
     const fpo_layout& L = tree->layout;
-    if (L.n_sigma != FPO_N_SIGMA || L.n_sh_fourier != FPO_N_SH_FOURIER || L.sh_degree != FPO_SH_DEGREE)
-        return fail(FPO_E_UNSUPPORTED, "only the (n1=31, n2=5, l_max=2) layout is compiled");
+    if (L.sh_degree != FPO_SH_DEGREE) return fail(FPO_E_UNSUPPORTED, "only l_max = 2 is compiled");
+    if (!default_layout(L) && !(allow_layouts && layout_supported(L.n_sigma, L.n_sh_fourier)))
+        return fail(FPO_E_UNSUPPORTED, allow_layouts ? "layout (n1, n2) not compiled"
+                                                     : "this call is compiled for the (n1=31, n2=5) layout only");
     if (!(L.period > 0.0f) || !std::isfinite(L.period)) return fail(FPO_E_INVALID, "layout.period must be > 0");
     if (!(L.sigma_scale >= 0.0f) || !std::isfinite(L.sigma_scale))
         return fail(FPO_E_INVALID, "layout.sigma_scale must be finite and >= 0");

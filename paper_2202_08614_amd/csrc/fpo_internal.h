@@ -20,8 +20,27 @@ inline int n_planes(fpo_dtype dt)
     return (FPO_N_COEFF + w - 1) / w;
 }
 
-// Validate a tree view (host-visible fields only).
-fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs);
+// Coefficient layouts (n1, n2) with compiled kernels: the default (31, 5)
+// everywhere; (11 | 21 | 31, 5 | 11) for packing, Fourier-mode F32 renders and
+// the per-time IDFT pass.
+inline bool layout_supported(int n1, int n2)
+{
+    return (n1 == 11 || n1 == 21 || n1 == 31) && (n2 == 5 || n2 == 11);
+}
+inline bool default_layout(const fpo_layout& L)
+{
+    return L.n_sigma == FPO_N_SIGMA && L.n_sh_fourier == FPO_N_SH_FOURIER;
+}
+// 16-byte words per leaf record (whole 128-byte lines).
+inline int record_words(fpo_dtype dt, int n1, int n2)
+{
+    const int w = coeffs_per_word(dt);
+    return ((n1 + 3 * FPO_N_SH * n2 + w - 1) / w + 7) / 8 * 8;
+}
+
+// Validate a tree view (host-visible fields only).  allow_layouts: the call
+// handles every layout_supported() layout (else only the default one).
+fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_layouts = false);
 // allow_skip: the call accepts the skip flags (fpo_render only).
 fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip = false);
 

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void skip_prepass_kernel(SkipLaunch a)
 
 // SKIP: walk only the proven part [t_start, t_end] of each chord that the
 // skip pre-pass left in a.skip.
-template <int MODE, bool SKIP>
+template <int MODE, bool SKIP, int N1 = FPO_N_SIGMA, int N2 = FPO_N_SH_FOURIER>
 __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
 {
     __shared__ int s_stack[kStackLevels * kBlock];
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
     const float dy = cam.frame[4] + sx * cam.frame[7] + sy * cam.frame[10];
     const float dz = cam.frame[5] + sx * cam.frame[8] + sy * cam.frame[11];
 
-    Shade<MODE> sh{a.tree, b, cam.snap};
+    Shade<MODE, N1, N2> sh{a.tree, b, cam.snap};
     sh.Tr = 1.0f;
     sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
     sh.stop_T = a.stop_T;
@@ -328,9 +328,9 @@ __global__ __launch_bounds__(kBlock) void camera_rays_kernel(const float* table,
 // dst word (slot, g) = coefficients 4g .. 4g+3 of leaf perm[slot] (F32
 // records of 48 words; padding words and slots >= n_leaves are zero).
 __global__ __launch_bounds__(kBlock) void pack_coeffs_kernel(const float* src, const int64_t* perm,
-                                                             int64_t n_leaves, int64_t stride, float4* dst)
+                                                             int64_t n_leaves, int64_t stride, float4* dst,
+                                                             int R, int n_coeff)
 {
-    constexpr int R = Pack<FPO_F32>::R;
     const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (id >= R * stride) return;
     const int64_t slot = id / R;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void pack_coeffs_kernel(const float* src, c
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int q = 4 * g + e;
-                if (q < FPO_N_COEFF) v[e] = src[p * FPO_N_COEFF + q];
+                if (q < n_coeff) v[e] = src[p * n_coeff + q];
             }
         }
     }
@@ -378,9 +378,12 @@ static void launch_cam(const dev::CamLaunch& a, int grid, int skip, hipStream_t 
 extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
                                  const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
 {
-    fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr);
+    fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr, true);
     if (st != FPO_OK) return st;
     if ((st = check_opts(opts, tree, true)) != FPO_OK) return st;
+    const bool variant = !default_layout(tree->layout);
+    if (variant && (tree->dtype != FPO_F32 || opts->snapshot || opts->flags != 0))
+        return fail(FPO_E_UNSUPPORTED, "layouts other than (31, 5) render from F32 stores in Fourier mode only");
     if (!cams || n_cams < 1) return fail(FPO_E_INVALID, "cams is NULL or n_cams < 1");
     if (!rgb_out) return fail(FPO_E_INVALID, "rgb_out is NULL");
     const int W = cams[0].width, H = cams[0].height;
@@ -451,6 +454,19 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
             else
                 hipLaunchKernelGGL(dev::skip_prepass_kernel<false>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
             if ((st = launch_status("fpo_render (skip pre-pass)")) != FPO_OK) return st;
+        }
+        if (variant) {
+            const int key = tree->layout.n_sigma * 100 + tree->layout.n_sh_fourier;
+            switch (key) {
+                case 1105: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 11, 5>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
+                case 2105: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 21, 5>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
+                case 1111: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 11, 11>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
+                case 2111: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 21, 11>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
+                case 3111: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 31, 11>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
+                default: return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
+            }
+            if ((st = launch_status("fpo_render")) != FPO_OK) return st;
+            continue;
         }
         switch (mode) {
             case FPO_F32: launch_cam<FPO_F32>(a, grid, skip, s); break;
@@ -541,15 +557,20 @@ extern "C" fpo_status fpo_camera_rays(const float* cam_table, int32_t n_cams, co
 }
 
 extern "C" fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
-                                      int64_t leaf_stride, float* dst, void* stream)
+                                      int64_t leaf_stride, const fpo_layout* layout, float* dst, void* stream)
 {
     if (!src || !perm || !dst) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_leaves < 1 || leaf_stride < n_leaves) return fail(FPO_E_INVALID, "bad n_leaves / leaf_stride");
-    const int64_t total = (int64_t)dev::Pack<FPO_F32>::R * leaf_stride;
+    const int n1 = layout ? layout->n_sigma : FPO_N_SIGMA;
+    const int n2 = layout ? layout->n_sh_fourier : FPO_N_SH_FOURIER;
+    if (!layout_supported(n1, n2)) return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
+    const int n_coeff = n1 + 3 * FPO_N_SH * n2;
+    const int R = record_words(FPO_F32, n1, n2);
+    const int64_t total = (int64_t)R * leaf_stride;
     if (total > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many leaves");
     const int64_t grid = (total + dev::kBlock - 1) / dev::kBlock;
     hipLaunchKernelGGL(dev::pack_coeffs_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,
                        static_cast<hipStream_t>(stream), src, perm, n_leaves, leaf_stride,
-                       reinterpret_cast<float4*>(dst));
+                       reinterpret_cast<float4*>(dst), R, n_coeff);
     return launch_status("fpo_pack_coeffs");
 }

@@ -1,0 +1,62 @@
+"""GPU parity of the Fourier-dimension variants of Table 3 (n1 in {11, 21,
+31} density terms, n2 in {5, 11} terms per SH coefficient): Fourier-mode
+renders and the per-time IDFT pass against the FP64 oracle with the same
+layout."""
+import numpy as np
+import pytest
+
+from paper_2202_08614_amd import _lib, synth
+from tests.gpu_util import check_parity, conditioned_reference, note, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = [(11, 5), (21, 5), (31, 5), (11, 11), (21, 11), (31, 11)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.mark.parametrize("n1,n2", LAYOUTS)
+def test_layout_render_matches_oracle(oracle_lib, dev, n1, n2):
+    import torch
+    sc = synth.c1_scene()
+    k = synth.gaussian_coeffs(sc.n_leaves, seed=n1 * 100 + n2, n_sigma=n1, n_sh_fourier=n2)
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, k, 6, device=dev, leaf_stride=sc.n_leaves + 3,
+                                       n_sigma=n1, n_sh_fourier=n2)
+    assert tree.coeffs.shape[1] == _lib.layout_record_words(n1, n2)
+    cam = synth.ring_camera(0.8, 0.3, 1.5, 45.0, 40, 32, 17.3)
+    note(f"layout ({n1}, {n2}) render")
+    rgb, _ = _lib.render(tree, [cam], _lib.make_opts(stop_T=1e-3))
+    torch.cuda.synchronize()
+    o, d = oracle_lib.camera_rays(cam)
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
+    p = oracle_lib.make_params(n_sigma=n1, n_sh_fourier=n2, stop_T=1e-3)
+    ref = conditioned_reference(oracle_lib, ot, k.astype(np.float64), p, [cam.time], o, d, np.zeros(len(o), np.int32))
+    assert (ref["T"][:, 0] < 0.9).sum() > 100
+    check_parity(rgb[0].cpu().numpy().reshape(-1, 3), ref, 1e-4)
+
+
+@pytest.mark.parametrize("n1,n2", LAYOUTS)
+def test_layout_idft_pass_matches_oracle(oracle_lib, dev, n1, n2):
+    import torch
+    dijk = synth.random_tree_leaves(5, 6, p_split=0.6)
+    k = synth.gaussian_coeffs(len(dijk), seed=7, n_sigma=n1, n_sh_fourier=n2)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, n_sigma=n1, n_sh_fourier=n2)
+    times = [3.7, 41.0]
+    basis = torch.from_numpy(_lib.time_basis(times, _lib.make_layout(n_sigma=max(n1, n2)))).to(dev)
+    note(f"layout ({n1}, {n2}) fpo_bake_times F32")
+    out = _lib.bake_times(tree, basis, _lib.FPO_F32)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[:, :, :28]                     # [n_t][slot][28]
+    p = oracle_lib.make_params(n_sigma=n1, n_sh_fourier=n2)
+    want = oracle_lib.bake(k.astype(np.float64), p, times)[:, :, tree.perm].transpose(0, 2, 1)
+    B = np.stack([oracle_lib.basis(t, 60.0, max(n1, n2)) for t in times])
+    ka = np.abs(k[tree.perm]).astype(np.float64)
+    mag = np.zeros_like(want)
+    mag[:, :, 0] = np.abs(B[:, :n1]) @ ka[:, :n1].T          # sum_i |k_i b_i| per time and leaf
+    kz = ka[:, n1:].reshape(-1, 27, n2)
+    mag[:, :, 1:] = np.einsum("ti,lmi->tlm", np.abs(B[:, :n2]), kz)
+    assert np.all(np.abs(got - want) <= (n1 + 4) * 2.0 ** -24 * mag + 1e-7)
+    assert np.all(out.cpu().numpy()[:, :, 28:] == 0.0)
