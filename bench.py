@@ -394,6 +394,78 @@ def construct_leg(dev, depth: int = 9, n_union: int = 2_000_000, n_frames: int =
     return res
 
 
+def layouts_leg(dev, sc, tree, reps: int = 3):
+    """Fourier-dimension variants (Table 3: n1 in {11, 21, 31}, n2 in {5, 11})
+    on the 2.0M-leaf scene: storage per leaf, Fourier-mode render and decode
+    (per-time IDFT pass + snapshot render), 16 cameras x 1080p per launch at
+    two time points."""
+    import torch
+    from paper_2202_08614_amd import _lib, synth
+    res = {}
+    cams = sc.cameras
+    per = 16
+    W, H = cams[0].width, cams[0].height
+    L = sc.n_leaves
+    stream = torch.cuda.current_stream()
+    frames = torch.empty((per, H, W, 3), dtype=torch.float32, device=dev)
+    snap = torch.empty((1, tree.leaf_stride, _lib.SNAP_VALUES), dtype=torch.float32, device=dev)
+    perm_d = torch.from_numpy(tree.perm).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(8614)
+    js = [0, 5]
+    for n1, n2 in ((11, 5), (21, 5), (31, 5), (11, 11), (21, 11), (31, 11)):
+        nc = n1 + 27 * n2
+        std = torch.tensor([1.0 / (i + 1) for i in range(n1)] + [1.0 / (i + 1) for i in range(n2)] * 27,
+                           dtype=torch.float32, device=dev)
+        src = torch.randn((L, nc), generator=gen, device=dev) * std
+        layout = _lib.make_layout(n_sigma=n1, n_sh_fourier=n2)
+        recs = torch.empty((tree.leaf_stride, _lib.layout_record_words(n1, n2), 4), dtype=torch.float32, device=dev)
+        _lib.pack_coeffs(src, perm_d, L, tree.leaf_stride, recs, layout)
+        del src
+        vt = _lib.DeviceTree(tree.children, tree.n_nodes, tree.max_depth, recs, None, _lib.FPO_F32, L,
+                             tree.leaf_stride, tree.perm, layout)
+        basis = torch.from_numpy(_lib.time_basis([cams[j * per].time for j in js], layout)).to(dev)
+        opts_f = _lib.make_opts(stop_T=sc.stop_T)
+        opts_s = _lib.make_opts(stop_T=sc.stop_T, snapshot=snap, snapshot_dtype=_lib.FPO_F32)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / (reps * len(js))
+
+        def fourier():
+            for j in js:
+                _lib.render(vt, cams[j * per:(j + 1) * per], opts_f, rgb=frames)
+
+        def decode():
+            for q, j in enumerate(js):
+                _lib.bake_times(vt, basis[q:q + 1], _lib.FPO_F32, out=snap)
+                _lib.render(vt, cams[j * per:(j + 1) * per], opts_s, rgb=frames)
+
+        def idft():
+            for q in range(len(js)):
+                _lib.bake_times(vt, basis[q:q + 1], _lib.FPO_F32, out=snap)
+
+        f_ms, d_ms, i_ms = timed(fourier), timed(decode), timed(idft)
+        res[f"{n1}x{n2}"] = {"coeffs_per_leaf": nc, "record_bytes": 16 * _lib.layout_record_words(n1, n2),
+                             "store_GB_f32": round(L * nc * 4 / 1e9, 3),
+                             "fourier_ms_per_launch": round(f_ms, 3), "fourier_fps_1080p": round(per / (f_ms * 1e-3), 1),
+                             "decode_ms_per_launch": round(d_ms, 3), "decode_fps_1080p": round(per / (d_ms * 1e-3), 1),
+                             "idft_pass_ms": round(i_ms, 3)}
+        log(f"layout {n1}x{n2}: {res[f'{n1}x{n2}']}")
+        del vt, recs
+        torch.cuda.empty_cache()
+    res["workload"] = ("2.0M-leaf depth-9 scene with random coefficients of each layout (std 1/(i+1)); 16 ring "
+                       "cameras x 1920x1080 per launch, time points 0 and 5 of the headline, T<1e-3; F32 store")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +479,7 @@ def main():
     ap.add_argument("--ft-steps", type=int, default=40)
     ap.add_argument("--no-proposal", action="store_true")
     ap.add_argument("--no-construct", action="store_true")
+    ap.add_argument("--no-layouts", action="store_true")
     ap.add_argument("--only-construct", action="store_true", help="run only the FPO-construction leg")
     ap.add_argument("--only-proposal", action="store_true", help="run only the learned-proposal leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -604,6 +677,8 @@ def main():
         "note": "per-frame store renders only frame times; the FPO renders any t (Eq. 8 is T-periodic and smooth)",
     }
     del frames
+    torch.cuda.empty_cache()
+    lay = None if args.no_layouts else layouts_leg(dev, sc, tree)
     bake = None if args.no_bake else bake_leg(dev, sc, tree, oracle)
     ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
     prop = None if args.no_proposal else proposal_leg(dev, sc, tree, oracle)
@@ -662,6 +737,7 @@ def main():
         },
         "bake": bake,
         "per_frame_storage": per_frame,
+        "layouts": lay,
         "finetune": ft,
         "proposal": prop,
         "construct": cons,

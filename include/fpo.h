@@ -199,9 +199,9 @@ fpo_status fpo_camera_pack(const fpo_camera* cams, int32_t n_cams, float* table_
  *   dst    device [leaf_stride][R] 16-byte words (F32 records, R = 48 for the
  *          default layout); padding slots and slots >= n_leaves are written
  *          with zero.
- * Layouts other than (31, 5) are accepted by fpo_render (F32 store, Fourier
- * mode, no skip) and fpo_bake_times (F32 output) only; every other call
- * returns FPO_E_UNSUPPORTED for them. */
+ * Layouts other than (31, 5) are accepted by fpo_render (Fourier mode: F32
+ * store, no skip; snapshot mode: any) and fpo_bake_times (F32 store and
+ * output) only; every other call returns FPO_E_UNSUPPORTED for them. */
 fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
                            int64_t leaf_stride, const fpo_layout* layout, float* dst, void* stream);
 

@@ -381,9 +381,10 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
     fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr, true);
     if (st != FPO_OK) return st;
     if ((st = check_opts(opts, tree, true)) != FPO_OK) return st;
-    const bool variant = !default_layout(tree->layout);
-    if (variant && (tree->dtype != FPO_F32 || opts->snapshot || opts->flags != 0))
-        return fail(FPO_E_UNSUPPORTED, "layouts other than (31, 5) render from F32 stores in Fourier mode only");
+    // the snapshot render does not read coefficients, so any compiled layout goes
+    const bool variant = !default_layout(tree->layout) && !opts->snapshot;
+    if (variant && (tree->dtype != FPO_F32 || opts->flags != 0))
+        return fail(FPO_E_UNSUPPORTED, "layouts other than (31, 5) render from F32 stores without skipping only");
     if (!cams || n_cams < 1) return fail(FPO_E_INVALID, "cams is NULL or n_cams < 1");
     if (!rgb_out) return fail(FPO_E_INVALID, "rgb_out is NULL");
     const int W = cams[0].width, H = cams[0].height;

@@ -286,9 +286,11 @@ def test_other_layouts_are_limited_to_render_pack_and_bake():
     assert st == _lib.FPO_E_UNSUPPORTED
     st = L.fpo_bake_times(ctypes.byref(view), p, 1, _lib.FPO_BF16, p, None)
     assert st == _lib.FPO_E_UNSUPPORTED
-    # a snapshot render or a quantised store with the layout
-    o2 = _lib.make_opts()
-    o2.snapshot = 64
+    # a skipping render or a quantised store with the layout
+    o2 = _lib.make_opts(flags=_lib.FPO_RENDER_SKIP_COARSE)
+    o2.coarse_bits = 64
+    o2.workspace = 64
+    o2.workspace_bytes = 1 << 20
     cams = _lib.camera_struct([synth.ring_camera(0, 0, 1.5, 30, 4, 4, 0)])
     assert L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(o2), p, None, None) == _lib.FPO_E_UNSUPPORTED
     view.dtype = _lib.FPO_BF16
