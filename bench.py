@@ -646,12 +646,12 @@ def main():
         flop_ray = FLOP_PER_RAY + FLOP_SIGMA * (seg - opq).mean() + FLOP_OPAQUE * opq.mean()
         gather_ray = BYTES_SIGMA_WORDS * (seg - opq).mean() + BYTES_LEAF * opq.mean()
         kernel = "render_cam_kernel<F32> (per-sample IDFT)"
-        kernel_key = "render_cam_kernel<0, false>"
+        kernel_key = "render_cam_kernel<0, false, 31, 5>"
     else:
         flop_ray = FLOP_PER_RAY + FLOP_SNAP_SIGMA * (seg - opq).mean() + FLOP_SNAP_OPAQUE * opq.mean()
         gather_ray = 16 * (seg - opq).mean() + 128 * opq.mean()
         kernel = "render_cam_kernel<snapshot F32> (after a per-leaf IDFT pass)"
-        kernel_key = "render_cam_kernel<16, false>"
+        kernel_key = "render_cam_kernel<16, false, 31, 5>"
     traffic = measured_traffic(kernel_key)
     flop_launch = flop_ray * rays_launch
     achieved_tflops = flop_launch / (launch_ms * 1e-3) / 1e12
