@@ -29,7 +29,7 @@ METRIC = "Mrays/s and 1080p frames/s vs FP64 oracle at stated PSNR; fine-tune ra
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBPS = 8000.0
 
-# Algorithmic FP32 operations per composited segment (see DESIGN.md):
+# Algorithmic FP32 operations per composited segment:
 # density IDFT 31 FMA + activation; for segments with positive optical depth
 # also 27 x 5 FMA SH-coefficient IDFT, 27 FMA SH dot products, 3 sigmoids and
 # the compositing update.
@@ -486,8 +486,8 @@ def main():
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprof byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rays are independent; the sharding design is documented in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(rays are independent, so views or pixel tiles would shard with no exchange).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -10,14 +10,15 @@
 // v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulate): the density row
 // contracts K = 32 (8 MFMAs), each of the 27 SH rows K = 8 (5 used, 2 MFMAs).
 // With all 28 rows of a tile in registers, each lane holds four complete
-// (time, leaf) records and writes them as whole 16-byte words, so the output
-// (the dominant traffic: n_t x 128 or 64 bytes per leaf) streams out in
-// full cache lines.
+// (time, leaf) records; a per-wave LDS transpose turns them into whole-line
+// stores, so the output (the dominant traffic: n_t x 128 or 64 bytes per
+// leaf) streams out in full cache lines.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "fpo.h"
 #include "fpo_device.h"
@@ -111,147 +112,167 @@ __global__ __launch_bounds__(kBlock) void quantize_kernel(const float4* src, int
 // MFMA bake
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kBakeLeaves = 16;           // leaves per wave (one MFMA N tile)
+// Two FP32 values -> one word of two BF16 (round to nearest even, one
+// v_cvt_pk_bf16_f32 on gfx950; denormals are kept).
+__device__ inline uint32_t pack_bf16x2(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+}
+
+constexpr int kBakeLeaves = 16;           // leaves per wave group (one MFMA N tile)
 constexpr int kBakeWaves = kBlock / kWave;
-constexpr int kCoefPad = 169;             // LDS row stride (odd: spreads banks)
+constexpr int kCoefPad = 169;             // LDS row stride, F32 rows (odd: spreads banks)
+constexpr int kCoefPad16 = 170;           // LDS row stride, BF16 rows (85 words: odd)
 
 struct BakeLaunch {
     TreeDev tree;
     const float* basis;    // [n_t][32]
     int32_t n_t;
-    int32_t out_bf16;
     int64_t n_leaves;
     void* out;             // [n_t][stride][32] records
 };
 
-struct BakeLds {
-    float coef[kBakeWaves][kBakeLeaves][kCoefPad];   // decoded coefficients, [leaf][q]
-    float basis[16][33];                             // current 16-time tile
-    float4 out[kBakeWaves][4][kBakeLeaves][8];       // 4 times x 16 leaves records, for stores
-};
-
-template <int DT>
-__device__ inline void stage_leaf_coeffs(const BakeLaunch& a, BakeLds& L, int wv, int ln, int64_t leaf0)
+// One wave per group of 16 leaves.  The 16 records (pad words included:
+// whole lines) are decoded into LDS rows coef[leaf][q]; for every tile of 16
+// times lane (kq, n) feeds A[t0 + n][k] (basis, through the cache) and
+// B[k][leaf n] (LDS), ending with D[t0 + 4 kq + r][leaf n] for all 28 rows and
+// r < 4: four whole records.  For each r the wave parks its 64 records
+// (scaled, and converted when the output is BF16) in LDS as [kq][leaf][word]
+// (word w of leaf n at slot w ^ (n & (words - 1)), so that record writes and
+// row reads spread over the banks) and writes them back out as 16 consecutive
+// records per time: lane L writes word L of each 64-word run, whole lines.
+// The waves of a block share nothing and never wait for each other.
+template <int DT, int OUT_BF16>
+__global__ __launch_bounds__(kBlock, (DT != FPO_F32 && OUT_BF16) ? 3 : 2) void bake_kernel(BakeLaunch a)
 {
-    constexpr int W = Pack<DT>::W;
-    constexpr int R = Pack<DT>::R;
-    constexpr int kWords = (FPO_N_COEFF + W - 1) / W;
-    for (int idx = ln; idx < kBakeLeaves * kWords; idx += kWave) {
-        const int li = idx / kWords;
-        const int g = idx - li * kWords;
-        const int64_t leaf = leaf0 + li;
-        float v[W];
-        if (leaf < a.n_leaves) {
-            Pack<DT>::unpack(a.tree.recs[leaf * R + g], v);
-        } else {
-#pragma unroll
-            for (int e = 0; e < W; ++e) v[e] = 0.0f;
-        }
-#pragma unroll
-        for (int e = 0; e < W; ++e) {
-            const int q = g * W + e;
-            if (q < kCoefPad) L.coef[wv][li][q] = q < FPO_N_COEFF ? v[e] : 0.0f;
-        }
-    }
-}
-
-template <int DT>
-__global__ __launch_bounds__(kBlock) void bake_kernel(BakeLaunch a)
-{
-    __shared__ BakeLds L;
+    constexpr int W = Pack<DT>::W;                            // codes per 16-byte word
+    constexpr int R = Pack<DT>::R;                            // words per record
+    constexpr int kWords = (FPO_N_COEFF + W - 1) / W;         // words holding the 166 codes
+    constexpr int kPf = kBakeLeaves * R / kWave;              // record words per lane
+    static_assert(kBakeLeaves * R % kWave == 0, "whole records per wave");
+    constexpr int kOut = OUT_BF16 ? 4 : 8;                    // 16-byte words per output record
+    constexpr int kRunsPerTime = kOut / 4;                    // 64-word store runs per time row
+    // BF16 and FP8 codes are exact in BF16: their rows are kept as BF16 bit
+    // patterns, which halves the LDS per wave (three blocks per CU)
+    constexpr bool kHalf = DT != FPO_F32;
+    constexpr int kPad = kHalf ? kCoefPad16 : kCoefPad;
+    using CoefT = std::conditional_t<kHalf, uint16_t, float>;
+    __shared__ CoefT coef[kBakeWaves][kBakeLeaves][kPad];
+    __shared__ uint4 stage[kBakeWaves][4][kBakeLeaves][kOut];
+    auto coef_at = [&](const CoefT* row, int q) -> float {
+        if constexpr (kHalf) return __uint_as_float((uint32_t)row[q] << 16);
+        else return row[q];
+    };
     const int wv = threadIdx.x / kWave;
     const int ln = threadIdx.x % kWave;
-    const int64_t leaf0 = ((int64_t)blockIdx.x * kBakeWaves + wv) * kBakeLeaves;
-    stage_leaf_coeffs<DT>(a, L, wv, ln, leaf0);
     const int n = ln & 15;      // A row (time) / B and D column (leaf)
     const int kq = ln >> 4;     // k index inside a K = 4 step; D rows 4 kq .. 4 kq + 3
-    const int64_t my_leaf = leaf0 + n;
-    const float s = (DT != FPO_F32 && my_leaf < a.n_leaves) ? a.tree.scale[my_leaf] : 1.0f;
-
-    for (int t0 = 0; t0 < a.n_t; t0 += 16) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < 16 * 32; idx += kBlock) {
-            const int tt = idx / 32, i = idx % 32;
-            L.basis[tt][i] = (t0 + tt < a.n_t && i < FPO_N_SIGMA)
-                                 ? a.basis[(int64_t)(t0 + tt) * FPO_BASIS_STRIDE + i] : 0.0f;
-        }
-        __syncthreads();
-        f32x4 acc[FPO_N_BAKED];
-        // density row: K = 32
-        acc[0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t grp = (int64_t)blockIdx.x * kBakeWaves + wv;
+    if (grp * kBakeLeaves >= a.n_leaves) return;
+    const int64_t row = a.tree.stride * kOut;                 // output words per time row
+    {
+        uint4 pf[kPf];
+        const uint4* src = a.tree.recs + grp * kBakeLeaves * R + ln;
+        const int n_words = (int)min<int64_t>(kBakeLeaves, a.n_leaves - grp * kBakeLeaves) * R;
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            const int k = 4 * kk + kq;
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(L.basis[n][k], L.coef[wv][n][k], acc[0], 0, 0, 0);
-        }
-        // SH rows: K = 5 (padded to 8)
-        const float a0 = kq < FPO_N_SH_FOURIER ? L.basis[n][kq] : 0.0f;
-        const float a1 = kq + 4 < FPO_N_SH_FOURIER ? L.basis[n][kq + 4] : 0.0f;
+        for (int p = 0; p < kPf; ++p) pf[p] = p * kWave + ln < n_words ? src[p * kWave] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-        for (int m = 0; m < FPO_N_BAKED - 1; ++m) {
-            const int q = FPO_N_SIGMA + FPO_N_SH_FOURIER * m;
-            const float b0 = L.coef[wv][n][q + kq];
-            const float b1 = kq + 4 < FPO_N_SH_FOURIER ? L.coef[wv][n][q + kq + 4] : 0.0f;
-            f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-            z = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, z, 0, 0, 0);
-            z = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, z, 0, 0, 0);
-            acc[1 + m] = z;
+        for (int p = 0; p < kPf; ++p) {
+            const int idx = p * kWave + ln;
+            const int li = idx / R;
+            const int g = idx - li * R;
+            if (g >= kWords) continue;
+            float v[W];
+            Pack<DT>::unpack(pf[p], v);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const int q = g * W + e;
+                if (q >= kPad) continue;
+                const float x = q < FPO_N_COEFF ? v[e] : 0.0f;
+                if constexpr (kHalf) coef[wv][li][q] = (uint16_t)(__float_as_uint(x) >> 16);
+                else coef[wv][li][q] = x;
+            }
         }
-        // lane (kq, n) holds rows q of D[t = 4 kq + r][leaf n]: four whole
-        // records.  For each r, park them in LDS as [kq][leaf][word] (word w
-        // of leaf n stored at slot w ^ (n & 7), so that the per-lane record
-        // writes and the row reads both spread over all 32 banks) and write
-        // out, per time, the 16 consecutive records of the wave (2 KB F32 /
-        // 1 KB BF16 contiguous) as full 16-byte words.
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+        const int64_t leaf0 = grp * kBakeLeaves;
+        const int64_t my_leaf = leaf0 + n;
+        const float s = (DT != FPO_F32 && my_leaf < a.n_leaves) ? a.tree.scale[my_leaf] : 1.0f;
         const int n_valid = (int)min<int64_t>(kBakeLeaves, a.n_leaves - leaf0);
+        const CoefT* cf = coef[wv][n];
+        uint4* dst = static_cast<uint4*>(a.out) + leaf0 * kOut + ln;
+
+        for (int t0 = 0; t0 < a.n_t; t0 += 16) {
+            // re-read the B operands from LDS every tile rather than hold 62
+            // of them in registers across the loop
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int ta = t0 + n;
+            const bool ta_ok = ta < a.n_t;
+            const float* brow = a.basis + (int64_t)(ta_ok ? ta : 0) * FPO_BASIS_STRIDE;
+            f32x4 acc[FPO_N_BAKED];
+            // density row: K = 32 (k = 31 is padding: zero basis)
+            acc[0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-#pragma unroll
-            for (int w = 0; w < 8; ++w) {
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int q = 4 * w + e;
-                    v[e] = q < FPO_N_BAKED ? acc[q][r] * s : 0.0f;
-                }
-                L.out[wv][kq][n][w ^ (n & 7)] = make_float4(v[0], v[1], v[2], v[3]);
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = 4 * kk + kq;
+                const float av = (ta_ok && k < FPO_N_SIGMA) ? brow[k] : 0.0f;
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, coef_at(cf, k), acc[0], 0, 0, 0);
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            if (a.out_bf16) {
-                // 4 times x 16 leaves x 4 BF16 words = 256 words: 4 per lane
+            // SH rows: K = 5 (padded to 8)
+            const float a0 = ta_ok ? brow[kq] : 0.0f;
+            const float a1 = (ta_ok && kq == 0) ? brow[4] : 0.0f;
 #pragma unroll
-                for (int it = 0; it < 4; ++it) {
-                    const int idx = it * kWave + ln;           // [tq][leaf][wo]
-                    const int tq = idx >> 6, li = (idx >> 2) & 15, wo = idx & 3;
-                    const int t = t0 + 4 * tq + r;
-                    if (t < a.n_t && li < n_valid) {
-                        const float4 v = L.out[wv][tq][li][(2 * wo) ^ (li & 7)];
-                        const float4 u = L.out[wv][tq][li][(2 * wo + 1) ^ (li & 7)];
-                        uint4 o4;
-                        o4.x = f32_to_bf16_rne(v.x) | (f32_to_bf16_rne(v.y) << 16);
-                        o4.y = f32_to_bf16_rne(v.z) | (f32_to_bf16_rne(v.w) << 16);
-                        o4.z = f32_to_bf16_rne(u.x) | (f32_to_bf16_rne(u.y) << 16);
-                        o4.w = f32_to_bf16_rne(u.z) | (f32_to_bf16_rne(u.w) << 16);
-                        const int64_t rec = (int64_t)t * a.tree.stride + leaf0 + li;
-                        static_cast<uint4*>(a.out)[rec * 4 + wo] = o4;
-                    }
-                }
-            } else {
-                // 4 times x 16 leaves x 8 F32 words = 512 words: 8 per lane
-#pragma unroll
-                for (int it = 0; it < 8; ++it) {
-                    const int idx = it * kWave + ln;           // [tq][leaf][w]
-                    const int tq = idx >> 7, li = (idx >> 3) & 15, w = idx & 7;
-                    const int t = t0 + 4 * tq + r;
-                    if (t < a.n_t && li < n_valid) {
-                        const int64_t rec = (int64_t)t * a.tree.stride + leaf0 + li;
-                        static_cast<float4*>(a.out)[rec * 8 + w] = L.out[wv][tq][li][w ^ (li & 7)];
-                    }
-                }
+            for (int m = 0; m < FPO_N_BAKED - 1; ++m) {
+                const int q = FPO_N_SIGMA + FPO_N_SH_FOURIER * m;
+                const float b0 = coef_at(cf, q + kq);
+                const float b1 = kq == 0 ? coef_at(cf, q + 4) : 0.0f;
+                f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                z = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, z, 0, 0, 0);
+                z = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, z, 0, 0, 0);
+                acc[1 + m] = z;
             }
-            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float v[32];
+#pragma unroll
+                for (int q = 0; q < 32; ++q) v[q] = q < FPO_N_BAKED ? acc[q][r] * s : 0.0f;
+                uint4* st = stage[wv][kq][n];
+                if constexpr (OUT_BF16) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w)
+                        st[w ^ (n & 3)] = make_uint4(pack_bf16x2(v[8 * w], v[8 * w + 1]),
+                                                     pack_bf16x2(v[8 * w + 2], v[8 * w + 3]),
+                                                     pack_bf16x2(v[8 * w + 4], v[8 * w + 5]),
+                                                     pack_bf16x2(v[8 * w + 6], v[8 * w + 7]));
+                } else {
+#pragma unroll
+                    for (int w = 0; w < 8; ++w)
+                        st[w ^ (n & 7)] = make_uint4(__float_as_uint(v[4 * w]), __float_as_uint(v[4 * w + 1]),
+                                                     __float_as_uint(v[4 * w + 2]), __float_as_uint(v[4 * w + 3]));
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // 4 times x 16 leaves x kOut words, in runs of 64 consecutive words
+#pragma unroll
+                for (int it = 0; it < kOut; ++it) {
+                    const int tq = it / kRunsPerTime;
+                    const int run = it % kRunsPerTime;
+                    const int li = run * (kWave / kOut) + ln / kOut;
+                    const int w = ln % kOut;
+                    const int t = t0 + 4 * tq + r;
+                    if (t < a.n_t && li < n_valid)
+                        dst[t * row + run * kWave] = stage[wv][tq][li][w ^ (li & (kOut - 1))];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
         }
     }
 }
@@ -297,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void eval_times_kernel(TreeDev tree, const 
                 uint32_t u[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    u[e] = f32_to_bf16_rne(v[8 * w + 2 * e]) | (f32_to_bf16_rne(v[8 * w + 2 * e + 1]) << 16);
+                    u[e] = pack_bf16x2(v[8 * w + 2 * e], v[8 * w + 2 * e + 1]);
                 o[w] = make_uint4(u[0], u[1], u[2], u[3]);
             }
         } else {
@@ -405,17 +426,16 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
     a.tree = dev::tree_dev(tree);
     a.basis = basis;
     a.n_t = n_t;
-    a.out_bf16 = out_dtype == FPO_BF16;
     a.n_leaves = tree->n_leaves;
     a.out = out;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool bf = out_dtype == FPO_BF16;
     if (n_t < kMfmaMinTimes) {
         const dev::TreeDev td = dev::tree_dev(tree);
         const int64_t g1 = (tree->n_leaves + dev::kBlock - 1) / dev::kBlock;
 #define FPO_EVAL(DT, BF)                                                                                   \
     hipLaunchKernelGGL((dev::eval_times_kernel<DT, BF>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td,  \
                        basis, n_t, tree->n_leaves, out)
-        const bool bf = out_dtype == FPO_BF16;
         switch (tree->dtype) {
             case FPO_F32: if (bf) FPO_EVAL(FPO_F32, 1); else FPO_EVAL(FPO_F32, 0); break;
             case FPO_BF16: if (bf) FPO_EVAL(FPO_BF16, 1); else FPO_EVAL(FPO_BF16, 0); break;
@@ -424,16 +444,13 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
 #undef FPO_EVAL
         return launch_status("fpo_bake_times");
     }
+#define FPO_BAKE(DT, BF) \
+    hipLaunchKernelGGL((dev::bake_kernel<DT, BF>), dim3((unsigned)grid), dim3(dev::kBlock), 0, s, a)
     switch (tree->dtype) {
-        case FPO_F32:
-            hipLaunchKernelGGL(dev::bake_kernel<FPO_F32>, dim3((unsigned)grid), dim3(dev::kBlock), 0, s, a);
-            break;
-        case FPO_BF16:
-            hipLaunchKernelGGL(dev::bake_kernel<FPO_BF16>, dim3((unsigned)grid), dim3(dev::kBlock), 0, s, a);
-            break;
-        default:
-            hipLaunchKernelGGL(dev::bake_kernel<FPO_FP8_E4M3>, dim3((unsigned)grid), dim3(dev::kBlock), 0, s, a);
-            break;
+        case FPO_F32: if (bf) FPO_BAKE(FPO_F32, 1); else FPO_BAKE(FPO_F32, 0); break;
+        case FPO_BF16: if (bf) FPO_BAKE(FPO_BF16, 1); else FPO_BAKE(FPO_BF16, 0); break;
+        default: if (bf) FPO_BAKE(FPO_FP8_E4M3, 1); else FPO_BAKE(FPO_FP8_E4M3, 0); break;
     }
+#undef FPO_BAKE
     return launch_status("fpo_bake_times");
 }
