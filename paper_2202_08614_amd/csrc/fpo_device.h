@@ -429,5 +429,132 @@ struct Shade {
     }
 };
 
+// --------------------------------------------------------------------------
+// One ray per wave, for small ray batches and the backward: a fine-tuning
+// batch of a few thousand rays fills only a few dozen wave slots at one ray
+// per lane, and one lane scattering 166 gradients per sample is bound by the
+// number of lines its atomics touch.  All
+// 64 lanes walk the same ray (uniform branches, broadcast child loads).  The
+// 166 F32 coefficients of a leaf are spread over the lanes, lane l holding
+// q = l, l + 64, l + 128, so a record is read (and a gradient record
+// written) with three coalesced accesses, and the dot products of Eq. 7 and
+// Eq. 9 with the SH sums of Eq. 1 become wave sums.
+// --------------------------------------------------------------------------
+
+// fpo_render_rays runs batches of at most this many rays one ray per wave (F32
+// Fourier mode); above it one ray per lane fills the machine and is faster.
+// The backward always runs one ray per wave: its coalesced gradient writes
+// beat one ray per lane at every batch size.
+constexpr int64_t kWaveRayBatch = 32768;
+
+// Butterfly sum over the wave.  Every lane combines the same pairs (a + b and
+// b + a are equal in IEEE arithmetic), so all lanes hold the same bits and
+// branches on the result stay uniform.
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// This lane's coefficient slots for one ray: q = lane + 64 s, s < 3.  A
+// density slot (q < 31) weighs b_q; an SH slot q = 31 + (9 c + j) 5 + i
+// weighs Y_j b_i and feeds channel c.
+struct WaveSlots {
+    float w[3];
+    int c[3];        // channel of an SH slot, -1 density, -2 past the 166 coefficients
+    __device__ inline void init(int lane, const float* brow, const float* Y)
+    {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int q = lane + kWave * s;
+            if (q >= FPO_N_COEFF) {
+                w[s] = 0.0f;
+                c[s] = -2;
+            } else if (q < FPO_N_SIGMA) {
+                w[s] = brow[q];
+                c[s] = -1;
+            } else {
+                const int u = q - FPO_N_SIGMA;
+                const int ch = u / (FPO_N_SH * FPO_N_SH_FOURIER);
+                const int rem = u - ch * (FPO_N_SH * FPO_N_SH_FOURIER);
+                const int j = rem / FPO_N_SH_FOURIER;
+                const int i = rem - j * FPO_N_SH_FOURIER;
+                float yj = Y[0];
+#pragma unroll
+                for (int jj = 1; jj < FPO_N_SH; ++jj) yj = j == jj ? Y[jj] : yj;
+                w[s] = yj * brow[i];
+                c[s] = ch;
+            }
+        }
+    }
+};
+
+// Fourier-mode F32 shading of one ray by a whole wave.  GRAD = false
+// composites front to back (C, Tr).  GRAD = true recomputes the same walk and
+// scatters dL/dk: with C the colour accumulated so far, Cf the forward
+// pass's final colour and g = dL/dCf,
+//     dL/dsigma_i = delta_i s sum_c g_c (T_{i+1} col_c - (Cf_c - C_c)),
+//     dL/dh_c     = g_c T_i alpha_i col_c (1 - col_c),
+// then dL/dk = dL/dsigma b_q (density) or dL/dh_c Y_j b_i (SH).
+template <bool GRAD>
+struct WaveShade {
+    const TreeDev& T;
+    WaveSlots sl;
+    int lane;
+    float Tr;
+    float C[3];
+    float stop_T;
+    float Cf[3];          // GRAD only
+    float g[3];           // GRAD only
+    float* grad;          // GRAD only: F32 leaf records, 192 floats per slot
+
+    __device__ inline bool segment(int leaf, float t0, float t1)
+    {
+        constexpr int kRecFloats = 4 * Pack<FPO_F32>::R;
+        const float delta = t1 - t0;
+        const float* rec = reinterpret_cast<const float*>(T.recs) + (int64_t)leaf * kRecFloats + lane;
+        const float k0 = rec[0];
+        const float sraw = wave_sum(sl.c[0] == -1 ? sl.w[0] * k0 : 0.0f);
+        const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
+        if (!(sig * delta > 0.0f)) return false;   // transparent: contributes nothing
+        const float k[3] = {k0, rec[kWave], sl.c[2] >= 0 ? rec[2 * kWave] : 0.0f};
+        float h[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) h[ch] = fmaf(sl.c[s] == ch ? sl.w[s] : 0.0f, k[s], h[ch]);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) h[ch] = wave_sum(h[ch]);
+        const float e = __expf(-sig * delta);
+        const float w = Tr * (1.0f - e);
+        if constexpr (!GRAD) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) C[ch] = fmaf(w, sigmoidf_(h[ch]), C[ch]);
+        } else {
+            const float T_next = Tr * e;
+            float dsig = 0.0f, dh[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float col = sigmoidf_(h[ch]);
+                C[ch] = fmaf(w, col, C[ch]);
+                dsig = fmaf(g[ch], T_next * col - (Cf[ch] - C[ch]), dsig);
+                dh[ch] = g[ch] * w * col * (1.0f - col);
+            }
+            dsig *= delta * T.sigma_scale;    // sigma_raw > 0 here
+            float* gr = grad + (int64_t)leaf * kRecFloats + lane;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const int ch = sl.c[s];
+                if (ch == -2) continue;
+                const float dv = ch == -1 ? dsig : ch == 0 ? dh[0] : ch == 1 ? dh[1] : dh[2];
+                unsafeAtomicAdd(gr + kWave * s, dv * sl.w[s]);
+            }
+        }
+        Tr *= e;
+        return Tr < stop_T;
+    }
+};
+
 }  // namespace dev
 }  // namespace fpo

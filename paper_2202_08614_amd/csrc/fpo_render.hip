@@ -258,6 +258,34 @@ __global__ __launch_bounds__(kBlock) void render_rays_kernel(RaysLaunch a)
     if (a.Tout) a.Tout[r_id] = sh.Tr;
 }
 
+// F32 Fourier-mode render of a small ray batch, one ray per wave.
+__global__ __launch_bounds__(kBlock) void render_rays_wave_kernel(RaysLaunch a)
+{
+    __shared__ int s_stack[kStackLevels * kBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t r_id = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (r_id >= a.n) return;
+    const int ti = min(max(a.t_idx[r_id], 0), a.n_t - 1);
+    WaveShade<false> sh{a.tree};
+    sh.lane = lane;
+    sh.Tr = 1.0f;
+    sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
+    sh.stop_T = a.stop_T;
+    Ray r;
+    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+                  a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
+        float Y[FPO_N_SH];
+        sh9(r.d[0], r.d[1], r.d[2], Y);
+        sh.sl.init(lane, a.basis + (int64_t)ti * FPO_BASIS_STRIDE, Y);
+        walk(a.tree, r, s_stack + threadIdx.x, sh);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.rgb[r_id * 3 + c] = fmaf(sh.Tr, a.bg[c], sh.C[c]);
+        if (a.Tout) a.Tout[r_id] = sh.Tr;
+    }
+}
+
 // Records the walk's segments, with distances from the caller's origin.
 struct TraceVisitor {
     int32_t* ids;
@@ -511,7 +539,13 @@ extern "C" fpo_status fpo_render_rays(const fpo_tree_view* tree, const float* o,
     a.stop_T = opts->stop_T;
     const int64_t grid = (n_rays + dev::kBlock - 1) / dev::kBlock;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    switch (mode_of(tree, opts)) {
+    const int mode = mode_of(tree, opts);
+    if (mode == FPO_F32 && n_rays <= dev::kWaveRayBatch) {
+        const int64_t wgrid = (n_rays + dev::kBlock / dev::kWave - 1) / (dev::kBlock / dev::kWave);
+        hipLaunchKernelGGL(dev::render_rays_wave_kernel, dim3((unsigned)wgrid), dim3(dev::kBlock), 0, s, a);
+        return launch_status("fpo_render_rays");
+    }
+    switch (mode) {
         case FPO_F32: launch_rays<FPO_F32>(a, grid, s); break;
         case FPO_BF16: launch_rays<FPO_BF16>(a, grid, s); break;
         case FPO_FP8_E4M3: launch_rays<FPO_FP8_E4M3>(a, grid, s); break;

@@ -11,8 +11,9 @@
 // and through Eq. 7 / Eq. 9 and the SH basis of Eq. 1
 //     dL/dk^sigma_q     = s [sigma_raw > 0] dL/dsigma_i b_q,
 //     dL/dk^z_{c,j,i}   = dL/dh_{i,c} Y_j b_i.
-// The 166 coefficient gradients of each sample are scattered with FP32
-// atomics into records laid out like the F32 coefficient store.
+// One wave per ray: each lane owns up to three of a leaf's 166 coefficients,
+// so every sample's gradients go out as three coalesced FP32 atomic adds into
+// records laid out like the F32 coefficient store.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,66 +26,6 @@
 
 namespace fpo {
 namespace dev {
-
-struct BackwardVisitor {
-    const TreeDev& T;
-    const float* b;
-    float* grad;          // F32 leaf records: 192 floats per leaf slot
-    float Y[9];
-    float Tr;
-    float acc[3];         // accumulated colour sum_{j<=i} T_j alpha_j c_j
-    float Cf[3];          // final colour of the forward pass (incl. T_N bg)
-    float g[3];           // dL/dC
-    float stop_T;
-    float sigma_scale;
-
-    __device__ inline void add(int q, int leaf, float v)
-    {
-        float* p = grad + (int64_t)leaf * (4 * Pack<FPO_F32>::R) + q;
-        unsafeAtomicAdd(p, v);
-    }
-
-    __device__ inline bool segment(int leaf, float t0, float t1)
-    {
-        using E = LeafEval<FPO_F32>;
-        const float delta = t1 - t0;
-        float k[E::kSigmaWords * 4];
-        float scale;
-        const float sraw = E::sigma(T, leaf, b, k, scale);
-        const float sig = sigma_scale * fmaxf(sraw, 0.0f);
-        if (!(sig * delta > 0.0f)) return false;
-        float h[3];
-        E::colour(T, leaf, b, Y, k, scale, h);
-        const float e = __expf(-sig * delta);
-        const float alpha = 1.0f - e;
-        const float w = Tr * alpha;
-        const float T_next = Tr * e;
-        float dsig = 0.0f;
-        float dh[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float col = sigmoidf_(h[c]);
-            acc[c] = fmaf(w, col, acc[c]);
-            const float R = Cf[c] - acc[c];
-            dsig = fmaf(g[c], T_next * col - R, dsig);
-            dh[c] = g[c] * w * col * (1.0f - col);
-        }
-        dsig *= delta * sigma_scale;      // d/dsigma_raw (sigma_raw > 0 here)
-#pragma unroll
-        for (int q = 0; q < FPO_N_SIGMA; ++q) add(q, leaf, dsig * b[q]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int j = 0; j < FPO_N_SH; ++j) {
-                const float dz = dh[c] * Y[j];
-#pragma unroll
-                for (int i = 0; i < FPO_N_SH_FOURIER; ++i)
-                    add(FPO_N_SIGMA + (c * FPO_N_SH + j) * FPO_N_SH_FOURIER + i, leaf, dz * b[i]);
-            }
-        Tr = T_next;
-        return Tr < stop_T;
-    }
-};
 
 struct BackwardLaunch {
     TreeDev tree;
@@ -100,35 +41,33 @@ struct BackwardLaunch {
     float stop_T;
 };
 
-__global__ __launch_bounds__(kBlock) void render_backward_kernel(BackwardLaunch a)
+// The backward, one ray per wave.
+__global__ __launch_bounds__(kBlock) void render_backward_wave_kernel(BackwardLaunch a)
 {
     __shared__ int s_stack[kStackLevels * kBlock];
-    const int64_t r_id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t r_id = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (r_id >= a.n) return;
-    int ti = min(max(a.t_idx[r_id], 0), a.n_t - 1);
-    float b[FPO_BASIS_STRIDE];
-    const float4* brow = reinterpret_cast<const float4*>(a.basis + (int64_t)ti * FPO_BASIS_STRIDE);
-#pragma unroll
-    for (int i = 0; i < FPO_BASIS_STRIDE / 4; ++i) {
-        const float4 v = brow[i];
-        b[4 * i] = v.x; b[4 * i + 1] = v.y; b[4 * i + 2] = v.z; b[4 * i + 3] = v.w;
-    }
-    BackwardVisitor vis{a.tree, b, a.grad};
-    vis.Tr = 1.0f;
+    const int ti = min(max(a.t_idx[r_id], 0), a.n_t - 1);
+    WaveShade<true> sh{a.tree};
+    sh.lane = lane;
+    sh.Tr = 1.0f;
+    sh.stop_T = a.stop_T;
+    sh.grad = a.grad;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        vis.acc[c] = 0.0f;
-        vis.Cf[c] = a.rgb_fwd[r_id * 3 + c];
-        vis.g[c] = a.grad_rgb[r_id * 3 + c];
+        sh.C[c] = 0.0f;
+        sh.Cf[c] = a.rgb_fwd[r_id * 3 + c];
+        sh.g[c] = a.grad_rgb[r_id * 3 + c];
     }
-    vis.stop_T = a.stop_T;
-    vis.sigma_scale = a.tree.sigma_scale;
-    if (vis.g[0] == 0.0f && vis.g[1] == 0.0f && vis.g[2] == 0.0f) return;
+    if (sh.g[0] == 0.0f && sh.g[1] == 0.0f && sh.g[2] == 0.0f) return;
     Ray r;
     if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
                   a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
-        sh9(r.d[0], r.d[1], r.d[2], vis.Y);
-        walk(a.tree, r, s_stack + threadIdx.x, vis);
+        float Y[FPO_N_SH];
+        sh9(r.d[0], r.d[1], r.d[2], Y);
+        sh.sl.init(lane, a.basis + (int64_t)ti * FPO_BASIS_STRIDE, Y);
+        walk(a.tree, r, s_stack + threadIdx.x, sh);
     }
 }
 
@@ -216,15 +155,15 @@ extern "C" fpo_status fpo_render_backward(const fpo_tree_view* tree, const float
     if (!o || !d || !t_idx || !basis || !rgb_fwd || !grad_rgb || !grad_coeffs)
         return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
-    if (n_rays > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rays");
+    if (n_rays > (int64_t)INT32_MAX * (dev::kBlock / dev::kWave)) return fail(FPO_E_INVALID, "too many rays");
     dev::BackwardLaunch a;
     std::memset(&a, 0, sizeof(a));
     a.tree = dev::tree_dev(tree);
     a.o = o; a.d = d; a.t_idx = t_idx; a.basis = basis; a.n = n_rays; a.n_t = n_t;
     a.rgb_fwd = rgb_fwd; a.grad_rgb = grad_rgb; a.grad = grad_coeffs;
     a.stop_T = opts->stop_T;
-    const int64_t grid = (n_rays + dev::kBlock - 1) / dev::kBlock;
-    hipLaunchKernelGGL(dev::render_backward_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0,
+    const int64_t wgrid = (n_rays + dev::kBlock / dev::kWave - 1) / (dev::kBlock / dev::kWave);
+    hipLaunchKernelGGL(dev::render_backward_wave_kernel, dim3((unsigned)wgrid), dim3(dev::kBlock), 0,
                        static_cast<hipStream_t>(stream), a);
     return launch_status("fpo_render_backward");
 }

@@ -110,18 +110,19 @@ def test_c1_trace_lists(oracle_lib, c1, dev):
     assert exempt <= 0.01 * len(o32)
 
 
-@pytest.mark.parametrize("seed,depth,stop_T", [(11, 5, 0.0), (12, 7, 0.0), (13, 6, 1e-2)])
-def test_random_trees_render_rays(oracle_lib, dev, seed, depth, stop_T):
+# 3000 rays run one ray per wave; 40000 rays (above the small-batch size) one ray per lane
+@pytest.mark.parametrize("seed,depth,stop_T,n", [(11, 5, 0.0, 3000), (12, 7, 0.0, 3000), (13, 6, 1e-2, 3000),
+                                                 (14, 6, 0.0, 40000), (15, 7, 1e-2, 40000)])
+def test_random_trees_render_rays(oracle_lib, dev, seed, depth, stop_T, n):
     import torch
     dijk = synth.random_tree_leaves(seed, depth, p_split=0.6)
     coeffs = synth.gaussian_coeffs(len(dijk), seed=seed)
     tree = _lib.DeviceTree.from_leaves(dijk, coeffs, depth, device=dev, sigma_scale=16.0)
-    n = 3000
     o, d = synth.random_rays(n, seed + 1)
     times = [0.0, 22.2, 41.3]
     t_idx = (np.arange(n) % 3).astype(np.int32)
     basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
-    note(f"render_rays random tree seed={seed} depth={depth} leaves={len(dijk)} stop_T={stop_T}")
+    note(f"render_rays random tree seed={seed} depth={depth} leaves={len(dijk)} stop_T={stop_T} n={n}")
     rgb, T = _lib.render_rays(tree, torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev),
                               torch.from_numpy(t_idx).to(dev), basis, _lib.make_opts(stop_T=stop_T, bg=(0.1, 0.2, 0.3)),
                               want_T=True)

@@ -41,17 +41,19 @@ def _scene_and_rays(oracle_lib, n_rays, seed, depth=5):
     return dijk, coeffs, o.astype(np.float32), d.astype(np.float32), times, t_idx
 
 
+# forward: 4096 rays run one ray per wave, 40000 rays one ray per lane
+@pytest.mark.parametrize("n_rays", [4096, 40000])
 @pytest.mark.parametrize("stop_T", [0.0, 1e-2])
-def test_backward_matches_oracle_gradient(oracle_lib, dev, stop_T):
+def test_backward_matches_oracle_gradient(oracle_lib, dev, stop_T, n_rays):
     import torch
-    dijk, coeffs, o, d, times, t_idx = _scene_and_rays(oracle_lib, 4096, 3)
+    dijk, coeffs, o, d, times, t_idx = _scene_and_rays(oracle_lib, n_rays, 3)
     tree = _lib.DeviceTree.from_leaves(dijk, coeffs, 5, device=dev, sigma_scale=16.0)
     rng = np.random.default_rng(7)
     g_rgb = rng.standard_normal((len(o), 3)).astype(np.float32)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     basis = to(_lib.time_basis(times))
     opts = _lib.make_opts(stop_T=stop_T, bg=(0.2, 0.3, 0.4))
-    note(f"backward vs oracle stop_T={stop_T}")
+    note(f"backward vs oracle stop_T={stop_T} n_rays={n_rays}")
     rgb, _ = _lib.render_rays(tree, to(o), to(d), to(t_idx), basis, opts)
     grad = torch.zeros_like(tree.coeffs)
     _lib.render_backward(tree, to(o), to(d), to(t_idx), basis, rgb, to(g_rgb), grad, opts)
