@@ -123,6 +123,33 @@ def blob_params(seed: int = GEOMETRY_SEED, n_gauss: int = 8) -> BlobParams:
     return BlobParams(A=A, f=f, phi=phi, w=w, a=a)
 
 
+@dataclasses.dataclass
+class Field:
+    """Analytic radiance field standing in for the generalizable NeRF that the
+    fusion stage queries (Sec. 3): density in stored units and a
+    view-dependent colour,
+        sigma(x)  = sum_g a_g exp(-|x - mu_g|^2 / (2 w_g^2)),
+        c_c(x, d) = 1 / (1 + exp(-(u_c . x + v_c . d + b_c))),  c < 3."""
+    mu: np.ndarray   # [G][3]
+    w: np.ndarray    # [G]
+    a: np.ndarray    # [G]
+    u: np.ndarray    # [3][3]
+    v: np.ndarray    # [3][3]
+    b: np.ndarray    # [3]
+
+
+def fusion_field(t: float = 22.2, seed: int = GEOMETRY_SEED, gain: float = 0.5) -> Field:
+    """The moving blob frozen at time t (the static frame being fused), with
+    a smooth colour that depends on position and view direction."""
+    p = blob_params(seed)
+    mu = 0.5 + p.A * np.sin(2.0 * math.pi * p.f[:, None] * t / PERIOD + p.phi)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    u = rng.normal(0.0, 2.0, size=(3, 3))
+    v = rng.normal(0.0, 1.0, size=(3, 3))
+    b = rng.normal(0.0, 0.5, size=3)
+    return Field(mu=mu, w=p.w.copy(), a=gain * p.a, u=u, v=v, b=b)
+
+
 def blob_max_field(depth: int, params: BlobParams, n_frames: int = 60,
                    period: float = PERIOD) -> np.ndarray:
     """max over frames t = 0..n_frames-1 of the moving-Gaussian density at every cell centre.
