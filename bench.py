@@ -394,6 +394,50 @@ def construct_leg(dev, depth: int = 9, n_union: int = 2_000_000, n_frames: int =
     return res
 
 
+def fusion_leg(dev, sc, tree, n_views: int = 100, size: int = 800, t: float = 22.2):
+    """PlenOctree fusion (Sec. 3, fine stage) on the 2M-leaf scene: the static
+    frame at time t (an F32 snapshot from fpo_bake_times) is fused with the
+    analytic radiance field from 100 dense views at 800x800, one view after
+    another (fpo_fusion_observe, then fpo_fusion_apply)."""
+    import torch
+    from paper_2202_08614_amd import _lib, synth
+    from paper_2202_08614_amd.fusion import Fusion
+    basis = torch.from_numpy(_lib.time_basis([t])).to(dev)
+    values0 = _lib.bake_times(tree, basis, _lib.FPO_F32)[0].clone()
+    field = synth.fusion_field(t)
+    cams = synth.fusion_cameras(n_views, size, size)
+    warm = Fusion(tree, values0.clone(), field)
+    warm.run(cams[:3])
+    del warm
+    fu = Fusion(tree, values0.clone(), field)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in cams]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for cam, (a, b, c) in zip(cams, ev):
+        a.record()
+        _lib.fusion_observe(tree, fu.values, cam, fu.field, fu.acc, fu.tau)
+        b.record()
+        _lib.fusion_apply(fu.values, fu.weight, fu.count, fu.acc, tree.n_leaves)
+        c.record()
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    obs_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    app_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    cnt = fu.count[:tree.n_leaves].cpu().numpy()
+    res = {"views": n_views, "total_ms": round(total_ms, 2), "ms_per_view": round(total_ms / n_views, 4),
+           "observe_ms": round(obs_ms, 4), "observe_Mrays_s": round(size * size / (obs_ms * 1e-3) / 1e6, 1),
+           "apply_ms": round(app_ms, 4),
+           "leaves_observed": int((cnt > 0).sum()), "mean_updates_per_observed_leaf": round(float(cnt[cnt > 0].mean()), 2),
+           "workload": (f"2.0M-leaf depth-9 scene as a static PlenOctree at t = {t} (F32 snapshot), analytic field, "
+                        f"{n_views} views {size}x{size}, tau = 1e-3")}
+    log(f"fusion: {res}")
+    del fu
+    torch.cuda.empty_cache()
+    return res
+
+
 def layouts_leg(dev, sc, tree, reps: int = 3):
     """Fourier-dimension variants (Table 3: n1 in {11, 21, 31}, n2 in {5, 11})
     on the 2.0M-leaf scene: storage per leaf, Fourier-mode render and decode
@@ -480,6 +524,7 @@ def main():
     ap.add_argument("--no-proposal", action="store_true")
     ap.add_argument("--no-construct", action="store_true")
     ap.add_argument("--no-layouts", action="store_true")
+    ap.add_argument("--no-fusion", action="store_true")
     ap.add_argument("--only-construct", action="store_true", help="run only the FPO-construction leg")
     ap.add_argument("--only-proposal", action="store_true", help="run only the learned-proposal leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -679,6 +724,7 @@ def main():
     del frames
     torch.cuda.empty_cache()
     lay = None if args.no_layouts else layouts_leg(dev, sc, tree)
+    fus = None if args.no_fusion else fusion_leg(dev, sc, tree)
     bake = None if args.no_bake else bake_leg(dev, sc, tree, oracle)
     ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
     prop = None if args.no_proposal else proposal_leg(dev, sc, tree, oracle)
@@ -741,6 +787,7 @@ def main():
         "finetune": ft,
         "proposal": prop,
         "construct": cons,
+        "fusion": fus,
         "paper_context": "100 fps at 800x800 (64 Mrays/s) on one RTX 3090, the paper's own scenes",
     }
     print(json.dumps(out), flush=True)

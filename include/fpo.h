@@ -365,6 +365,54 @@ fpo_status fpo_prune_leaves(const float* sigma_max, int64_t n_leaves, float thre
                             int64_t* n_keep_out);
 
 /* ---------------------------------------------------------------------- */
+/* PlenOctree fusion (Sec. 3, fine stage: Eq. 3-5)                         */
+/* ---------------------------------------------------------------------- */
+#define FPO_FIELD_MAX_GAUSS 8
+#define FPO_FUSION_ACC 32          /* accumulator floats per leaf slot */
+
+/* Analytic radiance field standing in for the generalizable network the
+ * fusion queries (the network itself is not part of this library):
+ *   sigma(x)  = sum_{g < n_gauss} a_g exp(-|x - mu_g|^2 / (2 w_g^2))   (stored units)
+ *   c_c(x, d) = 1 / (1 + exp(-(u_c . x + v_c . d + b_c))),  c < 3, d unit. */
+typedef struct {
+    float mu[FPO_FIELD_MAX_GAUSS][3];
+    float w[FPO_FIELD_MAX_GAUSS];
+    float a[FPO_FIELD_MAX_GAUSS];
+    int32_t n_gauss;
+    float u[3][3];
+    float v[3][3];
+    float b[3];
+} fpo_field;
+
+/* Observe pass of one fusion view (Sec. 3: render a view of the PlenOctree
+ * and query the points met with transmittance T > 1e-3).  Every pixel ray of
+ * cam walks the static PlenOctree front to back with the transmittance of
+ * the current values (sigma_eff = tree->layout.sigma_scale * max(sigma, 0)).
+ * Each leaf segment [t0, t1) entered with T > tau is an observation at its
+ * midpoint x along the ray direction d, weighted by its length delta:
+ *   acc[l][0] += T delta           acc[l][1] += T delta sigma(x)
+ *   acc[l][2 + 9c + j] += T delta Y_j(d) c_c(x, d)      acc[l][29] += delta
+ * (Y the real SH of degree 2); the walk stops at the first segment entered
+ * with T <= tau.  Only the tree structure of `tree` is used.
+ *   values  device [leaf_stride][32] F32 leaf records in slot order: 0 = sigma,
+ *           1 + 9c + j = z_{c,j} (the layout fpo_bake_times writes).
+ *   acc     device [leaf_stride][FPO_FUSION_ACC] F32, ADDED to (FP32 atomics:
+ *           the order of the sums is not fixed).  fpo_fusion_apply clears it. */
+fpo_status fpo_fusion_observe(const fpo_tree_view* tree, const float* values, const fpo_camera* cam,
+                              const fpo_field* field, float tau, float* acc, void* stream);
+
+/* Apply pass: Eq. 3-5 once for every leaf observed in the view (acc[l][29]
+ * > 0), with the view's length-weighted mean transmittance T_i = acc0 / acc29:
+ *   sigma <- (W sigma + acc1 / acc29) / (W + T_i)
+ *   z     <- (W z + acc[2 + q] / acc29) / (W + T_i)
+ *   C <- C + 1;  W <- (C - 1) / C W + T_i / C
+ * then clears acc[l].  Leaves not observed are left as they are.
+ *   values device [n_leaves][32] F32 (as above), weight device [n_leaves] F32,
+ *   count device [n_leaves] int32, acc device [n_leaves][FPO_FUSION_ACC]. */
+fpo_status fpo_fusion_apply(float* values, float* weight, int32_t* count, float* acc, int64_t n_leaves,
+                            void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Learned proposal (not in the paper)                                      */
 /* ---------------------------------------------------------------------- */
 /* A small MLP predicts, per ray and time, whether the ray meets a

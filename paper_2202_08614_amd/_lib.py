@@ -61,6 +61,16 @@ class CameraC(ctypes.Structure):
                 ("time", ctypes.c_double)]
 
 
+FIELD_MAX_GAUSS = 8
+FUSION_ACC = 32
+
+
+class FieldC(ctypes.Structure):
+    _fields_ = [("mu", (ctypes.c_float * 3) * FIELD_MAX_GAUSS), ("w", ctypes.c_float * FIELD_MAX_GAUSS),
+                ("a", ctypes.c_float * FIELD_MAX_GAUSS), ("n_gauss", ctypes.c_int32),
+                ("u", (ctypes.c_float * 3) * 3), ("v", (ctypes.c_float * 3) * 3), ("b", ctypes.c_float * 3)]
+
+
 class RenderOpts(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_float * 3), ("stop_T", ctypes.c_float),
                 ("snapshot", ctypes.c_void_p), ("snapshot_dtype", ctypes.c_int),
@@ -104,6 +114,9 @@ _SIGS = {
     "fpo_frame_values": [ctypes.POINTER(TreeView), _P, _P, _P, _I64, _P, _P, _P],
     "fpo_dft_frames": [_P, _I32, _I64, _I64, _I32, _P, _P, _P],
     "fpo_prune_leaves": [_P, _I64, ctypes.c_float, _P, _P],
+    "fpo_fusion_observe": [ctypes.POINTER(TreeView), _P, ctypes.POINTER(CameraC), ctypes.POINTER(FieldC),
+                           ctypes.c_float, _P, _P],
+    "fpo_fusion_apply": [_P, _P, _P, _P, _I64, _P],
 }
 # functions with another return type
 _OTHER = {"fpo_mlp_workspace_floats": ([_I64], ctypes.c_int64)}
@@ -545,3 +558,42 @@ def prune_leaves(sigma_max: np.ndarray, threshold: float = PRUNE_SIGMA) -> np.nd
     n = ctypes.c_int64(0)
     _check(lib().fpo_prune_leaves(_np_ptr(sm), int(sm.shape[0]), float(threshold), _np_ptr(keep), ctypes.byref(n)))
     return keep[:n.value]
+
+
+# ---------------------------------------------------------------------------
+# PlenOctree fusion
+# ---------------------------------------------------------------------------
+def field_struct(field) -> FieldC:
+    """fpo_field from an object with mu [G][3], w [G], a [G], u, v [3][3], b [3]."""
+    f = FieldC()
+    n = len(field.w)
+    if n > FIELD_MAX_GAUSS:
+        raise ValueError(f"at most {FIELD_MAX_GAUSS} Gaussians")
+    for g in range(n):
+        for c in range(3):
+            f.mu[g][c] = float(field.mu[g][c])
+        f.w[g] = float(field.w[g])
+        f.a[g] = float(field.a[g])
+    f.n_gauss = n
+    for c in range(3):
+        for k in range(3):
+            f.u[c][k] = float(field.u[c][k])
+            f.v[c][k] = float(field.v[c][k])
+        f.b[c] = float(field.b[c])
+    return f
+
+
+def fusion_observe(tree: DeviceTree, values, cam, field, acc, tau: float = 1e-3):
+    """fpo_fusion_observe: values [leaf_stride][32] F32 (slot order), acc
+    [leaf_stride][32] F32 (added to)."""
+    tv = tree.view()
+    cs = camera_struct([cam])
+    fs = field_struct(field) if not isinstance(field, FieldC) else field
+    _check(lib().fpo_fusion_observe(ctypes.byref(tv), _t_ptr(values), cs, ctypes.byref(fs), float(tau),
+                                    _t_ptr(acc), _stream()))
+
+
+def fusion_apply(values, weight, count, acc, n_leaves: int):
+    """fpo_fusion_apply over the first n_leaves slots."""
+    _check(lib().fpo_fusion_apply(_t_ptr(values), _t_ptr(weight), _t_ptr(count), _t_ptr(acc), int(n_leaves),
+                                  _stream()))

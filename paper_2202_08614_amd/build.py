@@ -23,6 +23,7 @@ SOURCES = [
     "fpo_bake.hip",
     "fpo_proposal.hip",
     "fpo_construct.hip",
+    "fpo_fusion.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -298,6 +298,14 @@ def c4_cameras(width: int = 800, height: int = 800) -> List[Camera]:
     return cams
 
 
+def fusion_cameras(n: int = 100, width: int = 800, height: int = 800) -> List[Camera]:
+    """Dense views for the fusion stage: azimuths on the golden angle,
+    elevations spread over [-40, 40] degrees, radius 1.6, FOV 40 degrees."""
+    golden = (math.sqrt(5.0) - 1.0) / 2.0
+    return [ring_camera(2.0 * math.pi * ((k * golden) % 1.0), math.radians(-40.0 + 80.0 * (k + 0.5) / n), 1.6,
+                        40.0, width, height, 0.0) for k in range(n)]
+
+
 def c4_scene(n_leaves: int = 500_000) -> Scene:
     dijk = blob_leaves(8, n_leaves)
     coeffs = gaussian_coeffs(dijk.shape[0])

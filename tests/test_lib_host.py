@@ -304,3 +304,39 @@ def test_other_layouts_are_limited_to_render_pack_and_bake():
     assert L.fpo_pack_coeffs(p, p, 1, 1, ctypes.byref(bad), p, None) == _lib.FPO_E_UNSUPPORTED
     assert _lib.layout_record_words(31, 5) == 48 and _lib.layout_record_words(11, 5) == 40
     assert _lib.layout_record_words(31, 11) == 88
+
+
+@host_only
+def test_fusion_calls_validate_on_host():
+    """fpo_fusion_observe / fpo_fusion_apply refuse bad arguments before any launch."""
+    L = _lib.lib()
+    view = _lib.TreeView()
+    view.children = 16
+    view.n_nodes = 1
+    view.max_depth = 3
+    view.n_leaves = 1
+    view.leaf_stride = 1
+    view.layout = _lib.make_layout()
+    cam = _lib.camera_struct([synth.ring_camera(0, 0, 1.5, 30, 4, 4, 0)])
+    field = _lib.field_struct(synth.fusion_field())
+    p = ctypes.c_void_p(16)
+    for tau in (0.0, 1.0, -1.0, float("nan")):
+        st = L.fpo_fusion_observe(ctypes.byref(view), p, cam, ctypes.byref(field), tau, p, None)
+        assert st == _lib.FPO_E_INVALID and b"tau" in L.fpo_last_error()
+    st = L.fpo_fusion_observe(ctypes.byref(view), None, cam, ctypes.byref(field), 1e-3, p, None)
+    assert st == _lib.FPO_E_INVALID and b"NULL" in L.fpo_last_error()
+    bad = _lib.field_struct(synth.fusion_field())
+    bad.n_gauss = 9
+    st = L.fpo_fusion_observe(ctypes.byref(view), p, cam, ctypes.byref(bad), 1e-3, p, None)
+    assert st == _lib.FPO_E_INVALID and b"n_gauss" in L.fpo_last_error()
+    bad.n_gauss = 2
+    bad.w[1] = 0.0
+    st = L.fpo_fusion_observe(ctypes.byref(view), p, cam, ctypes.byref(bad), 1e-3, p, None)
+    assert st == _lib.FPO_E_INVALID and b"widths" in L.fpo_last_error()
+    assert L.fpo_fusion_apply(p, p, p, p, -1, None) == _lib.FPO_E_INVALID
+    assert L.fpo_fusion_apply(ctypes.c_void_p(20), p, p, p, 3, None) == _lib.FPO_E_INVALID
+    assert b"aligned" in L.fpo_last_error()
+    assert L.fpo_fusion_apply(None, None, None, None, 0, None) == _lib.FPO_OK
+    with pytest.raises(ValueError):
+        _lib.field_struct(synth.Field(mu=np.zeros((9, 3)), w=np.ones(9), a=np.ones(9), u=np.zeros((3, 3)),
+                                      v=np.zeros((3, 3)), b=np.zeros(3)))
