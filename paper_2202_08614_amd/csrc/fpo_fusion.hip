@@ -60,10 +60,20 @@ __device__ inline float field_sigma(const FieldDev& f, const float x[3])
     return s;
 }
 
+constexpr int kObs = 30;            // accumulator values per observation
+constexpr int kObsStride = 36;      // LDS floats per staged observation (9 x 16 bytes: spreads banks)
+
+// The lanes that shade a segment in the same step stage their observations in
+// the wave's LDS buffer and then add them to the accumulators together: the
+// (observation, value) pairs are dealt out over those lanes, so one atomic
+// instruction covers consecutive values of one or two leaf records instead of
+// the same value of up to 64 different leaves.
 struct FusionVisitor {
     const float* values;
     float* acc;
     const FieldDev& f;
+    float* stage;           // this wave's [64][kObsStride] LDS buffer
+    int lane;
     float o[3];             // entry point: walk distances are measured from it
     float d[3];             // unit direction
     float Y[FPO_N_SH];
@@ -75,7 +85,11 @@ struct FusionVisitor {
     {
         if (!(T > tau)) return true;
         const float delta = t1 - t0;
-        if (delta > 0.0f) {
+        const bool obs = delta > 0.0f;
+        const uint64_t act = __ballot(obs);
+        if (obs) {
+            const int k = __popcll(act);
+            const int rank = __popcll(act & ((1ull << lane) - 1ull));
             const float tm = 0.5f * (t0 + t1);
             const float x[3] = {fmaf(tm, d[0], o[0]), fmaf(tm, d[1], o[1]), fmaf(tm, d[2], o[2])};
             const float sig = field_sigma(f, x);
@@ -88,16 +102,33 @@ struct FusionVisitor {
                 col[c] = sigmoidf_(h);
             }
             const float w = T * delta;
-            float* A = acc + (int64_t)leaf * FPO_FUSION_ACC;
-            unsafeAtomicAdd(A, w);
-            unsafeAtomicAdd(A + 1, w * sig);
+            float v[kObsStride];
+            v[0] = w;
+            v[1] = w * sig;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float wc = w * col[c];
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int j = 0; j < FPO_N_SH; ++j) unsafeAtomicAdd(A + 2 + c * FPO_N_SH + j, wc * Y[j]);
+                for (int j = 0; j < FPO_N_SH; ++j) v[2 + c * FPO_N_SH + j] = w * col[c] * Y[j];
+            v[29] = delta;
+            v[30] = 0.0f;
+            v[31] = __int_as_float(leaf);
+#pragma unroll
+            for (int e = 32; e < kObsStride; ++e) v[e] = 0.0f;
+            float4* st = reinterpret_cast<float4*>(stage + rank * kObsStride);
+#pragma unroll
+            for (int q = 0; q < kObsStride / 4; ++q) st[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int p = rank; p < k * kObs; p += k) {
+                const int s = p / kObs;
+                const int e = p - s * kObs;
+                const float* src = stage + s * kObsStride;
+                const int l = __float_as_int(src[31]);
+                unsafeAtomicAdd(acc + (int64_t)l * FPO_FUSION_ACC + e, src[e]);
             }
-            unsafeAtomicAdd(A + 29, delta);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             T *= __expf(-sigma_scale * fmaxf(values[(int64_t)leaf * 32], 0.0f) * delta);
         }
         return !(T > tau);
@@ -108,6 +139,7 @@ struct FusionVisitor {
 __global__ __launch_bounds__(kBlock) void fusion_observe_kernel(FusionLaunch a)
 {
     __shared__ int s_stack[kStackLevels * kBlock];
+    __shared__ __align__(16) float s_obs[kBlock / kWave][kWave * kObsStride];
     const int wv = threadIdx.x >> 6;
     const int ln = threadIdx.x & 63;
     const int bxi = blockIdx.x % a.bx;
@@ -122,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void fusion_observe_kernel(FusionLaunch a)
     const float dz = a.frame[5] + sx * a.frame[8] + sy * a.frame[11];
     Ray r;
     if (!setup_ray(a.frame[0], a.frame[1], a.frame[2], dx, dy, dz, r)) return;
-    FusionVisitor vis{a.values, a.acc, a.f};
+    FusionVisitor vis{a.values, a.acc, a.f, s_obs[wv], ln};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         vis.o[c] = r.o[c];
