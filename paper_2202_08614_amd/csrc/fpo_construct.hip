@@ -14,8 +14,9 @@
 // c_i = 2/T, or 1/T for every i with the printed weights), computed from exact
 // integer phases (i t mod 2T) with sinpi / cospi.  The 64 records of a tile are
 // contiguous in every frame: the block stages 4 frames of them at a time into
-// LDS with whole-line loads, then each wave reads its values from there.  The
-// kernel streams T records per leaf and is bound by HBM reads.
+// LDS with whole-line loads, then each wave reads its values from there; the
+// next 4 frames' loads are in flight in registers meanwhile.  The kernel
+// streams T records per leaf and is bound by HBM reads.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -111,60 +112,95 @@ __global__ __launch_bounds__(256) void dft_kernel(DftLaunch a)
     const int ll = threadIdx.x & 63;         // leaf within the tile
     const int q0 = 9 * (g - 1);              // SH coefficients q0 .. q0 + 8 (g >= 1), record values 1 + q
     const int64_t n_tiles = (a.n_leaves + 63) / 64;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t l0 = tile * 64;
-        const int64_t l = l0 + ll;
+    const int steps_per_tile = (T + kDftFrames - 1) / kDftFrames;
+    // The block's work is a flat sequence of (tile, frame group) steps.  The
+    // record words of step k + 1 are loaded into registers while step k is
+    // computed, so the loads overlap the arithmetic.
+    int64_t tile = blockIdx.x;
+    int step = 0;
+    float4 pf[kDftFrames * 2];
+    auto fetch = [&](int64_t tl, int st) {
+        const int64_t l0 = tl * 64;
         const int nl = (int)min<int64_t>(64, a.n_leaves - l0);
-        float acc[45];
+        const int f0 = st * kDftFrames;
 #pragma unroll
-        for (int e = 0; e < 45; ++e) acc[e] = 0.0f;
-        float smax = -__builtin_inff();
-        for (int t0 = 0; t0 < T; t0 += kDftFrames) {
-            const int nf = min(kDftFrames, T - t0);
-            // stage nf frames x 64 records: 512 float4 per frame, coalesced
-            for (int e = threadIdx.x; e < nf * 512; e += 256) {
-                const int f = e >> 9, w = e & 511;
-                const int rl = w >> 3, rw = w & 7;
-                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (rl < nl)
-                    v = reinterpret_cast<const float4*>(a.frames + ((int64_t)(t0 + f) * a.stride + l0) * 32)[w];
-                float* d = &X[f][rl * kRecPad + rw * 4];
-                d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-            }
-            __syncthreads();
-            for (int f = 0; f < nf; ++f) {
-                const float* r = &X[f][ll * kRecPad];
-                const float* bt = B[t0 + f];
-                if (g == 0) {
-                    const float s = r[0];
-                    smax = fmaxf(smax, s);
+        for (int u = 0; u < kDftFrames * 2; ++u) {
+            const int e = u * 256 + threadIdx.x;      // [frame][record][word]: 512 float4 per frame
+            const int f = e >> 9, w = e & 511;
+            const int rl = w >> 3;
+            pf[u] = (f0 + f < T && rl < nl)
+                        ? reinterpret_cast<const float4*>(a.frames + ((int64_t)(f0 + f) * a.stride + l0) * 32)[w]
+                        : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    };
+    if (tile < n_tiles) fetch(tile, 0);
+    float acc[45];
+    float smax = -__builtin_inff();
 #pragma unroll
-                    for (int i = 0; i < FPO_N_SIGMA; ++i) acc[i] = fmaf(s, bt[i], acc[i]);
-                } else {
+    for (int e = 0; e < 45; ++e) acc[e] = 0.0f;
+    while (tile < n_tiles) {
+        const int64_t l0 = tile * 64;
+        const int nl = (int)min<int64_t>(64, a.n_leaves - l0);
+        const int t0 = step * kDftFrames;
+        const int nf = min(kDftFrames, T - t0);
+        // park this step's words in LDS (the previous step's reads are done)
+        __syncthreads();
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) {
-                        const float z = r[1 + q0 + q];
+        for (int u = 0; u < kDftFrames * 2; ++u) {
+            const int e = u * 256 + threadIdx.x;
+            const int f = e >> 9, w = e & 511;
+            const int rl = w >> 3, rw = w & 7;
+            float* d = &X[f][rl * kRecPad + rw * 4];
+            d[0] = pf[u].x; d[1] = pf[u].y; d[2] = pf[u].z; d[3] = pf[u].w;
+        }
+        __syncthreads();
+        // next step's loads, in flight during this step's arithmetic
+        int64_t n_tile = tile;
+        int n_step = step + 1;
+        if (n_step == steps_per_tile) {
+            n_step = 0;
+            n_tile += gridDim.x;
+        }
+        if (n_tile < n_tiles) fetch(n_tile, n_step);
+        for (int f = 0; f < nf; ++f) {
+            const float* r = &X[f][ll * kRecPad];
+            const float* bt = B[t0 + f];
+            if (g == 0) {
+                const float sv = r[0];
+                smax = fmaxf(smax, sv);
 #pragma unroll
-                        for (int i = 0; i < FPO_N_SH_FOURIER; ++i) acc[q * 5 + i] = fmaf(z, bt[i], acc[q * 5 + i]);
-                    }
+                for (int i = 0; i < FPO_N_SIGMA; ++i) acc[i] = fmaf(sv, bt[i], acc[i]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const float z = r[1 + q0 + q];
+#pragma unroll
+                    for (int i = 0; i < FPO_N_SH_FOURIER; ++i) acc[q * 5 + i] = fmaf(z, bt[i], acc[q * 5 + i]);
                 }
             }
-            __syncthreads();
         }
-        if (ll < nl) {
-            float* out = a.coeffs + l * 192;
-            if (g == 0) {
+        if (step + 1 == steps_per_tile) {
+            const int64_t l = l0 + ll;
+            if (ll < nl) {
+                float* out = a.coeffs + l * 192;
+                if (g == 0) {
 #pragma unroll
-                for (int i = 0; i < FPO_N_SIGMA; ++i) out[i] = acc[i];
-                if (a.sigma_max) a.sigma_max[l] = smax;
-            } else {
-                float* o = out + FPO_N_SIGMA + q0 * FPO_N_SH_FOURIER;
+                    for (int i = 0; i < FPO_N_SIGMA; ++i) out[i] = acc[i];
+                    if (a.sigma_max) a.sigma_max[l] = smax;
+                } else {
+                    float* o = out + FPO_N_SIGMA + q0 * FPO_N_SH_FOURIER;
 #pragma unroll
-                for (int e = 0; e < 45; ++e) o[e] = acc[e];
-                if (g == 3)
-                    for (int e = FPO_N_COEFF; e < 192; ++e) out[e] = 0.0f;
+                    for (int e = 0; e < 45; ++e) o[e] = acc[e];
+                    if (g == 3)
+                        for (int e = FPO_N_COEFF; e < 192; ++e) out[e] = 0.0f;
+                }
             }
+#pragma unroll
+            for (int e = 0; e < 45; ++e) acc[e] = 0.0f;
+            smax = -__builtin_inff();
         }
+        tile = n_tile;
+        step = n_step;
     }
 }
 
