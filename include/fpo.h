@@ -99,7 +99,7 @@ typedef struct {
 typedef struct {
     const int32_t* children;  /* device [n_nodes][8] int32: 0 empty, >0 node, <0 -(leaf slot + 1);
                                  node 0 is the root; octant = x | y << 1 | z << 2 */
-    int64_t n_nodes;
+    int64_t n_nodes;          /* 1 .. 2^26 - 1 (32-bit byte offsets into children) */
     int32_t max_depth;        /* 1 .. FPO_MAX_DEPTH */
     const void* coeffs;       /* device leaf records (see above) */
     const float* leaf_scale;  /* device [leaf_stride] for BF16 / FP8, ignored for F32 */

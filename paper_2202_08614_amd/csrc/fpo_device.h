@@ -194,12 +194,17 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 // t_end the walk consults stop.more() once a step ends at or past t_end.
 // --------------------------------------------------------------------------
 struct NoStop {
-    __host__ __device__ inline bool more(float, float&) { return false; }
+    __device__ inline bool more(float, float&) { return false; }
 };
 
 template <class Visitor, class Stop>
-__host__ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop)
+__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop)
 {
+    // The child table is read through a buffer resource: 32-bit byte offsets
+    // (no 64-bit address arithmetic per step), and a read past the table
+    // returns 0 (an empty slot).
+    const __amdgpu_buffer_rsrc_t ct =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(T.children), (short)0, T.n_nodes * 32, 0x00020000);
     const int D = T.max_depth;
     const int G = 1 << D;
     const float fG = (float)G;
@@ -227,18 +232,25 @@ __host__ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, V
     const int max_steps = 3 * G + 4;
     for (int it = 0; it < max_steps; ++it) {
         int ch;
-        int csh;
+        int csh = D - 1 - lvl;
+        // octant of the current slot in its parent (mirrored back to the table's frame)
+        int oct = (((pos[0] >> csh) & 1) | (((pos[1] >> csh) & 1) << 1) | (((pos[2] >> csh) & 1) << 2)) ^ mirror;
         for (;;) {
-            csh = D - 1 - lvl;
-            const int oct = (((pos[0] >> csh) & 1) | (((pos[1] >> csh) & 1) << 1) | (((pos[2] >> csh) & 1) << 2)) ^ mirror;
-            ch = T.children[node * 8 + oct];
+            ch = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
             if (ch > 0 && ch < T.n_nodes && lvl < D - 1) {
                 ++lvl;
                 node = ch;
                 stk[lvl * kBlock] = node;
                 const int S = 1 << (csh - 1);
+                // the child's octant is the half the ray is in on each axis
+                oct = mirror;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) pos[a] += ((float)(pos[a] + S) - xf[a]) * k[a] <= t_cur ? S : 0;
+                for (int a = 0; a < 3; ++a) {
+                    const bool up = ((float)(pos[a] + S) - xf[a]) * k[a] <= t_cur;
+                    pos[a] += up ? S : 0;
+                    oct ^= up ? (1 << a) : 0;
+                }
+                csh -= 1;
                 continue;
             }
             if (ch > 0) ch = 0;   // malformed table: treat as empty
@@ -277,7 +289,7 @@ __host__ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, V
 }
 
 template <class Visitor>
-__host__ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
+__device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
 {
     NoStop ns;
     walk(T, r, stk, vis, __builtin_inff(), ns);

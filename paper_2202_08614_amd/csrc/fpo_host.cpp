@@ -35,7 +35,8 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_la
 {
     if (!tree) return fail(FPO_E_INVALID, "tree is NULL");
     if (!tree->children) return fail(FPO_E_INVALID, "tree->children is NULL");
-    if (tree->n_nodes < 1 || tree->n_nodes > INT32_MAX / 8)
+    // byte offsets into the child table are 32-bit: at most 2^26 - 1 nodes
+    if (tree->n_nodes < 1 || tree->n_nodes > INT32_MAX / 32)
         return fail(FPO_E_INVALID, "tree->n_nodes out of range");
     if (tree->max_depth < 1 || tree->max_depth > FPO_MAX_DEPTH)
         return fail(FPO_E_INVALID, "tree->max_depth must be in 1..10");
