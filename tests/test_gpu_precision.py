@@ -202,3 +202,37 @@ def test_decode_then_render_matches_oracle(oracle_lib, dev):
         o, d = oracle_lib.camera_rays(cams[k])
         ref = conditioned_reference(oracle_lib, ot, sc.coeffs, p, [t], o, d, np.zeros(len(o), np.int32))
         check_parity(rgb[k].cpu().numpy().reshape(-1, 3), ref, TOL)
+
+
+@pytest.mark.parametrize("store", [_lib.FPO_BF16, _lib.FPO_FP8_E4M3])
+def test_c3_bake_sampled(oracle_lib, dev, store):
+    """The bake at full size: the 2M-leaf scene quantised per leaf, 64 times
+    baked into BF16 snapshots in one call (the benchmark's launch); 4096
+    sampled leaves against the oracle's bake of their dequantised
+    coefficients, every time and value."""
+    import torch
+    sc = synth.c2_scene()
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    kind = {_lib.FPO_BF16: "bf16", _lib.FPO_FP8_E4M3: "fp8"}[store]
+    qt = _lib.quantize(tree, store)
+    n_t = 64
+    times = [k * synth.PERIOD / n_t for k in range(n_t)]
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    note(f"c3 fpo_bake_times {kind} store, 64 times x 2M leaves, BF16 out")
+    snaps = _lib.bake_times(qt, basis, _lib.FPO_BF16)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(64)
+    pick = rng.choice(sc.n_leaves, 4096, replace=False)          # caller-order leaves
+    inv = np.empty_like(tree.perm)
+    inv[tree.perm] = np.arange(len(tree.perm))                    # caller index -> slot
+    slots = torch.from_numpy(inv[pick].astype(np.int64)).to(dev)
+    got = snaps[:, slots, :28].float().cpu().numpy().transpose(0, 2, 1)      # [n_t][28][4096]
+    codes, scale = codec.quantize(sc.coeffs[pick], kind)
+    k_eff = codec.dequantize(codes, scale, kind)
+    want = oracle_lib.bake(k_eff, oracle_lib.make_params(), times)          # [n_t][28][4096]
+    B = np.stack([oracle_lib.basis(t, 60.0, 31) for t in times])
+    ka = np.abs(k_eff)
+    mag = np.zeros_like(want)
+    mag[:, 0] = np.abs(B) @ ka[:, :31].T
+    mag[:, 1:] = np.einsum("ti,lmi->tml", np.abs(B[:, :5]), ka[:, 31:].reshape(-1, 27, 5))
+    assert np.all(np.abs(got - want) <= 2.0 ** -8 * np.abs(want) + 2.0 ** -19 * mag + 1e-7)

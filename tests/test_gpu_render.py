@@ -269,3 +269,36 @@ def test_c2_sampled_parity(oracle_lib, c2, dev):
     assert hit.sum() > m // 3
     assert (ref["T"][:, 1] < 1e-3).sum() > 50          # early termination is exercised
     check_parity(got, ref, TOL)
+
+
+def test_c2_decode_sampled_parity(oracle_lib, c2, dev):
+    """The headline path at full size: the per-time IDFT pass (fpo_bake_times at
+    one time, F32 snapshot) and the snapshot render of the benchmark's 16
+    cameras, 1920x1080, early termination at 1e-3; sampled pixels against the
+    oracle on the Fourier coefficients."""
+    import torch
+    sc, tree = c2
+    cams = sc.cameras[:16]
+    basis = torch.from_numpy(_lib.time_basis([cams[0].time])).to(dev)
+    note("c2 decode: fpo_bake_times F32 + snapshot fpo_render 16 x 1920x1080")
+    snap = _lib.bake_times(tree, basis, _lib.FPO_F32)
+    opts = _lib.make_opts(stop_T=sc.stop_T, snapshot=snap, snapshot_dtype=_lib.FPO_F32, snapshot_cam_stride=0)
+    rgb, _ = _lib.render(tree, cams, opts)
+    torch.cuda.synchronize()
+    rgb = rgb.cpu().numpy()
+    rng = np.random.default_rng(2023)
+    m = 3000
+    ci = rng.integers(0, 16, m)
+    central = rng.random(m) < 0.8
+    px = np.where(central, rng.integers(int(0.35 * 1920), int(0.65 * 1920), m), rng.integers(0, 1920, m))
+    py = np.where(central, rng.integers(int(0.25 * 1080), int(0.75 * 1080), m), rng.integers(0, 1080, m))
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, 9)
+    p = oracle_lib.make_params(stop_T=sc.stop_T, band=1e-3)
+    o = np.zeros((m, 3)); d = np.zeros((m, 3))
+    for k in range(m):
+        ro, rd = oracle_lib.camera_rays(cams[ci[k]], np.array([px[k]]), np.array([py[k]]))
+        o[k], d[k] = ro[0], rd[0]
+    ref = conditioned_reference(oracle_lib, ot, sc.coeffs, p, [cams[0].time], o, d, np.zeros(m, np.int32))
+    got = rgb[ci, py, px]
+    assert (ref["n_seg"][:, 0] > 0).sum() > m // 3
+    check_parity(got, ref, TOL)

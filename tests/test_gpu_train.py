@@ -173,3 +173,42 @@ def test_finetune_converges(dev):
     last = ft.train(5)
     torch.cuda.synchronize()
     assert np.mean(last) < 0.5 * np.mean(first), (first, last)
+
+
+def test_c4_batch_gradient_matches_oracle(oracle_lib, dev):
+    """The fine-tune step at full size: the 500k-leaf depth-8 scene, one
+    8192-ray batch drawn over its 24 cameras x 30 times at 800x800 (the
+    benchmark's batch); forward colours and the gradient of every coefficient
+    against the FP64 oracle."""
+    import torch
+    sc = synth.c4_scene()
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    cams = sc.cameras
+    times = sorted({c.time for c in cams})
+    ci, py, px = synth.sample_pixels(8192, len(cams), 800, 800)
+    o = np.zeros((8192, 3)); d = np.zeros((8192, 3))
+    for c in np.unique(ci):
+        sel = np.nonzero(ci == c)[0]
+        o[sel], d[sel] = oracle_lib.camera_rays(cams[c], px[sel], py[sel])
+    t_idx = np.array([times.index(cams[c].time) for c in ci], np.int32)
+    g_rgb = np.random.default_rng(8).standard_normal((8192, 3)).astype(np.float32)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    basis = to(_lib.time_basis(times))
+    opts = _lib.make_opts(stop_T=1e-3)
+    note("c4 render_rays + render_backward 8192 rays, 500k leaves")
+    rgb, _ = _lib.render_rays(tree, to(o.astype(np.float32)), to(d.astype(np.float32)), to(t_idx), basis, opts)
+    grad = torch.zeros_like(tree.coeffs)
+    _lib.render_backward(tree, to(o.astype(np.float32)), to(d.astype(np.float32)), to(t_idx), basis, rgb,
+                         to(g_rgb), grad, opts)
+    torch.cuda.synchronize()
+    got = _unpack(grad.cpu().numpy(), tree.perm, sc.n_leaves)
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
+    p = oracle_lib.make_params(stop_T=1e-3)
+    want, rgb_ref = oracle_lib.render_grad(ot, sc.coeffs, p, times, o, d, t_idx, g_rgb.astype(np.float64))
+    # colours within 1e-4; a ray at a cell-face tie (about 2 in 10^5 on this scene) may differ
+    err = np.abs(rgb.cpu().numpy() - rgb_ref).max(axis=1)
+    assert (err > 1e-4).sum() <= 2, np.sort(err)[-5:]
+    gmax = np.abs(want).max()
+    assert gmax > 0 and (np.abs(want) > 1e-3 * gmax).sum() > 10000
+    bad = np.abs(got - want) > 1e-3 * np.abs(want) + 1e-5 * gmax
+    assert bad.sum() <= 1e-5 * bad.size, (bad.sum(), np.abs(got - want).max(), gmax)
