@@ -355,3 +355,35 @@ def test_proposal_training_and_gain(oracle_lib, dev, blob_scene):
             ts.append(time.perf_counter() - t0)
         times[name] = float(np.median(ts))
     print("[proposal] 16 x 480x270 render ms: " + ", ".join(f"{n} {1e3 * t:.3f}" for n, t in times.items()))
+
+
+def test_c5_skip_renders_sampled_parity(oracle_lib, dev):
+    """The skip modes at full size: the 2M-leaf depth-9 scene, 16 cameras of
+    1080p at one time in one call, early termination at 1e-3, with coarse
+    skipping and with proposal skipping (an untrained network and one that
+    predicts every chord past the exit); sampled pixels against the oracle."""
+    import torch
+    sc = synth.c2_scene()
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    bits = torch.from_numpy(_lib.coarse_occupancy(sc.leaf_dijk, sc.max_depth).view(np.int32)).to(dev)
+    cams = sc.cameras[:16]
+    packed = {"untrained": _lib.mlp_pack(torch.from_numpy(_params(31)).to(dev)),
+              "overshoot": _lib.mlp_pack(torch.from_numpy(_forced(32, [20.0, 20.0, 20.0])).to(dev))}
+    note("c5 skip renders 16 x 1920x1080")
+    imgs = _skip_renders(tree, cams, bits, packed, sc.stop_T)
+    rng = np.random.default_rng(5)
+    m = 3000
+    ci = rng.integers(0, 16, m)
+    central = rng.random(m) < 0.8
+    px = np.where(central, rng.integers(int(0.35 * 1920), int(0.65 * 1920), m), rng.integers(0, 1920, m))
+    py = np.where(central, rng.integers(int(0.25 * 1080), int(0.75 * 1080), m), rng.integers(0, 1080, m))
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
+    p = oracle_lib.make_params(stop_T=sc.stop_T, band=1e-3)
+    o = np.zeros((m, 3)); d = np.zeros((m, 3))
+    for k in range(m):
+        ro, rd = oracle_lib.camera_rays(cams[ci[k]], np.array([px[k]]), np.array([py[k]]))
+        o[k], d[k] = ro[0], rd[0]
+    ref = conditioned_reference(oracle_lib, ot, sc.coeffs, p, [cams[0].time], o, d, np.zeros(m, np.int32))
+    assert (ref["n_seg"][:, 0] > 0).sum() > m // 3
+    for name in ("plain", "coarse", "untrained", "overshoot"):
+        check_parity(imgs[name][ci, py, px], ref, 1e-4)
