@@ -773,6 +773,9 @@ def main():
             "segments_per_ray": round(float(seg.mean()), 3),
             "opaque_segments_per_ray": round(float(opq.mean()), 3),
             "gather_GBps": round(gather_gbps, 1),
+            "gather_frac": round(gather_gbps / HBM_PEAK_GBPS, 4),
+            "traffic_frac": (None if traffic is None
+                             else round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)),
         },
         "cpu_baseline": {
             "value": round(m / cpu_s / 1e6, 5),
