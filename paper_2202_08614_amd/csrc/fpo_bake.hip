@@ -277,10 +277,11 @@ __global__ __launch_bounds__(kBlock, (DT != FPO_F32 && OUT_BF16) ? 3 : 2) void b
     }
 }
 
-// Few time points (a per-frame decode): one thread per leaf, the 28 dot
-// products of Eq. 7 / Eq. 9 in FP32 FMAs, one output record per time.  With
-// n_t < 4 there is no dense contraction for the matrix cores to exploit; the
-// kernel streams the records in and the snapshots out.
+// Few time points (a per-frame decode) from a quantised store: one thread per
+// leaf, the 28 dot products of Eq. 7 / Eq. 9 in FP32 FMAs, one output record
+// per time.  With n_t < 4 there is no dense contraction for the matrix cores
+// to exploit; the kernel streams the records in and the snapshots out (BF16
+// and FP8 records are small enough that per-thread reads stream well).
 template <int DT, int OUT_BF16>
 __global__ __launch_bounds__(kBlock) void eval_times_kernel(TreeDev tree, const float* basis, int32_t n_t,
                                                             int64_t n_leaves, void* out)
@@ -326,6 +327,101 @@ __global__ __launch_bounds__(kBlock) void eval_times_kernel(TreeDev tree, const 
 #pragma unroll
             for (int w = 0; w < 8; ++w) o[w] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
         }
+    }
+}
+
+// Few time points from the F32 store (the decode path's per-time IDFT pass):
+// the same dot products, with the 768-byte records read as whole lines.  A
+// wave takes 16 leaves: their records come in as whole lines into LDS rows,
+// lane (n, g) then forms output row group g of leaf n (g = 0: density, 31
+// terms; g = 1..3: nine SH rows of 5 terms), and the 16 output records leave
+// through LDS as whole lines.
+constexpr int kEvalOutPad = 33;           // LDS floats per staged output record (odd stride)
+
+template <int OUT_BF16>
+__global__ __launch_bounds__(kBlock) void eval_times_f32_kernel(TreeDev tree, const float* basis, int32_t n_t,
+                                                                int64_t n_leaves, void* out)
+{
+    constexpr int DT = FPO_F32;
+    constexpr int W = Pack<DT>::W;
+    constexpr int R = Pack<DT>::R;
+    constexpr int kWords = (FPO_N_COEFF + W - 1) / W;
+    constexpr int kPf = kBakeLeaves * R / kWave;              // record words per lane
+    constexpr int kOut = OUT_BF16 ? 4 : 8;                    // 16-byte words per output record
+    __shared__ float coef[kBakeWaves][kBakeLeaves][kCoefPad];
+    __shared__ float res[kBakeWaves][kBakeLeaves][kEvalOutPad];
+    const int wv = threadIdx.x / kWave;
+    const int ln = threadIdx.x % kWave;
+    const int64_t leaf0 = ((int64_t)blockIdx.x * kBakeWaves + wv) * kBakeLeaves;
+    if (leaf0 >= n_leaves) return;
+    const int n_valid = (int)min<int64_t>(kBakeLeaves, n_leaves - leaf0);
+    {
+        uint4 pf[kPf];
+        const uint4* src = tree.recs + leaf0 * R + ln;
+#pragma unroll
+        for (int p = 0; p < kPf; ++p) pf[p] = p * kWave + ln < n_valid * R ? src[p * kWave] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int p = 0; p < kPf; ++p) {
+            const int idx = p * kWave + ln;
+            const int li = idx / R;
+            const int g = idx - li * R;
+            if (g >= kWords) continue;
+            float v[W];
+            Pack<DT>::unpack(pf[p], v);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const int q = g * W + e;
+                if (q < kCoefPad) coef[wv][li][q] = q < FPO_N_COEFF ? v[e] : 0.0f;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int n = ln & 15;           // leaf of the wave's group
+    const int g = ln >> 4;           // output row group
+    const float* k = coef[wv][n];
+    float* rs = res[wv][n];
+    for (int t = 0; t < n_t; ++t) {
+        const float* b = basis + (int64_t)t * FPO_BASIS_STRIDE;
+        if (g == 0) {
+            float sg = 0.0f;
+#pragma unroll
+            for (int i = 0; i < FPO_N_SIGMA; ++i) sg = fmaf(k[i], b[i], sg);
+            rs[0] = sg;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int m = 9 * (g - 1) + q;
+                float z = 0.0f;
+#pragma unroll
+                for (int i = 0; i < FPO_N_SH_FOURIER; ++i) z = fmaf(k[FPO_N_SIGMA + FPO_N_SH_FOURIER * m + i], b[i], z);
+                rs[1 + m] = z;
+            }
+            if (g == 3) rs[28] = rs[29] = rs[30] = rs[31] = 0.0f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // 16 records x kOut words, lane L writing word L of each 64-word run
+#pragma unroll
+        for (int it = 0; it < kOut / 4; ++it) {
+            const int idx = it * kWave + ln;
+            const int li = idx / kOut;
+            const int w = idx % kOut;
+            if (li >= n_valid) continue;
+            const float* v = res[wv][li];
+            const int64_t rec = (int64_t)t * tree.stride + leaf0 + li;
+            if constexpr (OUT_BF16) {
+                static_cast<uint4*>(out)[rec * 4 + w] =
+                    make_uint4(pack_bf16x2(v[8 * w], v[8 * w + 1]), pack_bf16x2(v[8 * w + 2], v[8 * w + 3]),
+                               pack_bf16x2(v[8 * w + 4], v[8 * w + 5]), pack_bf16x2(v[8 * w + 6], v[8 * w + 7]));
+            } else {
+                static_cast<float4*>(out)[rec * 8 + w] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -432,12 +528,21 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
     const bool bf = out_dtype == FPO_BF16;
     if (n_t < kMfmaMinTimes) {
         const dev::TreeDev td = dev::tree_dev(tree);
+        if (tree->dtype == FPO_F32) {
+            const int64_t g16 = (tree->n_leaves + per_block - 1) / per_block;
+            if (bf)
+                hipLaunchKernelGGL((dev::eval_times_f32_kernel<1>), dim3((unsigned)g16), dim3(dev::kBlock), 0, s, td,
+                                   basis, n_t, tree->n_leaves, out);
+            else
+                hipLaunchKernelGGL((dev::eval_times_f32_kernel<0>), dim3((unsigned)g16), dim3(dev::kBlock), 0, s, td,
+                                   basis, n_t, tree->n_leaves, out);
+            return launch_status("fpo_bake_times");
+        }
         const int64_t g1 = (tree->n_leaves + dev::kBlock - 1) / dev::kBlock;
 #define FPO_EVAL(DT, BF)                                                                                   \
     hipLaunchKernelGGL((dev::eval_times_kernel<DT, BF>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td,  \
                        basis, n_t, tree->n_leaves, out)
         switch (tree->dtype) {
-            case FPO_F32: if (bf) FPO_EVAL(FPO_F32, 1); else FPO_EVAL(FPO_F32, 0); break;
             case FPO_BF16: if (bf) FPO_EVAL(FPO_BF16, 1); else FPO_EVAL(FPO_BF16, 0); break;
             default: if (bf) FPO_EVAL(FPO_FP8_E4M3, 1); else FPO_EVAL(FPO_FP8_E4M3, 0); break;
         }

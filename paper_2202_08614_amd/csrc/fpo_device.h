@@ -244,7 +244,6 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
                 const int S = 1 << (csh - 1);
                 // the child's octant is the half the ray is in on each axis
                 oct = mirror;
-#pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const bool up = ((float)(pos[a] + S) - xf[a]) * k[a] <= t_cur;
                     pos[a] += up ? S : 0;
