@@ -110,12 +110,15 @@ def test_c1_trace_lists(oracle_lib, c1, dev):
     assert exempt <= 0.01 * len(o32)
 
 
-# 3000 rays run one ray per wave; 40000 rays (above the small-batch size) one ray per lane
-@pytest.mark.parametrize("seed,depth,stop_T,n", [(11, 5, 0.0, 3000), (12, 7, 0.0, 3000), (13, 6, 1e-2, 3000),
-                                                 (14, 6, 0.0, 40000), (15, 7, 1e-2, 40000)])
-def test_random_trees_render_rays(oracle_lib, dev, seed, depth, stop_T, n):
+# 3000 rays run one ray per wave; 40000 rays (above the small-batch size) one ray per lane;
+# depth 10 is the deepest tree the library takes (leaves at every depth 1 .. 10)
+@pytest.mark.parametrize("seed,depth,stop_T,n,p_split", [(11, 5, 0.0, 3000, 0.6), (12, 7, 0.0, 3000, 0.6),
+                                                         (13, 6, 1e-2, 3000, 0.6), (14, 6, 0.0, 40000, 0.6),
+                                                         (15, 7, 1e-2, 40000, 0.6), (16, 10, 0.0, 3000, 0.25),
+                                                         (17, 10, 0.0, 40000, 0.25)])
+def test_random_trees_render_rays(oracle_lib, dev, seed, depth, stop_T, n, p_split):
     import torch
-    dijk = synth.random_tree_leaves(seed, depth, p_split=0.6)
+    dijk = synth.random_tree_leaves(seed, depth, p_split=p_split)
     coeffs = synth.gaussian_coeffs(len(dijk), seed=seed)
     tree = _lib.DeviceTree.from_leaves(dijk, coeffs, depth, device=dev, sigma_scale=16.0)
     o, d = synth.random_rays(n, seed + 1)
