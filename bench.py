@@ -154,9 +154,11 @@ def bake_leg(dev, sc, tree, oracle_mod, n_t: int = 64, reps: int = 5):
     return res
 
 
-def finetune_leg(dev, steps: int = 40, warmup: int = 5):
+def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
     """Fine-tune throughput on the 500k-leaf depth-8 scene: 8192-ray batches
-    drawn uniformly over 24 cameras x 30 times at 800x800, L2 loss, Adam."""
+    drawn uniformly over 24 cameras x 30 times at 800x800, L2 loss, Adam.
+    With the oracle, also the oracle's forward + backward of the first batch
+    (the fine-tune CPU baseline)."""
     import torch
     from paper_2202_08614_amd import synth
     from paper_2202_08614_amd.finetune import FineTuner
@@ -187,6 +189,21 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5):
         res["ms_per_step_with_adam" if with_adam else "ms_per_step_fwd_bwd"] = round(ms, 4)
     res["batch"] = 8192
     res["params"] = int(ft.tree.coeffs.numel())
+    if oracle_mod is not None:
+        # the oracle on the first batch: rays from the library's camera-ray call, dL/dC from its loss
+        img, py, px = batches[0]
+        ft.step(img, py, px, loss, with_adam=False)
+        torch.cuda.synchronize()
+        o = ft.o.double().cpu().numpy()
+        d = ft.d.double().cpu().numpy()
+        t_idx = ft.img_t[img.long()].cpu().numpy().astype(np.int32)
+        g_rgb = ft.grad_rgb.double().cpu().numpy()
+        times = sorted({float(c.time) for c in cams})
+        ot = oracle_mod.OracleTree(dijk, 8)
+        c0 = time.time()
+        oracle_mod.render_grad(ot, init, oracle_mod.make_params(stop_T=1e-3), times, o, d, t_idx, g_rgb)
+        res["oracle_fwd_bwd_rays_per_s"] = round(8192 / (time.time() - c0), 1)
+        res["oracle_cores"] = 1
     res["workload"] = ("depth-8 union octree, 500k leaves x 166 FP32 coeffs; 8192-ray batches over 24 cameras x "
                        "30 times at 800x800; L2 loss; dense Adam over all coefficient records")
     log(f"fine-tune: {res}")
@@ -726,7 +743,7 @@ def main():
     lay = None if args.no_layouts else layouts_leg(dev, sc, tree)
     fus = None if args.no_fusion else fusion_leg(dev, sc, tree)
     bake = None if args.no_bake else bake_leg(dev, sc, tree, oracle)
-    ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps)
+    ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps, oracle_mod=oracle)
     prop = None if args.no_proposal else proposal_leg(dev, sc, tree, oracle)
     del tree
     torch.cuda.empty_cache()
@@ -783,6 +800,9 @@ def main():
             "cores": cores,
             "kind": "oracle",
             "sample": f"{m} rays drawn uniformly from the step's 160 frames, FP64 C oracle",
+            "finetune_fwd_bwd_rays_per_s": None if ft is None else ft.get("oracle_fwd_bwd_rays_per_s"),
+            "finetune_cores": None if ft is None else ft.get("oracle_cores"),
+            "finetune_sample": "one 8192-ray batch of the fine-tune leg, forward + backward, FP64 C oracle",
         },
         "bake": bake,
         "per_frame_storage": per_frame,
