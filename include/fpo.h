@@ -222,7 +222,10 @@ fpo_status fpo_camera_rays(const float* cam_table, int32_t n_cams, const int32_t
                            const int32_t* py, const int32_t* px, int64_t n,
                            float* o_out, float* d_out, void* stream);
 
-/* Render arbitrary rays; ray r uses basis row t_idx[r].
+/* Render arbitrary rays; ray r uses basis row t_idx[r].  In Fourier mode
+ * from an F32 store, batches of at most 32768 rays run one ray per wave (the
+ * lanes share each leaf's coefficients), larger ones one ray per lane; the
+ * two agree to FP32 rounding.
  *   o, d   device [n_rays][3] F32 (d is normalised by the kernel; |d| > 0).
  *   t_idx  device [n_rays] int32 in [0, n_t).
  *   basis  device [n_t][FPO_BASIS_STRIDE] F32 (fpo_time_basis).
@@ -248,7 +251,7 @@ fpo_status fpo_trace_rays(const fpo_tree_view* tree, const float* o, const float
 /* Gradient of a loss L w.r.t. the leaf coefficients, through the render of
  * fpo_render_rays (Sec. 4.3: the IDFT is differentiable, so the photometric
  * loss of Eq. 13 back-propagates into the Fourier coefficients).  Each ray's
- * walk and shading are recomputed; nothing per sample is stored.
+ * walk and shading are recomputed by one wave; nothing per sample is stored.
  *   o, d, t_idx, basis, n_t, n_rays, opts: as passed to fpo_render_rays
  *            (opts->snapshot must be NULL; the store must be FPO_F32).
  *   rgb_fwd  device [n_rays][3], the forward colours of these rays.
@@ -298,7 +301,8 @@ fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stri
                         void* q_out, float* scale_out, void* stream);
 
 /* Evaluate Eq. 7 and Eq. 9 at n_t times for every leaf (a time bake), with
- * matrix-core (MFMA) contractions [times x K] x [K x leaves] in FP32.
+ * matrix-core (MFMA) contractions [times x K] x [K x leaves] in FP32 from 4
+ * times on, and FP32 FMAs per leaf below (a per-frame decode).
  *   basis   device [n_t][FPO_BASIS_STRIDE] F32 (fpo_time_basis).
  *   out     device [n_t][leaf_stride] snapshot records of out_dtype (F32 or
  *           BF16, RNE), multiplied by the leaf scale for quantised stores;
