@@ -178,3 +178,36 @@ def test_apply_matches_oracle(oracle_lib, dev):
     assert np.allclose(g[0].cpu().numpy()[:, :28], want_v, rtol=1e-5, atol=1e-6)
     assert np.allclose(g[1].cpu().numpy(), want_w, rtol=1e-5, atol=1e-7)
     assert not g[3].any()
+
+
+def test_bench_size_view_properties(dev):
+    """The bench's fusion view at full size (2M leaves, 800x800, the static
+    frame at t = 22.2), where the oracle cannot follow every ray: after one
+    view from W = C = 0, an observed leaf has C = 1 and W = its mean
+    transmittance in (tau, 1]; its sigma is a weighted mean of field
+    densities, so 0 <= sigma <= sum_g a_g; z_{c,j} is a weighted mean of
+    Y_j(d) c_c with 0 < c_c < 1, so |z_{c,j}| <= max |Y_j| (below 1.1 for
+    degree 2); leaves not observed keep their values bit for bit."""
+    import torch
+    sc = synth.c2_scene()
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    basis = torch.from_numpy(_lib.time_basis([22.2])).to(dev)
+    values = _lib.bake_times(tree, basis, _lib.FPO_F32)[0].clone()
+    before = values.clone()
+    field = synth.fusion_field(22.2)
+    fu = Fusion(tree, values, field, tau=TAU)
+    note("fusion one bench view, 2M leaves, 800x800")
+    fu.view(synth.fusion_cameras(100, 800, 800)[0])
+    torch.cuda.synchronize()
+    n = tree.n_leaves
+    c = fu.count[:n].cpu().numpy()
+    w = fu.weight[:n].cpu().numpy()
+    v = values[:n].cpu().numpy()
+    v0 = before[:n].cpu().numpy()
+    obs = c == 1
+    assert set(np.unique(c).tolist()) <= {0, 1} and obs.sum() > n // 4
+    assert np.all(w[obs] > TAU) and np.all(w[obs] <= 1.0 + 1e-6) and np.all(w[~obs] == 0.0)
+    assert np.all(v[obs, 0] >= 0.0) and np.all(v[obs, 0] <= field.a.sum() * (1 + 1e-5))
+    assert np.all(np.abs(v[obs, 1:28]) <= 1.1)
+    assert np.array_equal(v[~obs], v0[~obs])
+    assert not fu.acc.any()
