@@ -385,6 +385,29 @@ struct SnapEval {
         const uint4* P = static_cast<const uint4*>(S) + (int64_t)leaf * R;
 #pragma unroll
         for (int g = 1; g < R; ++g) Pack<SDT>::unpack(P[g], v + g * W);
+        dot(v, Y, h);
+    }
+    // The same reads through a buffer resource over the snapshot (records
+    // within 4 GiB): one 32-bit offset per lane instead of a 64-bit address,
+    // which keeps the camera render within 64 VGPRs (8 waves per SIMD).
+    __device__ static inline uint4 word(__amdgpu_buffer_rsrc_t rs, int leaf, int g)
+    {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, (uint32_t)leaf * (R * 16) + g * 16, 0, 0);
+        return make_uint4(x[0], x[1], x[2], x[3]);
+    }
+    __device__ static inline float sigma(__amdgpu_buffer_rsrc_t rs, int leaf, float* v)
+    {
+        Pack<SDT>::unpack(word(rs, leaf, 0), v);
+        return v[0];
+    }
+    __device__ static inline void colour(__amdgpu_buffer_rsrc_t rs, int leaf, const float* Y, float* v, float* h)
+    {
+#pragma unroll
+        for (int g = 1; g < R; ++g) Pack<SDT>::unpack(word(rs, leaf, g), v + g * W);
+        dot(v, Y, h);
+    }
+    __device__ static inline void dot(const float* v, const float* Y, float* h)
+    {
         h[0] = h[1] = h[2] = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -400,11 +423,12 @@ struct SnapEval {
 constexpr int kSnapF32 = 16 + FPO_F32;
 constexpr int kSnapBF16 = 16 + FPO_BF16;
 
-template <int MODE, int N1 = FPO_N_SIGMA, int N2 = FPO_N_SH_FOURIER>
+template <int MODE, int N1 = FPO_N_SIGMA, int N2 = FPO_N_SH_FOURIER, bool BUF = false>
 struct Shade {
     const TreeDev& T;
     const float* b;       // basis row (Fourier mode)
     const void* snap;     // snapshot records (snapshot mode)
+    __amdgpu_buffer_rsrc_t srs;   // BUF: the same records through a buffer resource
     float Y[9];
     float Tr;             // transmittance
     float C[3];
@@ -417,10 +441,12 @@ struct Shade {
         if constexpr (MODE >= 16) {
             constexpr int SDT = MODE - 16;
             float v[32];
-            sraw = SnapEval<SDT>::sigma(snap, leaf, v);
+            if constexpr (BUF) sraw = SnapEval<SDT>::sigma(srs, leaf, v);
+            else sraw = SnapEval<SDT>::sigma(snap, leaf, v);
             const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
             if (!(sig * delta > 0.0f)) return false;
-            SnapEval<SDT>::colour(snap, leaf, Y, v, h);
+            if constexpr (BUF) SnapEval<SDT>::colour(srs, leaf, Y, v, h);
+            else SnapEval<SDT>::colour(snap, leaf, Y, v, h);
         } else {
             using E = LeafEval<MODE, N1, N2>;
             float k[E::kSigmaWords * E::W];

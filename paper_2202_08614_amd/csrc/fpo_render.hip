@@ -37,6 +37,7 @@ struct CamLaunch {
     const float2* skip;              // skip modes: [n_cams][H][W] (t_start, t_end) from the cube entry
     const uint32_t* bits;            // coarse occupancy (suffix checks)
     int32_t W, H, bx_per_cam, blocks_per_cam, n_cams;
+    uint32_t snap_bytes;             // BUF kernels: bytes of one camera's snapshot records
     float bg[3];
     float stop_T;
 };
@@ -153,10 +154,12 @@ __global__ __launch_bounds__(kBlock) void skip_prepass_kernel(SkipLaunch a)
 }
 
 // SKIP: walk only the proven part [t_start, t_end] of each chord that the
-// skip pre-pass left in a.skip.
-template <int MODE, bool SKIP, int N1 = FPO_N_SIGMA, int N2 = FPO_N_SH_FOURIER>
-__global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
+// skip pre-pass left in a.skip.  BUF (snapshot modes, records within 4 GiB):
+// snapshot reads through a buffer resource, and at most 64 VGPRs.
+template <int MODE, bool SKIP, int N1 = FPO_N_SIGMA, int N2 = FPO_N_SH_FOURIER, bool BUF = false>
+__global__ __launch_bounds__(kBlock, BUF ? 8 : 1) void render_cam_kernel(CamLaunch a)
 {
+    static_assert(!BUF || MODE >= 16, "buffer reads serve snapshot records only");
     __shared__ int s_stack[kStackLevels * kBlock];
     const int lin = xcd_band(blockIdx.x, gridDim.x);
     if (lin >= a.n_cams * a.blocks_per_cam) return;
@@ -181,7 +184,9 @@ __global__ __launch_bounds__(kBlock) void render_cam_kernel(CamLaunch a)
     const float dy = cam.frame[4] + sx * cam.frame[7] + sy * cam.frame[10];
     const float dz = cam.frame[5] + sx * cam.frame[8] + sy * cam.frame[11];
 
-    Shade<MODE, N1, N2> sh{a.tree, b, cam.snap};
+    Shade<MODE, N1, N2, BUF> sh{a.tree, b, cam.snap};
+    if constexpr (BUF)
+        sh.srs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(cam.snap), (short)0, (int)a.snap_bytes, 0x00020000);
     sh.Tr = 1.0f;
     sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
     sh.stop_T = a.stop_T;
@@ -394,13 +399,15 @@ static int mode_of(const fpo_tree_view* t, const fpo_render_opts* o)
 
 using namespace fpo;
 
-template <int MODE>
+template <int MODE, bool BUF = false>
 static void launch_cam(const dev::CamLaunch& a, int grid, int skip, hipStream_t s)
 {
     if (skip != 0)
-        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, true>), dim3(grid), dim3(dev::kBlock), 0, s, a);
+        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, true, FPO_N_SIGMA, FPO_N_SH_FOURIER, BUF>), dim3(grid),
+                           dim3(dev::kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, false>), dim3(grid), dim3(dev::kBlock), 0, s, a);
+        hipLaunchKernelGGL((dev::render_cam_kernel<MODE, false, FPO_N_SIGMA, FPO_N_SH_FOURIER, BUF>), dim3(grid),
+                           dim3(dev::kBlock), 0, s, a);
 }
 
 extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
@@ -443,6 +450,9 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
     a.stop_T = opts->stop_T;
     const int mode = mode_of(tree, opts);
     const size_t snap_rec = opts->snapshot_dtype == FPO_F32 ? 128 : 64;   // bytes per leaf record
+    // snapshot records within 4 GiB per camera are read with 32-bit offsets
+    const bool snap_buf = opts->snapshot && (uint64_t)tree->n_leaves * snap_rec <= 0xFFFFFFFFull;
+    a.snap_bytes = snap_buf ? (uint32_t)((uint64_t)tree->n_leaves * snap_rec) : 0u;
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int c0 = 0; c0 < n_cams; c0 += dev::kCamsPerLaunch) {
         const int nc = std::min(dev::kCamsPerLaunch, n_cams - c0);
@@ -501,8 +511,14 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
             case FPO_F32: launch_cam<FPO_F32>(a, grid, skip, s); break;
             case FPO_BF16: launch_cam<FPO_BF16>(a, grid, skip, s); break;
             case FPO_FP8_E4M3: launch_cam<FPO_FP8_E4M3>(a, grid, skip, s); break;
-            case dev::kSnapF32: launch_cam<dev::kSnapF32>(a, grid, skip, s); break;
-            case dev::kSnapBF16: launch_cam<dev::kSnapBF16>(a, grid, skip, s); break;
+            case dev::kSnapF32:
+                if (snap_buf) launch_cam<dev::kSnapF32, true>(a, grid, skip, s);
+                else launch_cam<dev::kSnapF32>(a, grid, skip, s);
+                break;
+            case dev::kSnapBF16:
+                if (snap_buf) launch_cam<dev::kSnapBF16, true>(a, grid, skip, s);
+                else launch_cam<dev::kSnapBF16>(a, grid, skip, s);
+                break;
             default: return fail(FPO_E_INVALID, "unknown render mode");
         }
         if ((st = launch_status("fpo_render")) != FPO_OK) return st;

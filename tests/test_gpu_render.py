@@ -275,16 +275,20 @@ def test_c2_sampled_parity(oracle_lib, c2, dev):
 
 
 def test_c2_decode_sampled_parity(oracle_lib, c2, dev):
-    """The headline path at full size: the per-time IDFT pass (fpo_bake_times at
-    one time, F32 snapshot) and the snapshot render of the benchmark's 16
-    cameras, 1920x1080, early termination at 1e-3; sampled pixels against the
-    oracle on the Fourier coefficients."""
+    """The headline path at full size, as the benchmark runs it: one
+    fpo_bake_times of the step's 10 time points into F32 snapshots, then the
+    snapshot render of the 16 cameras of time point 3 (1920x1080, early
+    termination at 1e-3) from its snapshot; sampled pixels against the oracle
+    on the Fourier coefficients."""
     import torch
     sc, tree = c2
-    cams = sc.cameras[:16]
-    basis = torch.from_numpy(_lib.time_basis([cams[0].time])).to(dev)
-    note("c2 decode: fpo_bake_times F32 + snapshot fpo_render 16 x 1920x1080")
-    snap = _lib.bake_times(tree, basis, _lib.FPO_F32)
+    times = [sc.cameras[16 * j].time for j in range(10)]
+    cams = sc.cameras[48:64]
+    assert all(c.time == times[3] for c in cams)
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    note("c2 decode: fpo_bake_times F32 of 10 times + snapshot fpo_render 16 x 1920x1080")
+    snaps = _lib.bake_times(tree, basis, _lib.FPO_F32)
+    snap = snaps[3]
     opts = _lib.make_opts(stop_T=sc.stop_T, snapshot=snap, snapshot_dtype=_lib.FPO_F32, snapshot_cam_stride=0)
     rgb, _ = _lib.render(tree, cams, opts)
     torch.cuda.synchronize()
@@ -305,3 +309,82 @@ def test_c2_decode_sampled_parity(oracle_lib, c2, dev):
     got = rgb[ci, py, px]
     assert (ref["n_seg"][:, 0] > 0).sum() > m // 3
     check_parity(got, ref, TOL)
+
+
+def _slab_snapshot_values(c):
+    """Snapshot values of caller leaf indices c (int64 numpy or torch): exact
+    dyadic numbers from an integer hash, so both sides hold the same bits.
+    Column 0 is sigma before activation in [1/32, 3/32), columns 1..27 the SH
+    coefficients in [-1, 1), columns 28..31 zero."""
+    cols = []
+    for q in range(28):
+        h = ((c * 1103 + q * 7919 + 17) % 1048573) * 48271 % 2147483647
+        cols.append((64 + h % 128) / 2048.0 if q == 0 else (h % 1024 - 512) / 512.0)
+    return cols
+
+
+def test_snapshot_records_beyond_4gib(oracle_lib, dev):
+    """F32 snapshot records of more than 2^25 leaves (over 4 GiB of records):
+    the camera render must address them with 64-bit offsets.  The slab of all
+    depth-9 cells with k < 129 has 33,816,576 leaves; the camera looks down on
+    the corner x, y > 1/2, whose top layer holds the leaves stored past 4 GiB.
+    Sampled pixels against the oracle's segment lists composited in FP64."""
+    import torch
+    i, j, k = np.meshgrid(np.arange(512, dtype=np.int32), np.arange(512, dtype=np.int32),
+                          np.arange(129, dtype=np.int32), indexing="ij")
+    dijk = np.stack([np.full(i.size, 9, np.int32), i.ravel(), j.ravel(), k.ravel()], 1)
+    del i, j, k
+    n = len(dijk)
+    assert n * 128 > 2 ** 32
+    note("slab tree: 33.8M leaves, host build")
+    children, perm = _lib.build_tree(dijk, 9)
+    tree = _lib.DeviceTree(torch.from_numpy(children).to(dev), children.shape[0], 9, None, None, _lib.FPO_F32,
+                           n, n, perm, _lib.make_layout())
+    note("slab snapshot: 33.8M x 32 F32 records generated on the GPU")
+    snap = torch.zeros((n, 32), dtype=torch.float32, device=dev)
+    perm_d = torch.from_numpy(perm).to(dev)
+    step = 1 << 22
+    for s0 in range(0, n, step):
+        cols = _slab_snapshot_values(perm_d[s0:s0 + step])
+        snap[s0:s0 + step, :28] = torch.stack([x.to(torch.float32) for x in cols], 1)
+    del perm_d
+    cam = synth.Camera(eye=(0.7513, 0.7487, 1.2), fwd=(0.02, -0.015, -1.0), up=(0.0, 1.0, 0.0),
+                       fov_y_deg=40.0, width=128, height=128, time=0.0)
+    stop_T = 1e-3
+    opts = _lib.make_opts(stop_T=stop_T, snapshot=snap, snapshot_dtype=_lib.FPO_F32, snapshot_cam_stride=0)
+    note("slab fpo_render snapshot F32 128x128")
+    rgb, T = _lib.render(tree, [cam], opts, want_T=True)
+    torch.cuda.synchronize()
+    rgb = rgb[0].cpu().numpy()
+    T = T[0].cpu().numpy()
+    del snap
+    torch.cuda.empty_cache()
+
+    ot = oracle_lib.OracleTree(dijk, 9)
+    slot = np.empty(n, dtype=np.int64)
+    slot[perm] = np.arange(n)
+    rng = np.random.default_rng(4096)
+    m = 300
+    px = rng.integers(0, 128, m)
+    py = rng.integers(0, 128, m)
+    o, d = oracle_lib.camera_rays(cam, px, py)
+    sigma_scale = float(tree.layout.sigma_scale)
+    past = 0
+    for r in range(m):
+        dn = d[r] / np.linalg.norm(d[r])
+        leaf, t0, t1 = ot.trace(o[r], dn)
+        Y = oracle_lib.sh9(dn)
+        Tr, C = 1.0, np.zeros(3)
+        if len(leaf):
+            past += int(np.any(slot[leaf] >= 2 ** 25))
+            v = np.stack(_slab_snapshot_values(np.asarray(leaf, dtype=np.int64)), 1)
+            for q in range(len(leaf)):
+                e = math.exp(-sigma_scale * max(v[q, 0], 0.0) * (t1[q] - t0[q]))
+                h = v[q, 1:28].reshape(3, 9) @ Y
+                C += Tr * (1.0 - e) / (1.0 + np.exp(-h))
+                Tr *= e
+                if Tr < stop_T:
+                    break
+        assert np.max(np.abs(rgb[py[r], px[r]] - C)) <= TOL, (r, rgb[py[r], px[r]], C)
+        assert abs(T[py[r], px[r]] - Tr) <= TOL
+    assert past >= m // 3
