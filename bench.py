@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = "Mrays/s and 1080p frames/s vs FP64 oracle at stated PSNR; fine-tune rays/s"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_MFMA_PEAK_TFLOPS = 157.3     # dense MFMA with FP32 operands (the bake's v_mfma_f32_16x16x4f32)
 HBM_PEAK_GBPS = 8000.0
 
 # Algorithmic FP32 operations per composited segment:
@@ -111,7 +112,8 @@ def bake_leg(dev, sc, tree, oracle_mod, n_t: int = 64, reps: int = 5):
         flops = 2.0 * L * n_t * 166
         r = {"bake_ms": round(ms, 4), "bake_bytes": nbytes, "bake_GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
              "bake_hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-             "bake_mfma_frac": round(flops / (ms * 1e-3) / 2.5e15, 5)}
+             "bake_TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
+             "bake_mfma_frac": round(flops / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4)}
         if name == "bf16":
             opts = _lib.make_opts(stop_T=1e-3, snapshot=snaps, snapshot_dtype=_lib.FPO_BF16,
                                   snapshot_cam_stride=tree.leaf_stride)
@@ -206,6 +208,28 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
         oracle_mod.render_grad(ot, init, oracle_mod.make_params(stop_T=1e-3), times, o, d, t_idx, g_rgb)
         res["oracle_fwd_bwd_rays_per_s"] = round(8192 / (time.time() - c0), 1)
         res["oracle_cores"] = 1
+        # Algorithmic HBM bytes of one step (segment counts of this batch from the oracle): a
+        # segment with positive optical depth reads its 664-byte record in the forward and in
+        # the backward and adds 664 bytes of gradient; a transparent one reads its 31 density
+        # coefficients (124 B) twice.  Dense Adam: 32 B per parameter (p, g, m, v read; p, m, v
+        # written, g cleared) over the padded coefficient planes.
+        cnt = oracle_mod.render_rays(ot, init, oracle_mod.make_params(stop_T=1e-3), times, o, d, t_idx)
+        seg = cnt["n_seg"][:, 0].astype(np.float64)
+        opq = cnt["n_opaque"][:, 0].astype(np.float64)
+        fb_bytes = float((opq * 3 * 664 + (seg - opq) * 2 * 124).sum())
+        adam_bytes = 32.0 * res["params"]
+        adam_ms = res["ms_per_step_with_adam"] - res["ms_per_step_fwd_bwd"]
+        fb_gbps = fb_bytes / (res["ms_per_step_fwd_bwd"] * 1e-3) / 1e9
+        adam_gbps = adam_bytes / (adam_ms * 1e-3) / 1e9 if adam_ms > 0 else None
+        res["roofline"] = {
+            "bound": "hbm", "peak_GBps": HBM_PEAK_GBPS,
+            "segments_per_ray": round(float(seg.mean()), 3), "opaque_segments_per_ray": round(float(opq.mean()), 3),
+            "fwd_bwd_bytes_per_step": int(fb_bytes), "fwd_bwd_GBps": round(fb_gbps, 1),
+            "fwd_bwd_frac": round(fb_gbps / HBM_PEAK_GBPS, 4),
+            "adam_bytes_per_step": int(adam_bytes), "adam_ms": round(adam_ms, 4),
+            "adam_GBps": None if adam_gbps is None else round(adam_gbps, 1),
+            "adam_frac": None if adam_gbps is None else round(adam_gbps / HBM_PEAK_GBPS, 4),
+        }
     res["workload"] = ("depth-8 union octree, 500k leaves x 166 FP32 coeffs; 8192-ray batches over 24 cameras x "
                        "30 times at 800x800; L2 loss; dense Adam over all coefficient records")
     log(f"fine-tune: {res}")
@@ -576,6 +600,8 @@ def main():
     ap.add_argument("--no-fusion", action="store_true")
     ap.add_argument("--only-construct", action="store_true", help="run only the FPO-construction leg")
     ap.add_argument("--only-proposal", action="store_true", help="run only the learned-proposal leg")
+    ap.add_argument("--only-bake", action="store_true", help="run only the bake leg")
+    ap.add_argument("--only-finetune", action="store_true", help="run only the fine-tune leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprof byte counters)")
     args = ap.parse_args()
@@ -599,6 +625,11 @@ def main():
     if args.only_construct:
         print(json.dumps({"construct": construct_leg(dev)}), flush=True)
         return
+    if args.only_finetune:
+        import oracle
+        print(json.dumps({"finetune": finetune_leg(dev, steps=args.ft_steps,
+                                                   oracle_mod=None if args.no_cpu else oracle)}), flush=True)
+        return
     t0 = time.time()
     sc = synth.c2_scene()
     log(f"scene: {sc.n_leaves} leaves, generated in {time.time() - t0:.1f}s")
@@ -609,6 +640,11 @@ def main():
     if args.only_proposal:
         import oracle
         print(json.dumps({"proposal": proposal_leg(dev, sc, tree, oracle)}), flush=True)
+        return
+    if args.only_bake:
+        import oracle
+        print(json.dumps({"bake": bake_leg(dev, sc, tree, None if args.no_cpu else oracle)}, default=float),
+              flush=True)
         return
     cams = sc.cameras
     n_t = 10
