@@ -191,6 +191,23 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
         ms = e0.elapsed_time(e1) / steps
         res["rays_per_s_with_adam" if with_adam else "rays_per_s_fwd_bwd"] = round(8192 / (ms * 1e-3), 1)
         res["ms_per_step_with_adam" if with_adam else "ms_per_step_fwd_bwd"] = round(ms, 4)
+    # the same steps with the backward walking every ray again (no segment records)
+    ft_walk = FineTuner(ft.tree, ft.images, cams, stop_T=1e-3, lr=1e-2, batch=8192, seed=synth.RAY_SEED,
+                        record=False)
+    for b in batches[:warmup]:
+        ft_walk.step(*b, loss, with_adam=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for b in batches[warmup:]:
+        ft_walk.step(*b, loss, with_adam=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["rays_per_s_fwd_bwd_rewalk"] = round(8192 / (ms * 1e-3), 1)
+    res["ms_per_step_fwd_bwd_rewalk"] = round(ms, 4)
+    del ft_walk
+    res["segment_records"] = ft.record
     res["batch"] = 8192
     res["params"] = int(ft.tree.coeffs.numel())
     if oracle_mod is not None:
@@ -231,7 +248,8 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
             "adam_frac": None if adam_gbps is None else round(adam_gbps / HBM_PEAK_GBPS, 4),
         }
     res["workload"] = ("depth-8 union octree, 500k leaves x 166 FP32 coeffs; 8192-ray batches over 24 cameras x "
-                       "30 times at 800x800; L2 loss; dense Adam over all coefficient records")
+                       "30 times at 800x800; L2 loss; dense Adam over all coefficient records; the forward "
+                       "records each ray's segments and the backward takes them one wave per segment")
     log(f"fine-tune: {res}")
     del ft
     torch.cuda.empty_cache()

@@ -85,6 +85,8 @@ typedef enum { FPO_F32 = 0, FPO_BF16 = 1, FPO_FP8_E4M3 = 2 } fpo_dtype;
 #define FPO_PRUNE_SIGMA 1e-3f      /* Sec. 3: leaves below this density are dropped */
 #define FPO_RENDER_SKIP_COARSE 1   /* fpo_render_opts.flags */
 #define FPO_RENDER_SKIP_PROPOSAL 2
+#define FPO_RAYS_RECORD 4          /* fpo_render_rays / fpo_render_backward: segment records */
+#define FPO_RECORD_BYTES 32        /* one recorded segment in the workspace */
 
 /* Fourier / SH sizes, period and density scale.  Only (31, 5, 2) is compiled. */
 typedef struct {
@@ -143,13 +145,24 @@ typedef struct {
                                  (where a check fails, the walk starts at the first or
                                  ends at the last set cell instead).
                                  Either way the image equals the plain render up to FP32
-                                 rounding of the segment ends. */
+                                 rounding of the segment ends.
+                                 fpo_render_rays and fpo_render_backward only:
+                                 FPO_RAYS_RECORD: the forward (F32 Fourier mode, at most
+                                 32768 rays) writes each ray's segments of positive optical
+                                 depth into workspace; the backward of the same rays then
+                                 treats them independently instead of re-walking the rays. */
     const uint32_t* coarse_bits; /* device [FPO_COARSE_WORDS] from fpo_coarse_occupancy of
                                     this tree (skip modes) */
     const void* proposal;     /* device FPO_MLP_PACKED_BYTES from fpo_mlp_pack
                                  (FPO_RENDER_SKIP_PROPOSAL) */
-    void* workspace;          /* device scratch for skip modes, 8-byte aligned, at least
-                                 min(n_cams, 16) * W * H * 8 bytes */
+    void* workspace;          /* device scratch.  Skip modes: 8-byte aligned, at least
+                                 min(n_cams, 16) * W * H * 8 bytes.  FPO_RAYS_RECORD:
+                                 16-byte aligned; int32 [n_rays] counts (-1: the ray had more
+                                 segments than fit), then from the next 256-byte boundary
+                                 cap records of FPO_RECORD_BYTES per ray, ray-major, cap =
+                                 (workspace_bytes - that offset) / (32 n_rays) >= 1; a record
+                                 is {int32 leaf slot, delta, T before, colour before [3], 0, 0}.
+                                 Written by fpo_render_rays, read by fpo_render_backward. */
     int64_t workspace_bytes;
 } fpo_render_opts;
 
@@ -250,8 +263,12 @@ fpo_status fpo_trace_rays(const fpo_tree_view* tree, const float* o, const float
 
 /* Gradient of a loss L w.r.t. the leaf coefficients, through the render of
  * fpo_render_rays (Sec. 4.3: the IDFT is differentiable, so the photometric
- * loss of Eq. 13 back-propagates into the Fourier coefficients).  Each ray's
- * walk and shading are recomputed by one wave; nothing per sample is stored.
+ * loss of Eq. 13 back-propagates into the Fourier coefficients).  Without
+ * FPO_RAYS_RECORD each ray's walk and shading are recomputed by one wave.
+ * With it (opts->workspace as the forward left it, for the same rays, tree
+ * values and opts), 8 waves share each ray's recorded segments, one wave per
+ * segment, and only rays whose records overflowed are walked again; the
+ * gradient is the same up to the order of the atomic additions.
  *   o, d, t_idx, basis, n_t, n_rays, opts: as passed to fpo_render_rays
  *            (opts->snapshot must be NULL; the store must be FPO_F32).
  *   rgb_fwd  device [n_rays][3], the forward colours of these rays.

@@ -212,6 +212,20 @@ def skip_workspace(n_cams: int, height: int, width: int, device):
     return torch.empty((min(n_cams, 16) * height * width * 2,), dtype=torch.float32, device=device)
 
 
+def record_workspace(n_rays: int, cap: int, device):
+    """Workspace for FPO_RAYS_RECORD: int32 counts of n_rays, then cap records
+    of RECORD_BYTES per ray from the next 256-byte boundary."""
+    import torch
+    head = (4 * n_rays + 255) // 256 * 256
+    nbytes = head + n_rays * cap * RECORD_BYTES
+    return torch.empty((nbytes // 4,), dtype=torch.int32, device=device)
+
+
+def record_counts(workspace, n_rays: int):
+    """The per-ray record counts the forward left (-1: overflow)."""
+    return workspace[:n_rays]
+
+
 # ---------------------------------------------------------------------------
 # host calls
 # ---------------------------------------------------------------------------
@@ -428,6 +442,8 @@ def bake_times(tree: DeviceTree, basis, out_dtype: int = FPO_F32, out=None):
 MLP_N_IN = 7
 FPO_RENDER_SKIP_COARSE = 1
 FPO_RENDER_SKIP_PROPOSAL = 2
+FPO_RAYS_RECORD = 4
+RECORD_BYTES = 32
 MLP_N_PARAMS = 9795
 MLP_N_PARAMS_PADDED = 9796
 MLP_PACKED_BYTES = 23056

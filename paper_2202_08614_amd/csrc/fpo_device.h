@@ -534,8 +534,14 @@ struct WaveSlots {
 //     dL/dsigma_i = delta_i s sum_c g_c (T_{i+1} col_c - (Cf_c - C_c)),
 //     dL/dh_c     = g_c T_i alpha_i col_c (1 - col_c),
 // then dL/dk = dL/dsigma b_q (density) or dL/dh_c Y_j b_i (SH).
-template <bool GRAD>
+//
+// Segment records (REC, forward only): every segment with positive optical
+// depth is written as {leaf, delta, T_i, C_i[3]} (C_i the colour accumulated
+// before it), 32 bytes, so that the backward can treat the ray's segments
+// independently of each other.
+template <bool GRAD, bool REC = false>
 struct WaveShade {
+    static_assert(!(GRAD && REC), "segment records are written by the forward");
     const TreeDev& T;
     WaveSlots sl;
     int lane;
@@ -545,17 +551,22 @@ struct WaveShade {
     float Cf[3];          // GRAD only
     float g[3];           // GRAD only
     float* grad;          // GRAD only: F32 leaf records, 192 floats per slot
+    float4* rec;          // REC: this ray's segment records
+    int rec_cap;
+    int rec_n;
 
-    __device__ inline bool segment(int leaf, float t0, float t1)
+    // One segment entered with transmittance Tr_in after colour A (updated in
+    // place).  Returns false for a transparent segment (nothing to do);
+    // otherwise e = exp(-sigma delta).
+    __device__ inline bool shade(int leaf, float delta, float Tr_in, float* A, float& e)
     {
         constexpr int kRecFloats = 4 * Pack<FPO_F32>::R;
-        const float delta = t1 - t0;
-        const float* rec = reinterpret_cast<const float*>(T.recs) + (int64_t)leaf * kRecFloats + lane;
-        const float k0 = rec[0];
+        const float* rc = reinterpret_cast<const float*>(T.recs) + (int64_t)leaf * kRecFloats + lane;
+        const float k0 = rc[0];
         const float sraw = wave_sum(sl.c[0] == -1 ? sl.w[0] * k0 : 0.0f);
         const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
         if (!(sig * delta > 0.0f)) return false;   // transparent: contributes nothing
-        const float k[3] = {k0, rec[kWave], sl.c[2] >= 0 ? rec[2 * kWave] : 0.0f};
+        const float k[3] = {k0, rc[kWave], sl.c[2] >= 0 ? rc[2 * kWave] : 0.0f};
         float h[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < 3; ++s)
@@ -563,19 +574,26 @@ struct WaveShade {
             for (int ch = 0; ch < 3; ++ch) h[ch] = fmaf(sl.c[s] == ch ? sl.w[s] : 0.0f, k[s], h[ch]);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) h[ch] = wave_sum(h[ch]);
-        const float e = __expf(-sig * delta);
-        const float w = Tr * (1.0f - e);
+        e = __expf(-sig * delta);
+        const float w = Tr_in * (1.0f - e);
         if constexpr (!GRAD) {
+            if constexpr (REC) {
+                if (lane == 0 && rec_n < rec_cap) {
+                    rec[2 * rec_n] = make_float4(__int_as_float(leaf), delta, Tr_in, A[0]);
+                    rec[2 * rec_n + 1] = make_float4(A[1], A[2], 0.0f, 0.0f);
+                }
+                ++rec_n;
+            }
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) C[ch] = fmaf(w, sigmoidf_(h[ch]), C[ch]);
+            for (int ch = 0; ch < 3; ++ch) A[ch] = fmaf(w, sigmoidf_(h[ch]), A[ch]);
         } else {
-            const float T_next = Tr * e;
+            const float T_next = Tr_in * e;
             float dsig = 0.0f, dh[3];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 const float col = sigmoidf_(h[ch]);
-                C[ch] = fmaf(w, col, C[ch]);
-                dsig = fmaf(g[ch], T_next * col - (Cf[ch] - C[ch]), dsig);
+                A[ch] = fmaf(w, col, A[ch]);
+                dsig = fmaf(g[ch], T_next * col - (Cf[ch] - A[ch]), dsig);
                 dh[ch] = g[ch] * w * col * (1.0f - col);
             }
             dsig *= delta * T.sigma_scale;    // sigma_raw > 0 here
@@ -588,6 +606,13 @@ struct WaveShade {
                 unsafeAtomicAdd(gr + kWave * s, dv * sl.w[s]);
             }
         }
+        return true;
+    }
+
+    __device__ inline bool segment(int leaf, float t0, float t1)
+    {
+        float e;
+        if (!shade(leaf, t1 - t0, Tr, C, e)) return false;
         Tr *= e;
         return Tr < stop_T;
     }

@@ -61,13 +61,16 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_la
     return FPO_OK;
 }
 
-fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip)
+fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip, bool allow_record)
 {
     if (!opts) return fail(FPO_E_INVALID, "opts is NULL");
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(opts->bg[c])) return fail(FPO_E_INVALID, "opts->bg must be finite");
     if (!(opts->stop_T >= 0.0f && opts->stop_T < 1.0f)) return fail(FPO_E_INVALID, "opts->stop_T must be in [0, 1)");
-    if (opts->flags != 0) {
+    if (opts->flags == FPO_RAYS_RECORD) {
+        if (!allow_record) return fail(FPO_E_INVALID, "FPO_RAYS_RECORD is for fpo_render_rays and fpo_render_backward");
+        if (opts->snapshot) return fail(FPO_E_UNSUPPORTED, "FPO_RAYS_RECORD runs in Fourier mode only");
+    } else if (opts->flags != 0) {
         if (!allow_skip) return fail(FPO_E_INVALID, "opts->flags must be 0 for this call");
         if (opts->flags != FPO_RENDER_SKIP_COARSE && opts->flags != FPO_RENDER_SKIP_PROPOSAL)
             return fail(FPO_E_INVALID, "opts->flags must be 0, FPO_RENDER_SKIP_COARSE or FPO_RENDER_SKIP_PROPOSAL");
@@ -85,6 +88,20 @@ fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bo
         if (opts->snapshot_cam_stride < 0) return fail(FPO_E_INVALID, "snapshot_cam_stride < 0");
     }
     (void)tree;
+    return FPO_OK;
+}
+
+fpo_status record_layout(const fpo_render_opts* opts, int64_t n_rays, RecordLayout& out)
+{
+    if (!opts->workspace || (reinterpret_cast<uintptr_t>(opts->workspace) & 15) != 0)
+        return fail(FPO_E_INVALID, "FPO_RAYS_RECORD needs a 16-byte aligned opts->workspace");
+    const int64_t head = (4 * n_rays + 255) / 256 * 256;
+    const int64_t per_ray = (opts->workspace_bytes - head) / FPO_RECORD_BYTES / std::max<int64_t>(n_rays, 1);
+    if (opts->workspace_bytes < head || per_ray < 1)
+        return fail(FPO_E_INVALID, "opts->workspace_bytes below the counts and one record per ray");
+    out.count = static_cast<int32_t*>(opts->workspace);
+    out.records = static_cast<char*>(opts->workspace) + head;
+    out.cap = (int32_t)std::min<int64_t>(per_ray, 1 << 20);
     return FPO_OK;
 }
 

@@ -41,8 +41,20 @@ inline int record_words(fpo_dtype dt, int n1, int n2)
 // Validate a tree view (host-visible fields only).  allow_layouts: the call
 // handles every layout_supported() layout (else only the default one).
 fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_layouts = false);
-// allow_skip: the call accepts the skip flags (fpo_render only).
-fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip = false);
+// allow_skip: the call accepts the skip flags (fpo_render only); allow_record:
+// it accepts FPO_RAYS_RECORD (fpo_render_rays, fpo_render_backward).
+fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip = false,
+                      bool allow_record = false);
+
+// Segment records in opts->workspace (FPO_RAYS_RECORD): per-ray counts at the
+// start, records of FPO_RECORD_BYTES from the next 256-byte boundary, cap
+// records per ray (at least 1).
+struct RecordLayout {
+    int32_t* count;
+    void* records;
+    int32_t cap;
+};
+fpo_status record_layout(const fpo_render_opts* opts, int64_t n_rays, RecordLayout& out);
 
 // Camera frame in FP64, rounded to FP32: eye, unit forward, right * tan_x, up' * tan_y.
 fpo_status camera_frame(const fpo_camera& cam, float out[12]);

@@ -226,6 +226,9 @@ struct RaysLaunch {
     float* Tout;
     float bg[3];
     float stop_T;
+    int32_t* rec_count;     // segment records (one ray per wave only): per-ray count, -1 on overflow
+    float4* rec;            // [n][rec_cap] records of 32 bytes
+    int32_t rec_cap;
 };
 
 template <int MODE>
@@ -263,19 +266,25 @@ __global__ __launch_bounds__(kBlock) void render_rays_kernel(RaysLaunch a)
     if (a.Tout) a.Tout[r_id] = sh.Tr;
 }
 
-// F32 Fourier-mode render of a small ray batch, one ray per wave.
-__global__ __launch_bounds__(kBlock) void render_rays_wave_kernel(RaysLaunch a)
+// F32 Fourier-mode render of a small ray batch, one ray per wave.  REC: also
+// write each ray's segment records (FPO_RAYS_RECORD).
+template <bool REC>
+__global__ __launch_bounds__(kBlock, REC ? 8 : 1) void render_rays_wave_kernel(RaysLaunch a)
 {
     __shared__ int s_stack[kStackLevels * kBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t r_id = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (r_id >= a.n) return;
     const int ti = min(max(a.t_idx[r_id], 0), a.n_t - 1);
-    WaveShade<false> sh{a.tree};
+    WaveShade<false, REC> sh{a.tree};
     sh.lane = lane;
     sh.Tr = 1.0f;
     sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
     sh.stop_T = a.stop_T;
+    if constexpr (REC) {
+        sh.rec = a.rec + r_id * a.rec_cap * 2;
+        sh.rec_cap = a.rec_cap;
+    }
     Ray r;
     if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
                   a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
@@ -288,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void render_rays_wave_kernel(RaysLaunch a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.rgb[r_id * 3 + c] = fmaf(sh.Tr, a.bg[c], sh.C[c]);
         if (a.Tout) a.Tout[r_id] = sh.Tr;
+        if constexpr (REC) a.rec_count[r_id] = sh.rec_n <= a.rec_cap ? sh.rec_n : -1;
     }
 }
 
@@ -538,9 +548,16 @@ extern "C" fpo_status fpo_render_rays(const fpo_tree_view* tree, const float* o,
 {
     fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr);
     if (st != FPO_OK) return st;
-    if ((st = check_opts(opts, tree)) != FPO_OK) return st;
+    const bool record = opts && opts->flags == FPO_RAYS_RECORD;
+    if ((st = check_opts(opts, tree, false, true)) != FPO_OK) return st;
     if (n_rays < 0) return fail(FPO_E_INVALID, "n_rays < 0");
     if (n_rays == 0) return FPO_OK;
+    RecordLayout rl;
+    if (record) {
+        if (mode_of(tree, opts) != FPO_F32 || n_rays > dev::kWaveRayBatch)
+            return fail(FPO_E_UNSUPPORTED, "FPO_RAYS_RECORD needs F32 Fourier mode and at most 32768 rays");
+        if ((st = record_layout(opts, n_rays, rl)) != FPO_OK) return st;
+    }
     if (!o || !d || !t_idx || !basis || !rgb_out) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
     if (n_rays > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rays");
@@ -553,12 +570,20 @@ extern "C" fpo_status fpo_render_rays(const fpo_tree_view* tree, const float* o,
     a.rgb = rgb_out; a.Tout = T_out;
     for (int c = 0; c < 3; ++c) a.bg[c] = opts->bg[c];
     a.stop_T = opts->stop_T;
+    if (record) {
+        a.rec_count = rl.count;
+        a.rec = reinterpret_cast<float4*>(rl.records);
+        a.rec_cap = rl.cap;
+    }
     const int64_t grid = (n_rays + dev::kBlock - 1) / dev::kBlock;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int mode = mode_of(tree, opts);
     if (mode == FPO_F32 && n_rays <= dev::kWaveRayBatch) {
         const int64_t wgrid = (n_rays + dev::kBlock / dev::kWave - 1) / (dev::kBlock / dev::kWave);
-        hipLaunchKernelGGL(dev::render_rays_wave_kernel, dim3((unsigned)wgrid), dim3(dev::kBlock), 0, s, a);
+        if (record)
+            hipLaunchKernelGGL(dev::render_rays_wave_kernel<true>, dim3((unsigned)wgrid), dim3(dev::kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL(dev::render_rays_wave_kernel<false>, dim3((unsigned)wgrid), dim3(dev::kBlock), 0, s, a);
         return launch_status("fpo_render_rays");
     }
     switch (mode) {

@@ -2,8 +2,10 @@
 // render into the leaf Fourier coefficients, the L2 photometric loss of
 // Eq. 13 and a fused Adam update over the coefficient planes.
 //
-// Backward: per ray, the forward walk is recomputed (no per-sample state is
-// stored); the only forward state used is the ray's final colour.  Walking
+// Backward: per ray, the forward walk is recomputed, or, when the forward
+// recorded its segments (FPO_RAYS_RECORD), each recorded segment is taken on
+// its own; besides the records, the only forward state used is the ray's
+// final colour.  Walking
 // front to back with transmittance T_i and accumulated colour A_i, the
 // suffix R_i = C - A_i gives
 //     dL/dsigma_i = delta_i * sum_c g_c (T_{i+1} c_{i,c} - R_{i,c}),
@@ -39,7 +41,13 @@ struct BackwardLaunch {
     const float* grad_rgb;
     float* grad;
     float stop_T;
+    const int32_t* rec_count;   // segment records of the forward (FPO_RAYS_RECORD)
+    const float4* rec;
+    int32_t rec_cap;
 };
+
+// Waves per ray when the forward recorded its segments.
+constexpr int kRecGroups = 8;
 
 // The backward, one ray per wave.
 __global__ __launch_bounds__(kBlock) void render_backward_wave_kernel(BackwardLaunch a)
@@ -68,6 +76,58 @@ __global__ __launch_bounds__(kBlock) void render_backward_wave_kernel(BackwardLa
         sh9(r.d[0], r.d[1], r.d[2], Y);
         sh.sl.init(lane, a.basis + (int64_t)ti * FPO_BASIS_STRIDE, Y);
         walk(a.tree, r, s_stack + threadIdx.x, sh);
+    }
+}
+
+// The backward from segment records: wave (r, q) takes ray r's recorded
+// segments q, q + 8, ...; each already carries the transmittance and the
+// colour accumulated in front of it, so no walk is needed and the segments of
+// one ray run side by side.  A ray whose records overflowed is walked again by
+// its wave q = 0.
+__global__ __launch_bounds__(kBlock) void render_backward_rec_kernel(BackwardLaunch a)
+{
+    __shared__ int s_stack[kStackLevels * kBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w_id = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t r_id = w_id / kRecGroups;
+    const int q = (int)(w_id - r_id * kRecGroups);
+    if (r_id >= a.n) return;
+    int cnt = a.rec_count[r_id];
+    if (cnt > a.rec_cap) cnt = -1;       // not a count the forward writes: walk the ray instead
+    if (cnt < 0 ? q != 0 : q >= cnt) return;
+    WaveShade<true> sh{a.tree};
+    sh.lane = lane;
+    sh.Tr = 1.0f;
+    sh.stop_T = a.stop_T;
+    sh.grad = a.grad;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        sh.C[c] = 0.0f;
+        sh.Cf[c] = a.rgb_fwd[r_id * 3 + c];
+        sh.g[c] = a.grad_rgb[r_id * 3 + c];
+    }
+    if (sh.g[0] == 0.0f && sh.g[1] == 0.0f && sh.g[2] == 0.0f) return;
+    Ray r;
+    if (!setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+                   a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r))
+        return;
+    const int ti = min(max(a.t_idx[r_id], 0), a.n_t - 1);
+    float Y[FPO_N_SH];
+    sh9(r.d[0], r.d[1], r.d[2], Y);
+    sh.sl.init(lane, a.basis + (int64_t)ti * FPO_BASIS_STRIDE, Y);
+    if (cnt < 0) {
+        walk(a.tree, r, s_stack + threadIdx.x, sh);
+        return;
+    }
+    const float4* rr = a.rec + r_id * a.rec_cap * 2;
+    for (int i = q; i < cnt; i += kRecGroups) {
+        const float4 x0 = rr[2 * i];
+        const float4 x1 = rr[2 * i + 1];
+        const int leaf = __float_as_int(x0.x);
+        if (leaf < 0 || leaf >= a.tree.n_leaves) continue;   // only the forward's leaves are read
+        float A[3] = {x0.w, x1.x, x1.y};
+        float e;
+        sh.shade(leaf, x0.y, x0.z, A, e);
     }
 }
 
@@ -147,7 +207,7 @@ extern "C" fpo_status fpo_render_backward(const fpo_tree_view* tree, const float
 {
     fpo_status st = check_tree(tree, true);
     if (st != FPO_OK) return st;
-    if ((st = check_opts(opts, tree)) != FPO_OK) return st;
+    if ((st = check_opts(opts, tree, false, true)) != FPO_OK) return st;
     if (opts->snapshot) return fail(FPO_E_UNSUPPORTED, "backward runs in Fourier mode only");
     if (tree->dtype != FPO_F32) return fail(FPO_E_UNSUPPORTED, "backward needs the F32 coefficient store");
     if (n_rays < 0) return fail(FPO_E_INVALID, "n_rays < 0");
@@ -162,6 +222,20 @@ extern "C" fpo_status fpo_render_backward(const fpo_tree_view* tree, const float
     a.o = o; a.d = d; a.t_idx = t_idx; a.basis = basis; a.n = n_rays; a.n_t = n_t;
     a.rgb_fwd = rgb_fwd; a.grad_rgb = grad_rgb; a.grad = grad_coeffs;
     a.stop_T = opts->stop_T;
+    if (opts->flags == FPO_RAYS_RECORD) {
+        if (n_rays > dev::kWaveRayBatch)
+            return fail(FPO_E_UNSUPPORTED, "FPO_RAYS_RECORD needs at most 32768 rays");
+        RecordLayout rl;
+        if ((st = record_layout(opts, n_rays, rl)) != FPO_OK) return st;
+        a.rec_count = rl.count;
+        a.rec = static_cast<const float4*>(rl.records);
+        a.rec_cap = rl.cap;
+        const int64_t waves = n_rays * dev::kRecGroups;
+        const int64_t rgrid = (waves + dev::kBlock / dev::kWave - 1) / (dev::kBlock / dev::kWave);
+        hipLaunchKernelGGL(dev::render_backward_rec_kernel, dim3((unsigned)rgrid), dim3(dev::kBlock), 0,
+                           static_cast<hipStream_t>(stream), a);
+        return launch_status("fpo_render_backward");
+    }
     const int64_t wgrid = (n_rays + dev::kBlock / dev::kWave - 1) / (dev::kBlock / dev::kWave);
     hipLaunchKernelGGL(dev::render_backward_wave_kernel, dim3((unsigned)wgrid), dim3(dev::kBlock), 0,
                        static_cast<hipStream_t>(stream), a);

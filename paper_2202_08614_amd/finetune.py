@@ -4,7 +4,10 @@ One step: draw a batch of (image, row, column) samples, generate their rays
 (fpo_camera_rays), render them (fpo_render_rays), take the L2 photometric
 loss of Eq. 13 against the images (fpo_l2_loss), back-propagate into the
 leaf coefficients (fpo_render_backward) and apply Adam (fpo_adam_step).
-Each image carries its own camera and time.
+Each image carries its own camera and time.  With record=True the forward
+keeps each ray's segments (FPO_RAYS_RECORD, up to record_cap per ray) and the
+backward works through them segment by segment instead of walking the rays
+again.
 """
 from __future__ import annotations
 
@@ -18,7 +21,8 @@ from . import _lib
 
 class FineTuner:
     def __init__(self, tree: _lib.DeviceTree, images: torch.Tensor, cams: Sequence, stop_T: float = 1e-3,
-                 lr: float = 1e-2, batch: int = 8192, seed: int = 2022):
+                 lr: float = 1e-2, batch: int = 8192, seed: int = 2022, record: bool = True,
+                 record_cap: int = 128):
         dev = tree.children.device
         self.tree = tree
         self.images = images
@@ -27,8 +31,14 @@ class FineTuner:
         times = sorted({float(c.time) for c in cams})
         self.basis = torch.from_numpy(_lib.time_basis(times, tree.layout)).to(dev)
         self.img_t = torch.tensor([times.index(float(c.time)) for c in cams], dtype=torch.int32, device=dev)
-        self.opts = _lib.make_opts(stop_T=stop_T)
         self.batch = int(batch)
+        self.record = bool(record) and self.batch <= 32768
+        if self.record:
+            self.workspace = _lib.record_workspace(self.batch, record_cap, dev)
+            self.opts = _lib.make_opts(stop_T=stop_T, flags=_lib.FPO_RAYS_RECORD, workspace=self.workspace)
+        else:
+            self.workspace = None
+            self.opts = _lib.make_opts(stop_T=stop_T)
         self.gen = torch.Generator(device=dev)
         self.gen.manual_seed(seed)
         self.grad = torch.zeros_like(tree.coeffs)
@@ -45,13 +55,14 @@ class FineTuner:
     @classmethod
     def from_scene(cls, leaf_dijk: np.ndarray, gt_coeffs: np.ndarray, init_coeffs: np.ndarray, max_depth: int,
                    cams: Sequence, dev, sigma_scale: float = 64.0, stop_T: float = 1e-3, lr: float = 1e-2,
-                   batch: int = 8192, seed: int = 2022) -> "FineTuner":
+                   batch: int = 8192, seed: int = 2022, record: bool = True, record_cap: int = 128) -> "FineTuner":
         """Targets are rendered from the ground-truth coefficients by fpo_render."""
         gt = _lib.DeviceTree.from_leaves(leaf_dijk, gt_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
         images, _ = _lib.render(gt, cams, _lib.make_opts(stop_T=stop_T))
         del gt
         tree = _lib.DeviceTree.from_leaves(leaf_dijk, init_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
-        return cls(tree, images, cams, stop_T=stop_T, lr=lr, batch=batch, seed=seed)
+        return cls(tree, images, cams, stop_T=stop_T, lr=lr, batch=batch, seed=seed, record=record,
+                   record_cap=record_cap)
 
     def sample(self):
         dev = self.images.device

@@ -69,6 +69,56 @@ def test_backward_matches_oracle_gradient(oracle_lib, dev, stop_T, n_rays):
     assert not bad.any(), (bad.sum(), np.abs(got - want).max(), gmax)
 
 
+# cap 1: nearly every ray overflows and is walked again; 4: a mix; 1000: every ray recorded
+@pytest.mark.parametrize("cap", [1, 4, 1000])
+@pytest.mark.parametrize("stop_T", [0.0, 1e-2])
+def test_recorded_backward_matches_oracle_gradient(oracle_lib, dev, stop_T, cap):
+    """FPO_RAYS_RECORD: the forward writes each ray's segments of positive
+    optical depth; its colours equal the plain forward's bit for bit, its
+    counts equal the oracle's opaque-segment counts (-1 where they exceed cap),
+    and the backward from the records gives the plain backward's gradient (up
+    to the order of the atomic additions) and the oracle's."""
+    import torch
+    n_rays = 4096
+    dijk, coeffs, o, d, times, t_idx = _scene_and_rays(oracle_lib, n_rays, 3)
+    tree = _lib.DeviceTree.from_leaves(dijk, coeffs, 5, device=dev, sigma_scale=16.0)
+    rng = np.random.default_rng(7)
+    g_rgb = rng.standard_normal((n_rays, 3)).astype(np.float32)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    o_d, d_d, t_d, g_d = to(o), to(d), to(t_idx), to(g_rgb)
+    basis = to(_lib.time_basis(times))
+    ws = _lib.record_workspace(n_rays, cap, dev)
+    ws.fill_(-7)
+    plain = _lib.make_opts(stop_T=stop_T, bg=(0.2, 0.3, 0.4))
+    rec = _lib.make_opts(stop_T=stop_T, bg=(0.2, 0.3, 0.4), flags=_lib.FPO_RAYS_RECORD, workspace=ws)
+    note(f"recorded backward stop_T={stop_T} cap={cap}")
+    rgb0, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, plain)
+    rgb1, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, rec)
+    g0 = torch.zeros_like(tree.coeffs)
+    g1 = torch.zeros_like(tree.coeffs)
+    _lib.render_backward(tree, o_d, d_d, t_d, basis, rgb0, g_d, g0, plain)
+    _lib.render_backward(tree, o_d, d_d, t_d, basis, rgb1, g_d, g1, rec)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb0, rgb1)
+    cnt = _lib.record_counts(ws, n_rays).cpu().numpy()
+    ot = oracle_lib.OracleTree(dijk, 5)
+    p = oracle_lib.make_params(stop_T=stop_T, bg=(0.2, 0.3, 0.4), sigma_scale=16.0)
+    ref = oracle_lib.render_rays(ot, coeffs, p, times, o.astype(np.float64), d.astype(np.float64), t_idx)
+    n_opq = ref["n_opaque"][:, 0]
+    want_cnt = np.where(n_opq > cap, -1, n_opq)
+    assert (cnt >= -1).all() and (cnt <= cap).all()
+    assert (cnt == want_cnt).mean() >= 0.999, np.nonzero(cnt != want_cnt)[0][:10]
+    assert ((cnt == -1).sum() > 0) == (n_opq.max() > cap)
+    a = _unpack(g0.cpu().numpy(), tree.perm, len(dijk))
+    b = _unpack(g1.cpu().numpy(), tree.perm, len(dijk))
+    gmax = np.abs(a).max()
+    assert gmax > 0 and np.all(np.abs(a - b) <= 1e-5 * np.abs(a) + 1e-7 * gmax), np.abs(a - b).max()
+    want, _ = oracle_lib.render_grad(ot, coeffs, p, times, o.astype(np.float64), d.astype(np.float64),
+                                     t_idx, g_rgb.astype(np.float64))
+    bad = np.abs(b - want) > 1e-3 * np.abs(want) + 1e-5 * np.abs(want).max()
+    assert not bad.any(), (bad.sum(), np.abs(b - want).max())
+
+
 def test_backward_matches_gpu_central_differences(oracle_lib, dev):
     """dL/dk on 64 coefficients against central differences (h = 1e-3) of
     the GPU forward, L = sum_r w_r . rgb_r accumulated in FP64."""
@@ -194,21 +244,27 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev):
     g_rgb = np.random.default_rng(8).standard_normal((8192, 3)).astype(np.float32)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     basis = to(_lib.time_basis(times))
-    opts = _lib.make_opts(stop_T=1e-3)
-    note("c4 render_rays + render_backward 8192 rays, 500k leaves")
-    rgb, _ = _lib.render_rays(tree, to(o.astype(np.float32)), to(d.astype(np.float32)), to(t_idx), basis, opts)
-    grad = torch.zeros_like(tree.coeffs)
-    _lib.render_backward(tree, to(o.astype(np.float32)), to(d.astype(np.float32)), to(t_idx), basis, rgb,
-                         to(g_rgb), grad, opts)
-    torch.cuda.synchronize()
-    got = _unpack(grad.cpu().numpy(), tree.perm, sc.n_leaves)
+    ws = _lib.record_workspace(8192, 128, dev)
+    plain = _lib.make_opts(stop_T=1e-3)
+    rec = _lib.make_opts(stop_T=1e-3, flags=_lib.FPO_RAYS_RECORD, workspace=ws)
     ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
     p = oracle_lib.make_params(stop_T=1e-3)
     want, rgb_ref = oracle_lib.render_grad(ot, sc.coeffs, p, times, o, d, t_idx, g_rgb.astype(np.float64))
-    # colours within 1e-4; a ray at a cell-face tie (about 2 in 10^5 on this scene) may differ
-    err = np.abs(rgb.cpu().numpy() - rgb_ref).max(axis=1)
-    assert (err > 1e-4).sum() <= 2, np.sort(err)[-5:]
     gmax = np.abs(want).max()
     assert gmax > 0 and (np.abs(want) > 1e-3 * gmax).sum() > 10000
-    bad = np.abs(got - want) > 1e-3 * np.abs(want) + 1e-5 * gmax
-    assert bad.sum() <= 1e-5 * bad.size, (bad.sum(), np.abs(got - want).max(), gmax)
+    # the plain backward (rays walked again) and the one from segment records (as the fine-tune runs)
+    for name, opts in (("plain", plain), ("recorded", rec)):
+        note(f"c4 render_rays + render_backward ({name}) 8192 rays, 500k leaves")
+        rgb, _ = _lib.render_rays(tree, to(o.astype(np.float32)), to(d.astype(np.float32)), to(t_idx), basis,
+                                  opts)
+        grad = torch.zeros_like(tree.coeffs)
+        _lib.render_backward(tree, to(o.astype(np.float32)), to(d.astype(np.float32)), to(t_idx), basis, rgb,
+                             to(g_rgb), grad, opts)
+        torch.cuda.synchronize()
+        got = _unpack(grad.cpu().numpy(), tree.perm, sc.n_leaves)
+        # colours within 1e-4; a ray at a cell-face tie (about 2 in 10^5 on this scene) may differ
+        err = np.abs(rgb.cpu().numpy() - rgb_ref).max(axis=1)
+        assert (err > 1e-4).sum() <= 2, (name, np.sort(err)[-5:])
+        bad = np.abs(got - want) > 1e-3 * np.abs(want) + 1e-5 * gmax
+        assert bad.sum() <= 1e-5 * bad.size, (name, bad.sum(), np.abs(got - want).max(), gmax)
+    assert (_lib.record_counts(ws, 8192) >= 0).all()

@@ -340,3 +340,46 @@ def test_fusion_calls_validate_on_host():
     with pytest.raises(ValueError):
         _lib.field_struct(synth.Field(mu=np.zeros((9, 3)), w=np.ones(9), a=np.ones(9), u=np.zeros((3, 3)),
                                       v=np.zeros((3, 3)), b=np.zeros(3)))
+
+
+@host_only
+def test_segment_records_validate_on_host():
+    """FPO_RAYS_RECORD: fpo_render refuses it; fpo_render_rays and
+    fpo_render_backward refuse it beyond the one-ray-per-wave batch, with a
+    snapshot, and with a workspace that is misaligned or holds less than the
+    counts and one record per ray -- all before any launch."""
+    L = _lib.lib()
+    view = _lib.TreeView()
+    view.children = 16
+    view.n_nodes = 1
+    view.max_depth = 3
+    view.coeffs = 16
+    view.dtype = _lib.FPO_F32
+    view.n_leaves = 1
+    view.leaf_stride = 1
+    view.layout = _lib.make_layout()
+    p = ctypes.c_void_p(16)
+    opts = _lib.make_opts(flags=_lib.FPO_RAYS_RECORD)
+    opts.workspace = 1 << 20
+    opts.workspace_bytes = 256 + 10 * _lib.RECORD_BYTES
+    cam = _lib.camera_struct([synth.ring_camera(0, 0, 1.5, 30, 4, 4, 0)])
+    assert L.fpo_render(ctypes.byref(view), cam, 1, ctypes.byref(opts), p, None, None) == _lib.FPO_E_INVALID
+    assert b"FPO_RAYS_RECORD" in L.fpo_last_error()
+
+    def rays(n):
+        return L.fpo_render_rays(ctypes.byref(view), p, p, p, p, 1, n, ctypes.byref(opts), p, None, None)
+
+    def back(n):
+        return L.fpo_render_backward(ctypes.byref(view), p, p, p, p, 1, n, ctypes.byref(opts), p, p, p, None)
+
+    assert rays(40000) == _lib.FPO_E_UNSUPPORTED and back(40000) == _lib.FPO_E_UNSUPPORTED
+    opts.workspace_bytes = 256 + 10 * _lib.RECORD_BYTES - 1
+    assert rays(10) == _lib.FPO_E_INVALID and b"workspace_bytes" in L.fpo_last_error()
+    assert back(10) == _lib.FPO_E_INVALID and b"workspace_bytes" in L.fpo_last_error()
+    opts.workspace_bytes = 256 + 10 * _lib.RECORD_BYTES
+    opts.workspace = (1 << 20) + 8
+    assert rays(10) == _lib.FPO_E_INVALID and b"aligned" in L.fpo_last_error()
+    assert back(10) == _lib.FPO_E_INVALID and b"aligned" in L.fpo_last_error()
+    opts.workspace = 1 << 20
+    opts.snapshot = 1 << 21
+    assert rays(10) == _lib.FPO_E_UNSUPPORTED and back(10) == _lib.FPO_E_UNSUPPORTED
