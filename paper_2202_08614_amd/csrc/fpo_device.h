@@ -484,14 +484,28 @@ struct Shade {
 // beat one ray per lane at every batch size.
 constexpr int64_t kWaveRayBatch = 32768;
 
-// Butterfly sum over the wave.  Every lane combines the same pairs (a + b and
-// b + a are equal in IEEE arithmetic), so all lanes hold the same bits and
-// branches on the result stay uniform.
+// Sum over the wave.  Within each row of 16 lanes, four DPP steps add lane
+// pairs, quads, half rows and rows (every lane adds the same two partial sums,
+// a + b and b + a being equal in IEEE arithmetic, so the row's lanes agree);
+// the four row sums are then read into scalar registers and added in one
+// fixed order.  All lanes hold the same bits, branches on the result stay
+// uniform, and no step goes through LDS.
+template <int CTRL>
+__device__ inline float dpp_add(float v)
+{
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
 __device__ inline float wave_sum(float v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v = dpp_add<0xb1>(v);     // quad_perm [1, 0, 3, 2]: pairs
+    v = dpp_add<0x4e>(v);     // quad_perm [2, 3, 0, 1]: quads
+    v = dpp_add<0x141>(v);    // row_half_mirror: half rows
+    v = dpp_add<0x140>(v);    // row_mirror: rows
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 // This lane's coefficient slots for one ray: q = lane + 64 s, s < 3.  A
@@ -562,11 +576,12 @@ struct WaveShade {
     {
         constexpr int kRecFloats = 4 * Pack<FPO_F32>::R;
         const float* rc = reinterpret_cast<const float*>(T.recs) + (int64_t)leaf * kRecFloats + lane;
-        const float k0 = rc[0];
-        const float sraw = wave_sum(sl.c[0] == -1 ? sl.w[0] * k0 : 0.0f);
+        // all three loads go out before the density sum decides whether the
+        // colour is needed: one memory round trip per segment instead of two
+        const float k[3] = {rc[0], rc[kWave], sl.c[2] >= 0 ? rc[2 * kWave] : 0.0f};
+        const float sraw = wave_sum(sl.c[0] == -1 ? sl.w[0] * k[0] : 0.0f);
         const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
         if (!(sig * delta > 0.0f)) return false;   // transparent: contributes nothing
-        const float k[3] = {k0, rc[kWave], sl.c[2] >= 0 ? rc[2 * kWave] : 0.0f};
         float h[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < 3; ++s)
