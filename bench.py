@@ -152,6 +152,15 @@ def bake_leg(dev, sc, tree, oracle_mod, n_t: int = 64, reps: int = 5):
         res[name] = r
         del snaps, qt
         torch.cuda.empty_cache()
+    if oracle_mod is not None:
+        # CPU baseline of the bake: the oracle's FP64 evaluation of 1% of the leaves at the 64
+        # times on one host thread, extrapolated to every leaf
+        n_s = max(L // 100, 1)
+        c0 = time.time()
+        oracle_mod.bake(sc.coeffs[:n_s], oracle_mod.make_params(), times)
+        cpu_s = time.time() - c0
+        res["oracle_bake_s_extrapolated"] = round(cpu_s * L / n_s, 2)
+        res["oracle_bake_sample"] = f"{n_s} leaves x {n_t} times, 1 thread, x {L / n_s:.0f}"
     res["workload"] = ("2.0M-leaf depth-9 scene quantised per leaf; 64 times baked into BF16 snapshots "
                        "[64][28][L] by MFMA; 64 views 800x800, view k from snapshot k, T<1e-3")
     log(f"bake: {res}")
@@ -893,6 +902,8 @@ def main():
             "finetune_fwd_bwd_rays_per_s": None if ft is None else ft.get("oracle_fwd_bwd_rays_per_s"),
             "finetune_cores": None if ft is None else ft.get("oracle_cores"),
             "finetune_sample": "one 8192-ray batch of the fine-tune leg, forward + backward, FP64 C oracle",
+            "bake_64_times_s": None if bake is None else bake.get("oracle_bake_s_extrapolated"),
+            "bake_sample": None if bake is None else bake.get("oracle_bake_sample"),
         },
         "bake": bake,
         "per_frame_storage": per_frame,
