@@ -225,14 +225,20 @@ def test_finetune_converges(dev):
     assert np.mean(last) < 0.5 * np.mean(first), (first, last)
 
 
-def test_c4_batch_gradient_matches_oracle(oracle_lib, dev):
+@pytest.fixture(scope="module")
+def c4(dev):
+    sc = synth.c4_scene()
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    return sc, tree
+
+
+def test_c4_batch_gradient_matches_oracle(oracle_lib, dev, c4):
     """The fine-tune step at full size: the 500k-leaf depth-8 scene, one
     8192-ray batch drawn over its 24 cameras x 30 times at 800x800 (the
     benchmark's batch); forward colours and the gradient of every coefficient
     against the FP64 oracle."""
     import torch
-    sc = synth.c4_scene()
-    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    sc, tree = c4
     cams = sc.cameras
     times = sorted({c.time for c in cams})
     ci, py, px = synth.sample_pixels(8192, len(cams), 800, 800)
@@ -268,3 +274,56 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev):
         bad = np.abs(got - want) > 1e-3 * np.abs(want) + 1e-5 * gmax
         assert bad.sum() <= 1e-5 * bad.size, (name, bad.sum(), np.abs(got - want).max(), gmax)
     assert (_lib.record_counts(ws, 8192) >= 0).all()
+
+
+def test_c4_backward_matches_central_differences(oracle_lib, dev, c4):
+    """The check the fine-tune configuration names, at its size: on the 500k-leaf
+    scene and one 8192-ray batch, dL/dk from the recorded forward and the
+    backward from segment records (as the fine-tuner runs them) on 64
+    coefficients against central differences (h = 1e-3) of the GPU forward,
+    L = sum_r w_r . rgb_r accumulated in FP64.  Without early termination:
+    a perturbation that moves a ray's transmittance across the threshold
+    changes its colour by a step, which no derivative describes."""
+    import torch
+    sc, tree = c4
+    cams = sc.cameras
+    times = sorted({c.time for c in cams})
+    ci, py, px = synth.sample_pixels(8192, len(cams), 800, 800)
+    o = np.zeros((8192, 3)); d = np.zeros((8192, 3))
+    for c in np.unique(ci):
+        sel = np.nonzero(ci == c)[0]
+        o[sel], d[sel] = oracle_lib.camera_rays(cams[c], px[sel], py[sel])
+    t_idx = np.array([times.index(cams[c].time) for c in ci], np.int32)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    o_d, d_d, t_d = to(o.astype(np.float32)), to(d.astype(np.float32)), to(t_idx)
+    basis = to(_lib.time_basis(times))
+    w = np.random.default_rng(11).standard_normal((8192, 3))
+    ws = _lib.record_workspace(8192, 128, dev)
+    opts = _lib.make_opts(stop_T=0.0, flags=_lib.FPO_RAYS_RECORD, workspace=ws)
+    plain = _lib.make_opts(stop_T=0.0)
+    note("c4 recorded backward vs GPU central differences, 64 coefficients")
+    rgb, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, opts)
+    grad = torch.zeros_like(tree.coeffs)
+    _lib.render_backward(tree, o_d, d_d, t_d, basis, rgb, to(w.astype(np.float32)), grad, opts)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().reshape(-1)
+    flat_abs = np.abs(g)
+    cand = np.nonzero(flat_abs > 0.05 * flat_abs.max())[0]
+    assert len(cand) >= 64
+    pick = np.random.default_rng(12).choice(cand, 64, replace=False)
+    h = 1e-3
+    flat_coeffs = tree.coeffs.view(-1)
+
+    def loss():
+        r, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, plain)
+        return float((r.double().cpu().numpy() * w).sum())
+
+    for idx in pick:
+        k0 = float(flat_coeffs[idx])
+        flat_coeffs[idx] = k0 + h
+        lp = loss()
+        flat_coeffs[idx] = k0 - h
+        lm = loss()
+        flat_coeffs[idx] = k0
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[idx]) <= 2e-2 * abs(g[idx]) + 2e-3 * flat_abs.max(), (int(idx), fd, float(g[idx]))
