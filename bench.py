@@ -69,9 +69,7 @@ def render_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel_key: str):
-    """HBM bytes per launch of `kernel_key` from the committed counter
-    summary, or None if there is none for the current sources."""
+def _counter_record(kernel_key: str):
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -79,8 +77,25 @@ def measured_traffic(kernel_key: str):
         return None
     if t.get("source_sha256") != render_source_hash():
         return None
-    k = t.get("kernels", {}).get(kernel_key)
+    return t.get("kernels", {}).get(kernel_key)
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch of `kernel_key` from the committed counter
+    summary, or None if there is none for the current sources."""
+    k = _counter_record(kernel_key)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def measured_valu_insts(kernel_key: str):
+    """Wave-level VALU instructions per launch (SQ_INSTS_VALU) of `kernel_key`
+    from the same committed counter summary, or None."""
+    k = _counter_record(kernel_key)
+    return None if k is None else k.get("valu_insts_per_launch")
+
+
+# A wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz.
+SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9
 
 
 def bake_leg(dev, sc, tree, oracle_mod, n_t: int = 64, reps: int = 5):
@@ -812,6 +827,7 @@ def main():
         kernel = "render_cam_kernel<snapshot F32> (after a per-leaf IDFT pass)"
         kernel_key = "render_cam_kernel<16, false, 31, 5, true>"
     traffic = measured_traffic(kernel_key)
+    valu = measured_valu_insts(kernel_key)
     flop_launch = flop_ray * rays_launch
     achieved_tflops = flop_launch / (launch_ms * 1e-3) / 1e12
     gather_gbps = gather_ray * rays_launch / (launch_ms * 1e-3) / 1e9
@@ -890,6 +906,9 @@ def main():
             "gather_GBps": round(gather_gbps, 1),
             "gather_frac": round(gather_gbps / HBM_PEAK_GBPS, 4),
             "hbm_measured_GBps": hbm,
+            "valu_insts_per_launch": valu,
+            "valu_issue_frac": (None if valu is None
+                                else round(valu * 4 / (SIMD_CYCLES_PER_S * launch_ms * 1e-3), 4)),
             "traffic_frac": (None if traffic is None
                              else round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)),
         },
