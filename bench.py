@@ -824,7 +824,7 @@ def main():
     else:
         flop_ray = FLOP_PER_RAY + FLOP_SNAP_SIGMA * (seg - opq).mean() + FLOP_SNAP_OPAQUE * opq.mean()
         gather_ray = 16 * (seg - opq).mean() + 128 * opq.mean()
-        kernel = "render_cam_kernel<snapshot F32> (after a per-leaf IDFT pass)"
+        kernel = "render_cam_kernel<snapshot F32> (after the bake of the step's 10 time points)"
         kernel_key = "render_cam_kernel<16, false, 31, 5, true>"
     traffic = measured_traffic(kernel_key)
     valu = measured_valu_insts(kernel_key)
