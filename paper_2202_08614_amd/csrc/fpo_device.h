@@ -184,6 +184,9 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 //   - step to the neighbouring slot of the same size across that face (the
 //     other coordinates are unchanged) and pop to the deepest node that still
 //     contains it, found from the highest bit the step changed.
+// The step and the load of the next slot's child-table entry come before the
+// current leaf is shaded (they do not depend on it), so that load and the
+// leaf's own loads are in flight together.
 // Each step moves the exit axis forward by a whole slot and never moves any
 // axis back, so the walk ends within 3G steps.  Rays parallel to an axis use a
 // tiny direction instead of zero: their crossing times on that axis exceed
@@ -229,27 +232,32 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
 #pragma unroll
         for (int a = 0; a < 3; ++a) pos[a] = ((float)S - xf[a]) * k[a] <= t_cur ? S : 0;
     }
+    // entry of the current slot (a child of node), requested one step ahead
+    int ch_next;
+    {
+        const int csh = D - 1 - lvl;
+        const int oct = (((pos[0] >> csh) & 1) | (((pos[1] >> csh) & 1) << 1) | (((pos[2] >> csh) & 1) << 2)) ^ mirror;
+        ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
+    }
     const int max_steps = 3 * G + 4;
     for (int it = 0; it < max_steps; ++it) {
-        int ch;
+        int ch = ch_next;
         int csh = D - 1 - lvl;
-        // octant of the current slot in its parent (mirrored back to the table's frame)
-        int oct = (((pos[0] >> csh) & 1) | (((pos[1] >> csh) & 1) << 1) | (((pos[2] >> csh) & 1) << 2)) ^ mirror;
         for (;;) {
-            ch = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
             if (ch > 0 && ch < T.n_nodes && lvl < D - 1) {
                 ++lvl;
                 node = ch;
                 stk[lvl * kBlock] = node;
                 const int S = 1 << (csh - 1);
                 // the child's octant is the half the ray is in on each axis
-                oct = mirror;
+                int oct = mirror;
                 for (int a = 0; a < 3; ++a) {
                     const bool up = ((float)(pos[a] + S) - xf[a]) * k[a] <= t_cur;
                     pos[a] += up ? S : 0;
                     oct ^= up ? (1 << a) : 0;
                 }
                 csh -= 1;
+                ch = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
                 continue;
             }
             if (ch > 0) ch = 0;   // malformed table: treat as empty
@@ -264,25 +272,32 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
         if (te[1] < t_exit) { t_exit = te[1]; ax = 1; }
         if (te[2] < t_exit) { t_exit = te[2]; ax = 2; }
         t_exit = fmaxf(t_exit, t_cur);
+        // step to the next slot and request its entry before shading this one
+        const int old = ax == 0 ? pos[0] : ax == 1 ? pos[1] : pos[2];
+        const int nw = old + size;
+        const bool more = nw < G;
+        if (more) {
+            const int h = 31 - __builtin_clz((unsigned)(old ^ nw));
+            const int keep = D - 1 - h;     // deepest stack level whose node contains the new slot
+            pos[0] = ax == 0 ? nw : pos[0];
+            pos[1] = ax == 1 ? nw : pos[1];
+            pos[2] = ax == 2 ? nw : pos[2];
+            if (keep < lvl) {
+                lvl = keep;
+                node = stk[lvl * kBlock];
+                const int m = ~((1 << h) - 1);
+                pos[0] &= m; pos[1] &= m; pos[2] &= m;
+            }
+            const int cs = D - 1 - lvl;
+            const int oct = (((pos[0] >> cs) & 1) | (((pos[1] >> cs) & 1) << 1) | (((pos[2] >> cs) & 1) << 2)) ^ mirror;
+            ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
+        }
         if (ch < 0) {
             const int leaf = -ch - 1;
             if (leaf < T.n_leaves && vis.segment(leaf, t_cur, t_exit)) return;
         }
         if (t_exit >= t_end && !stop.more(t_exit, t_end)) return;
-        const int old = ax == 0 ? pos[0] : ax == 1 ? pos[1] : pos[2];
-        const int nw = old + size;
-        if (nw >= G) return;
-        const int h = 31 - __builtin_clz((unsigned)(old ^ nw));
-        const int keep = D - 1 - h;     // deepest stack level whose node contains the new slot
-        pos[0] = ax == 0 ? nw : pos[0];
-        pos[1] = ax == 1 ? nw : pos[1];
-        pos[2] = ax == 2 ? nw : pos[2];
-        if (keep < lvl) {
-            lvl = keep;
-            node = stk[lvl * kBlock];
-            const int m = ~((1 << h) - 1);
-            pos[0] &= m; pos[1] &= m; pos[2] &= m;
-        }
+        if (!more) return;
         t_cur = t_exit;
     }
 }
