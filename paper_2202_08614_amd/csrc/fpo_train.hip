@@ -13,9 +13,10 @@
 // and through Eq. 7 / Eq. 9 and the SH basis of Eq. 1
 //     dL/dk^sigma_q     = s [sigma_raw > 0] dL/dsigma_i b_q,
 //     dL/dk^z_{c,j,i}   = dL/dh_{i,c} Y_j b_i.
-// One wave per ray: each lane owns up to three of a leaf's 166 coefficients,
-// so every sample's gradients go out as three coalesced FP32 atomic adds into
-// records laid out like the F32 coefficient store.
+// One wave per ray (or, from records, per segment): each lane owns up to three
+// of a leaf's 166 coefficients, so every sample's gradients go out as three
+// coalesced FP32 atomic adds into records laid out like the F32 coefficient
+// store.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
