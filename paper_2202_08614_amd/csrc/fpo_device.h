@@ -196,6 +196,11 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 // Distances are measured from the entry point r.o.  With a stop distance
 // t_end the walk consults stop.more() once a step ends at or past t_end.
 // --------------------------------------------------------------------------
+// Visitors that load a leaf's data may start the loads as soon as the walk
+// knows the leaf, before it works out the step to the next slot.
+template <class Visitor>
+__device__ inline void prefetch_leaf(Visitor&, int) {}
+
 struct NoStop {
     __device__ inline bool more(float, float&) { return false; }
 };
@@ -272,6 +277,7 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
         if (te[1] < t_exit) { t_exit = te[1]; ax = 1; }
         if (te[2] < t_exit) { t_exit = te[2]; ax = 2; }
         t_exit = fmaxf(t_exit, t_cur);
+        if (ch < 0 && -ch - 1 < T.n_leaves) prefetch_leaf(vis, -ch - 1);
         // step to the next slot and request its entry before shading this one
         const int old = ax == 0 ? pos[0] : ax == 1 ? pos[1] : pos[2];
         const int nw = old + size;
@@ -583,17 +589,27 @@ struct WaveShade {
     float4* rec;          // REC: this ray's segment records
     int rec_cap;
     int rec_n;
+    float pk[3];          // this lane's coefficients of the leaf being shaded
 
-    // One segment entered with transmittance Tr_in after colour A (updated in
-    // place).  Returns false for a transparent segment (nothing to do);
-    // otherwise e = exp(-sigma delta).
-    __device__ inline bool shade(int leaf, float delta, float Tr_in, float* A, float& e)
+    // Load this lane's three coefficients of a leaf (all three before the
+    // density sum decides whether the colour is needed: one memory round trip
+    // per segment instead of two).
+    __device__ inline void prefetch(int leaf)
     {
         constexpr int kRecFloats = 4 * Pack<FPO_F32>::R;
         const float* rc = reinterpret_cast<const float*>(T.recs) + (int64_t)leaf * kRecFloats + lane;
-        // all three loads go out before the density sum decides whether the
-        // colour is needed: one memory round trip per segment instead of two
-        const float k[3] = {rc[0], rc[kWave], sl.c[2] >= 0 ? rc[2 * kWave] : 0.0f};
+        pk[0] = rc[0];
+        pk[1] = rc[kWave];
+        pk[2] = sl.c[2] >= 0 ? rc[2 * kWave] : 0.0f;
+    }
+
+    // One segment entered with transmittance Tr_in after colour A (updated in
+    // place), its coefficients loaded by prefetch(leaf).  Returns false for a
+    // transparent segment (nothing to do); otherwise e = exp(-sigma delta).
+    __device__ inline bool shade(int leaf, float delta, float Tr_in, float* A, float& e)
+    {
+        constexpr int kRecFloats = 4 * Pack<FPO_F32>::R;
+        const float k[3] = {pk[0], pk[1], pk[2]};
         const float sraw = wave_sum(sl.c[0] == -1 ? sl.w[0] * k[0] : 0.0f);
         const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
         if (!(sig * delta > 0.0f)) return false;   // transparent: contributes nothing
@@ -647,6 +663,12 @@ struct WaveShade {
         return Tr < stop_T;
     }
 };
+
+template <bool GRAD, bool REC>
+__device__ inline void prefetch_leaf(WaveShade<GRAD, REC>& v, int leaf)
+{
+    v.prefetch(leaf);
+}
 
 }  // namespace dev
 }  // namespace fpo

@@ -128,6 +128,7 @@ __global__ __launch_bounds__(kBlock) void render_backward_rec_kernel(BackwardLau
         if (leaf < 0 || leaf >= a.tree.n_leaves) continue;   // only the forward's leaves are read
         float A[3] = {x0.w, x1.x, x1.y};
         float e;
+        sh.prefetch(leaf);
         sh.shade(leaf, x0.y, x0.z, A, e);
     }
 }
