@@ -327,3 +327,39 @@ def test_c4_backward_matches_central_differences(oracle_lib, dev, c4):
         flat_coeffs[idx] = k0
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[idx]) <= 2e-2 * abs(g[idx]) + 2e-3 * flat_abs.max(), (int(idx), fd, float(g[idx]))
+
+
+@pytest.mark.parametrize("n_rays", [1, 32768])
+def test_recorded_path_at_its_limits(oracle_lib, dev, n_rays):
+    """FPO_RAYS_RECORD at one ray and at the largest batch it accepts (32768,
+    the last one-ray-per-wave batch): the recording forward's colours equal the
+    plain forward's, and the gradient from the records equals the re-walk's up
+    to the order of the atomic additions."""
+    import torch
+    dijk, coeffs, o, d, times, t_idx = _scene_and_rays(oracle_lib, max(n_rays, 2), 17)
+    o, d, t_idx = o[:n_rays], d[:n_rays], t_idx[:n_rays]
+    tree = _lib.DeviceTree.from_leaves(dijk, coeffs, 5, device=dev, sigma_scale=16.0)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    o_d, d_d, t_d = to(o), to(d), to(t_idx)
+    if n_rays == 1:     # a ray through the shell, so that the single ray has segments
+        o_d = to(np.array([[0.5, 0.5, -0.5]], np.float32))
+        d_d = to(np.array([[0.013, 0.021, 1.0]], np.float32))
+    g_d = to(np.random.default_rng(5).standard_normal((n_rays, 3)).astype(np.float32))
+    basis = to(_lib.time_basis(times))
+    ws = _lib.record_workspace(n_rays, 64, dev)
+    plain = _lib.make_opts(stop_T=1e-3)
+    rec = _lib.make_opts(stop_T=1e-3, flags=_lib.FPO_RAYS_RECORD, workspace=ws)
+    note(f"recorded path n_rays={n_rays}")
+    rgb0, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, plain)
+    rgb1, _ = _lib.render_rays(tree, o_d, d_d, t_d, basis, rec)
+    g0 = torch.zeros_like(tree.coeffs)
+    g1 = torch.zeros_like(tree.coeffs)
+    _lib.render_backward(tree, o_d, d_d, t_d, basis, rgb0, g_d, g0, plain)
+    _lib.render_backward(tree, o_d, d_d, t_d, basis, rgb1, g_d, g1, rec)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb0, rgb1)
+    cnt = _lib.record_counts(ws, n_rays).cpu().numpy()
+    assert (cnt >= -1).all() and (cnt > 0).any()
+    a, b = g0.cpu().numpy(), g1.cpu().numpy()
+    gmax = np.abs(a).max()
+    assert gmax > 0 and np.all(np.abs(a - b) <= 1e-5 * np.abs(a) + 1e-7 * gmax)
