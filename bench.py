@@ -204,12 +204,12 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
     res = {}
     for with_adam in (True, False):
         for b in batches[:warmup]:
-            ft.step(*b, loss, with_adam=with_adam)
+            ft.step(*b[:3], loss, with_adam=with_adam, t_idx=b[3])
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for b in batches[warmup:]:
-            ft.step(*b, loss, with_adam=with_adam)
+            ft.step(*b[:3], loss, with_adam=with_adam, t_idx=b[3])
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
@@ -219,12 +219,12 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
     ft_walk = FineTuner(ft.tree, ft.images, cams, stop_T=1e-3, lr=1e-2, batch=8192, seed=synth.RAY_SEED,
                         record=False)
     for b in batches[:warmup]:
-        ft_walk.step(*b, loss, with_adam=False)
+        ft_walk.step(*b[:3], loss, with_adam=False, t_idx=b[3])
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for b in batches[warmup:]:
-        ft_walk.step(*b, loss, with_adam=False)
+        ft_walk.step(*b[:3], loss, with_adam=False, t_idx=b[3])
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -236,7 +236,7 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
     res["params"] = int(ft.tree.coeffs.numel())
     if oracle_mod is not None:
         # the oracle on the first batch: rays from the library's camera-ray call, dL/dC from its loss
-        img, py, px = batches[0]
+        img, py, px, _ = batches[0]
         ft.step(img, py, px, loss, with_adam=False)
         torch.cuda.synchronize()
         o = ft.o.double().cpu().numpy()

@@ -65,15 +65,17 @@ class FineTuner:
                    record_cap=record_cap)
 
     def sample(self):
+        """A batch: image, row and column of each ray, and the time index of its image."""
         dev = self.images.device
         n = self.batch
         img = torch.randint(0, self.n_img, (n,), generator=self.gen, device=dev, dtype=torch.int32)
         py = torch.randint(0, self.H, (n,), generator=self.gen, device=dev, dtype=torch.int32)
         px = torch.randint(0, self.W, (n,), generator=self.gen, device=dev, dtype=torch.int32)
-        return img, py, px
+        return img, py, px, self.img_t[img.long()]
 
-    def step(self, img, py, px, loss_out: torch.Tensor, with_adam: bool = True):
-        t_idx = self.img_t[img.long()]
+    def step(self, img, py, px, loss_out: torch.Tensor, with_adam: bool = True, t_idx=None):
+        if t_idx is None:
+            t_idx = self.img_t[img.long()]
         _lib.camera_rays(self.cam_table, img, py, px, self.o, self.d)
         _lib.render_rays(self.tree, self.o, self.d, t_idx, self.basis, self.opts, rgb=self.rgb)
         _lib.l2_loss(self.rgb, self.images, img, py, px, grad_rgb=self.grad_rgb, loss=loss_out)
@@ -86,6 +88,6 @@ class FineTuner:
     def train(self, n_steps: int) -> List[float]:
         losses = torch.zeros(n_steps, dtype=torch.float32, device=self.images.device)
         for s in range(n_steps):
-            img, py, px = self.sample()
-            self.step(img, py, px, losses[s:s + 1])
+            img, py, px, t_idx = self.sample()
+            self.step(img, py, px, losses[s:s + 1], t_idx=t_idx)
         return losses.cpu().tolist()
