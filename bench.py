@@ -215,6 +215,22 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
         ms = e0.elapsed_time(e1) / steps
         res["rays_per_s_with_adam" if with_adam else "rays_per_s_fwd_bwd"] = round(8192 / (ms * 1e-3), 1)
         res["ms_per_step_with_adam" if with_adam else "ms_per_step_fwd_bwd"] = round(ms, 4)
+    # the same steps captured once in a HIP graph and replayed (batch copied in before each replay)
+    ft_graph = FineTuner(ft.tree, ft.images, cams, stop_T=1e-3, lr=1e-2, batch=8192, seed=synth.RAY_SEED,
+                         graph=True)
+    for b in batches[:warmup]:
+        ft_graph.step(*b[:3], loss, t_idx=b[3])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for b in batches[warmup:]:
+        ft_graph.step(*b[:3], loss, t_idx=b[3])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["rays_per_s_with_adam_graph"] = round(8192 / (ms * 1e-3), 1)
+    res["ms_per_step_with_adam_graph"] = round(ms, 4)
+    del ft_graph
     # the same steps with the backward walking every ray again (no segment records)
     ft_walk = FineTuner(ft.tree, ft.images, cams, stop_T=1e-3, lr=1e-2, batch=8192, seed=synth.RAY_SEED,
                         record=False)

@@ -301,6 +301,14 @@ fpo_status fpo_l2_loss(const float* rgb, const float* images, int32_t n_images, 
 fpo_status fpo_adam_step(float* params, float* grad, float* m, float* v, int64_t n, float lr,
                          float beta1, float beta2, float eps, int32_t step, void* stream);
 
+/* The same step with its count in device memory, for callers that capture the
+ * fine-tuning step in a HIP graph: state is device int32[4], 16-byte aligned,
+ * {step, c1, c2, unused} (c1, c2 as FP32 bits), zeroed by the caller before
+ * the first step.  Each call (or replay of a captured call) adds one to the
+ * step and applies the update of fpo_adam_step with that step. */
+fpo_status fpo_adam_step_dev(float* params, float* grad, float* m, float* v, int64_t n, float lr,
+                             float beta1, float beta2, float eps, int32_t* state, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Precision and time bake                                                  */
 /* ---------------------------------------------------------------------- */

@@ -101,6 +101,8 @@ _SIGS = {
     "fpo_l2_loss": [_P, _P, _I32, _I32, _I32, _P, _P, _P, _I64, _P, _P, _P],
     "fpo_adam_step": [_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, _I32, _P],
+    "fpo_adam_step_dev": [_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                          ctypes.c_float, _P, _P],
     "fpo_quantize": [_P, _I64, _I64, ctypes.c_int, _P, _P, _P],
     "fpo_bake_times": [ctypes.POINTER(TreeView), _P, _I32, ctypes.c_int, _P, _P],
     "fpo_coarse_occupancy": [_P, _I64, _I32, _P],
@@ -409,6 +411,14 @@ def adam_step(params, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.
               eps: float = 1e-8):
     _check(lib().fpo_adam_step(_t_ptr(params), _t_ptr(grad), _t_ptr(m), _t_ptr(v), int(params.numel()),
                                float(lr), float(beta1), float(beta2), float(eps), int(step), _stream()))
+
+
+def adam_step_dev(params, grad, m, v, state, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8):
+    """fpo_adam_step_dev: the step count in `state` (device int32[4], zeroed
+    before the first step) advances by one per call or graph replay."""
+    _check(lib().fpo_adam_step_dev(_t_ptr(params), _t_ptr(grad), _t_ptr(m), _t_ptr(v), int(params.numel()),
+                                   float(lr), float(beta1), float(beta2), float(eps), _t_ptr(state), _stream()))
 
 
 def quantize(tree: DeviceTree, dtype: int) -> DeviceTree:

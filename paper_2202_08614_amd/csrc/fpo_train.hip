@@ -172,11 +172,17 @@ __global__ __launch_bounds__(kBlock) void l2_loss_kernel(const float* rgb, const
 
 // Adam (Kingma and Ba 2015) over n floats; the gradient is cleared after use.
 // c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
+// cs: null, or device {c1, c2} written by adam_count_kernel (then c1, c2 are unused).
 __global__ __launch_bounds__(kBlock) void adam_kernel(float4* p, float4* g, float4* m, float4* v, int64_t n4,
-                                                      float lr, float b1, float b2, float eps, float c1, float c2)
+                                                      float lr, float b1, float b2, float eps, float c1, float c2,
+                                                      const float* cs)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n4) return;
+    if (cs) {
+        c1 = cs[0];
+        c2 = cs[1];
+    }
     float4 pp = p[i], gg = g[i], mm = m[i], vv = v[i];
     float* P = &pp.x;
     float* G = &gg.x;
@@ -194,6 +200,20 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(float4* p, float4* g, floa
     m[i] = mm;
     v[i] = vv;
     g[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Step count kept on the device: state = {int32 step, float c1, float c2, 0}.
+// One thread advances the step and writes the bias corrections for it, so a
+// captured graph that replays this launch and adam_kernel advances by one
+// step per replay.
+__global__ void adam_count_kernel(int32_t* state, float b1, float b2)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int32_t t = state[0] + 1;
+    state[0] = t;
+    float* cs = reinterpret_cast<float*>(state + 1);
+    cs[0] = (float)(1.0 / (1.0 - pow((double)b1, (double)t)));
+    cs[1] = (float)(1.0 / (1.0 - pow((double)b2, (double)t)));
 }
 
 }  // namespace dev
@@ -280,6 +300,31 @@ extern "C" fpo_status fpo_adam_step(float* params, float* grad, float* m, float*
     const int64_t grid = (n4 + dev::kBlock - 1) / dev::kBlock;
     hipLaunchKernelGGL(dev::adam_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0, static_cast<hipStream_t>(stream),
                        reinterpret_cast<float4*>(params), reinterpret_cast<float4*>(grad), reinterpret_cast<float4*>(m),
-                       reinterpret_cast<float4*>(v), n4, lr, beta1, beta2, eps, (float)c1, (float)c2);
+                       reinterpret_cast<float4*>(v), n4, lr, beta1, beta2, eps, (float)c1, (float)c2,
+                       static_cast<const float*>(nullptr));
     return launch_status("fpo_adam_step");
+}
+
+extern "C" fpo_status fpo_adam_step_dev(float* params, float* grad, float* m, float* v, int64_t n, float lr,
+                                        float beta1, float beta2, float eps, int32_t* state, void* stream)
+{
+    if (!params || !grad || !m || !v || !state) return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n < 0 || n % 4 != 0) return fail(FPO_E_INVALID, "n must be a non-negative multiple of 4");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(FPO_E_INVALID, "betas must be in [0, 1)");
+    if (!(lr >= 0.0f) || !(eps > 0.0f)) return fail(FPO_E_INVALID, "lr must be >= 0 and eps > 0");
+    if ((((uintptr_t)params) | ((uintptr_t)grad) | ((uintptr_t)m) | ((uintptr_t)v) | ((uintptr_t)state)) & 15)
+        return fail(FPO_E_INVALID, "buffers must be 16-byte aligned");
+    const int64_t n4 = n / 4;
+    if (n4 > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many parameters");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(dev::adam_count_kernel, dim3(1), dim3(dev::kWave), 0, s, state, beta1, beta2);
+    if (n4 > 0) {
+        const int64_t grid = (n4 + dev::kBlock - 1) / dev::kBlock;
+        hipLaunchKernelGGL(dev::adam_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0, s,
+                           reinterpret_cast<float4*>(params), reinterpret_cast<float4*>(grad),
+                           reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n4, lr, beta1, beta2, eps,
+                           0.0f, 0.0f, reinterpret_cast<const float*>(state + 1));
+    }
+    return launch_status("fpo_adam_step_dev");
 }

@@ -7,7 +7,8 @@ leaf coefficients (fpo_render_backward) and apply Adam (fpo_adam_step).
 Each image carries its own camera and time.  With record=True the forward
 keeps each ray's segments (FPO_RAYS_RECORD, up to record_cap per ray) and the
 backward works through them segment by segment instead of walking the rays
-again.
+again.  With graph=True the step (rays, render, loss, backward, Adam with its
+step count on the device) is captured once in a HIP graph and replayed.
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ from . import _lib
 class FineTuner:
     def __init__(self, tree: _lib.DeviceTree, images: torch.Tensor, cams: Sequence, stop_T: float = 1e-3,
                  lr: float = 1e-2, batch: int = 8192, seed: int = 2022, record: bool = True,
-                 record_cap: int = 128):
+                 record_cap: int = 128, graph: bool = False):
         dev = tree.children.device
         self.tree = tree
         self.images = images
@@ -51,18 +52,27 @@ class FineTuner:
         self.d = torch.empty((n, 3), dtype=torch.float32, device=dev)
         self.rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
         self.grad_rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        # graph=True: the whole step with Adam is captured once in a HIP graph and replayed;
+        # a batch is copied into static buffers first, and Adam's step count lives on the device
+        self.graph = bool(graph)
+        self._graph = None
+        if self.graph:
+            self.adam_state = torch.zeros(4, dtype=torch.int32, device=dev)
+            self.g_in = [torch.zeros(n, dtype=torch.int32, device=dev) for _ in range(4)]   # img, py, px, t_idx
+            self.g_loss = torch.zeros(1, dtype=torch.float32, device=dev)
 
     @classmethod
     def from_scene(cls, leaf_dijk: np.ndarray, gt_coeffs: np.ndarray, init_coeffs: np.ndarray, max_depth: int,
                    cams: Sequence, dev, sigma_scale: float = 64.0, stop_T: float = 1e-3, lr: float = 1e-2,
-                   batch: int = 8192, seed: int = 2022, record: bool = True, record_cap: int = 128) -> "FineTuner":
+                   batch: int = 8192, seed: int = 2022, record: bool = True, record_cap: int = 128,
+                   graph: bool = False) -> "FineTuner":
         """Targets are rendered from the ground-truth coefficients by fpo_render."""
         gt = _lib.DeviceTree.from_leaves(leaf_dijk, gt_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
         images, _ = _lib.render(gt, cams, _lib.make_opts(stop_T=stop_T))
         del gt
         tree = _lib.DeviceTree.from_leaves(leaf_dijk, init_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
         return cls(tree, images, cams, stop_T=stop_T, lr=lr, batch=batch, seed=seed, record=record,
-                   record_cap=record_cap)
+                   record_cap=record_cap, graph=graph)
 
     def sample(self):
         """A batch: image, row and column of each ray, and the time index of its image."""
@@ -73,14 +83,31 @@ class FineTuner:
         px = torch.randint(0, self.W, (n,), generator=self.gen, device=dev, dtype=torch.int32)
         return img, py, px, self.img_t[img.long()]
 
-    def step(self, img, py, px, loss_out: torch.Tensor, with_adam: bool = True, t_idx=None):
-        if t_idx is None:
-            t_idx = self.img_t[img.long()]
+    def _forward_backward(self, img, py, px, t_idx, loss_out):
         _lib.camera_rays(self.cam_table, img, py, px, self.o, self.d)
         _lib.render_rays(self.tree, self.o, self.d, t_idx, self.basis, self.opts, rgb=self.rgb)
         _lib.l2_loss(self.rgb, self.images, img, py, px, grad_rgb=self.grad_rgb, loss=loss_out)
         _lib.render_backward(self.tree, self.o, self.d, t_idx, self.basis, self.rgb, self.grad_rgb, self.grad,
                              self.opts)
+
+    def step(self, img, py, px, loss_out: torch.Tensor, with_adam: bool = True, t_idx=None):
+        if t_idx is None:
+            t_idx = self.img_t[img.long()]
+        if self.graph and with_adam:
+            for dst, src in zip(self.g_in, (img, py, px, t_idx)):
+                dst.copy_(src)
+            self.g_loss.zero_()
+            if self._graph is None:
+                torch.cuda.synchronize()
+                self._graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(self._graph):
+                    self._forward_backward(*self.g_in, self.g_loss)
+                    _lib.adam_step_dev(self.tree.coeffs, self.grad, self.m, self.v, self.adam_state, lr=self.lr)
+            self._graph.replay()
+            loss_out.add_(self.g_loss)
+            self.t += 1
+            return
+        self._forward_backward(img, py, px, t_idx, loss_out)
         if with_adam:
             self.t += 1
             _lib.adam_step(self.tree.coeffs, self.grad, self.m, self.v, self.t, lr=self.lr)

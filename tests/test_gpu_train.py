@@ -363,3 +363,45 @@ def test_recorded_path_at_its_limits(oracle_lib, dev, n_rays):
     a, b = g0.cpu().numpy(), g1.cpu().numpy()
     gmax = np.abs(a).max()
     assert gmax > 0 and np.all(np.abs(a - b) <= 1e-5 * np.abs(a) + 1e-7 * gmax)
+
+
+def test_finetune_graph_replays_match_eager_steps(dev):
+    """The fine-tune step captured once in a HIP graph and replayed against the
+    eager step on the same batches, with other GPU work and a synchronisation
+    between the replays: after every step the moments agree, the parameters
+    agree wherever the gradient's sign is not at the mercy of the order of the
+    FP32 atomic additions (Adam's first steps move a parameter by lr times the
+    sign of its gradient), the gradient is cleared, the device step count has
+    advanced by one with the bias corrections of that step, and the losses
+    agree."""
+    import torch
+    from paper_2202_08614_amd.finetune import FineTuner
+    dijk = synth.blob_leaves(6, 6000, n_frames=8)
+    gt = synth.gaussian_coeffs(len(dijk), seed=1)
+    init = synth.perturb_coeffs(gt, 0.05, seed=2)
+    cams = [synth.ring_camera(2 * np.pi * k / 6, 0.26, 1.5, 30.0, 96, 96, t) for t in (1.0, 31.0) for k in range(6)]
+    note("fine-tune eager steps vs HIP graph replays")
+    fe = FineTuner.from_scene(dijk, gt, init, 6, cams, dev, batch=8192, seed=3)
+    fg = FineTuner.from_scene(dijk, gt, init, 6, cams, dev, batch=8192, seed=3, graph=True)
+    le = torch.zeros(5, device=dev)
+    lg = torch.zeros(5, device=dev)
+    for k in range(5):
+        b = fe.sample()
+        fe.step(*b[:3], le[k:k + 1], t_idx=b[3])
+        fg.step(*b[:3], lg[k:k + 1], t_idx=b[3])
+        junk = torch.randn(1 << 16, device=dev).square().sum()      # other work between the replays
+        torch.cuda.synchronize()
+        assert float(junk) > 0
+        assert int(fg.adam_state[0]) == k + 1
+        c = fg.adam_state[1:3].view(torch.float32).cpu().numpy()
+        t = k + 1
+        b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))    # the betas reach the library as FP32
+        assert np.allclose(c, [1 / (1 - b1 ** t), 1 / (1 - b2 ** t)], rtol=1e-6)
+        assert not fg.grad.any() and not fe.grad.any()
+        for a, b_ in ((fe.m, fg.m), (fe.v, fg.v)):
+            scale = float(a.abs().max())
+            assert scale > 0 and float((a - b_).abs().max()) <= 1e-4 * scale
+        steady = fe.m.abs() > 1e-3 * float(fe.m.abs().max())
+        assert int(steady.sum()) > 1000
+        assert torch.allclose(fe.tree.coeffs[steady], fg.tree.coeffs[steady], rtol=1e-5, atol=1e-5)
+    assert torch.allclose(le, lg, rtol=1e-4)
