@@ -383,3 +383,18 @@ def test_segment_records_validate_on_host():
     opts.workspace = 1 << 20
     opts.snapshot = 1 << 21
     assert rays(10) == _lib.FPO_E_UNSUPPORTED and back(10) == _lib.FPO_E_UNSUPPORTED
+
+
+@host_only
+def test_adam_step_dev_validates_on_host():
+    """fpo_adam_step_dev refuses a missing or misaligned state and bad
+    hyperparameters before any launch."""
+    L = _lib.lib()
+    p = ctypes.c_void_p(256)
+    assert L.fpo_adam_step_dev(p, p, p, p, 8, 0.01, 0.9, 0.999, 1e-8, None, None) == _lib.FPO_E_INVALID
+    assert b"NULL" in L.fpo_last_error()
+    assert L.fpo_adam_step_dev(p, p, p, p, 8, 0.01, 0.9, 0.999, 1e-8, ctypes.c_void_p(260), None) == _lib.FPO_E_INVALID
+    assert b"aligned" in L.fpo_last_error()
+    assert L.fpo_adam_step_dev(p, p, p, p, 6, 0.01, 0.9, 0.999, 1e-8, p, None) == _lib.FPO_E_INVALID
+    assert L.fpo_adam_step_dev(p, p, p, p, 8, 0.01, 1.0, 0.999, 1e-8, p, None) == _lib.FPO_E_INVALID
+    assert L.fpo_adam_step_dev(p, p, p, p, 8, -1.0, 0.9, 0.999, 1e-8, p, None) == _lib.FPO_E_INVALID
