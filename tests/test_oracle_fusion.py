@@ -179,7 +179,9 @@ def test_length_weighting_within_a_view(oracle_lib):
     for r in range(2):
         dn = d[r] / np.linalg.norm(d[r])
         L = chord_length(lo[0], hi[0], o[r], d[r])
-        t_in = max(min((lo[0][a] - o[r][a]) / dn[a], (hi[0][a] - o[r][a]) / dn[a]) for a in range(3))
+        # slab entry over the axes the ray moves along (both rays start inside the z slab)
+        t_in = max(min((lo[0][a] - o[r][a]) / dn[a], (hi[0][a] - o[r][a]) / dn[a])
+                   for a in range(3) if dn[a] != 0.0)
         Ls.append(L)
         sig.append(fusion.field_sigma(f, o[r] + (t_in + 0.5 * L) * dn))
     assert Ls[0] > 0.02 and Ls[1] > 0.2 and abs(Ls[0] - Ls[1]) > 0.1
