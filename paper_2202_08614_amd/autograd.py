@@ -2,7 +2,15 @@
 
 The forward and backward passes are libfpo calls (fpo_render_rays and
 fpo_render_backward); the optimiser step is fpo_adam_step.  Nothing here
-computes on tensors itself.
+computes on tensors itself: a caller writes the loss of Eq. 13 (or any other
+loss of the rendered colours) with torch, calls loss.backward(), and the
+library's backward kernel scatters dL/drgb into the coefficient records.
+
+    coeffs = tree.coeffs.requires_grad_()
+    opt = Adam(coeffs, lr=1e-2)
+    rgb = render(tree, o, d, t_idx, basis, opts)
+    ((rgb - target) ** 2).sum(1).mean().backward()
+    opt.step()                       # uses and clears coeffs.grad
 """
 from __future__ import annotations
 
@@ -15,7 +23,10 @@ from . import _lib
 
 class FPORender(torch.autograd.Function):
     """rgb = render(coeffs) for given rays; coeffs are the F32 leaf records
-    of `tree` (passed explicitly so that autograd tracks them)."""
+    of `tree` (passed explicitly so that autograd tracks them).  With
+    FPO_RAYS_RECORD in opts the forward's segment records in opts.workspace
+    serve the backward, so the same opts must not be reused for another
+    forward before backward() runs."""
 
     @staticmethod
     def forward(ctx, coeffs, tree: _lib.DeviceTree, o, d, t_idx, basis, opts: _lib.RenderOpts):
@@ -36,6 +47,8 @@ class FPORender(torch.autograd.Function):
 
 
 def render(tree: _lib.DeviceTree, o, d, t_idx, basis, opts: Optional[_lib.RenderOpts] = None):
+    """Colours [n][3] of rays (o, d) at basis rows t_idx, differentiable in
+    tree.coeffs."""
     return FPORender.apply(tree.coeffs, tree, o, d, t_idx, basis, opts or _lib.make_opts())
 
 
@@ -45,13 +58,20 @@ class Adam:
 
     def __init__(self, params: torch.Tensor, lr: float = 1e-2, betas=(0.9, 0.999), eps: float = 1e-8):
         self.params = params
-        self.m = torch.zeros_like(params)
-        self.v = torch.zeros_like(params)
+        self.m = torch.zeros_like(params, requires_grad=False)
+        self.v = torch.zeros_like(params, requires_grad=False)
         self.lr = float(lr)
         self.betas = (float(betas[0]), float(betas[1]))
         self.eps = float(eps)
         self.t = 0
 
-    def step(self, grad: torch.Tensor):
+    def step(self, grad: Optional[torch.Tensor] = None):
+        """One update with `grad`, or with params.grad (left by backward())."""
+        if grad is None:
+            grad = self.params.grad
+            if grad is None:
+                raise RuntimeError("no gradient: call backward() first or pass grad")
         self.t += 1
-        _lib.adam_step(self.params, grad, self.m, self.v, self.t, self.lr, self.betas[0], self.betas[1], self.eps)
+        with torch.no_grad():
+            _lib.adam_step(self.params, grad, self.m, self.v, self.t, self.lr, self.betas[0], self.betas[1],
+                           self.eps)

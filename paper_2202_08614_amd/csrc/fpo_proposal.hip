@@ -214,6 +214,16 @@ __global__ __launch_bounds__(kBlock) void mlp_forward_kernel(const float* __rest
 
 __device__ inline float sigmoid_exact(float v) { return 1.0f / (1.0f + expf(-v)); }
 
+// log(1 + u) for u in [0, 1] in FP32 only: with w = 1 + u rounded, the ratio
+// u / (w - 1) corrects the rounding of w (Goldberg, "What every computer
+// scientist should know about floating-point arithmetic", 1991, Thm. 4), so
+// logf(w) suffices; the library's log1pf would bring an FP64 instruction in.
+__device__ inline float log1p_unit(float u)
+{
+    const float w = 1.0f + u;
+    return w == 1.0f ? u : logf(w) * (u / (w - 1.0f));
+}
+
 __global__ __launch_bounds__(kBlock) void mlp_grad_rays_kernel(const float* __restrict__ P, const float* __restrict__ X,
                                                                const float* __restrict__ Y, const int32_t* __restrict__ idx,
                                                                int64_t n, int64_t ld, float inv_n, float* __restrict__ ws)
@@ -244,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void mlp_grad_rays_kernel(const float* __re
     // loss and dL/do: logistic loss on the hit logit, pinball on the sigmoid
     // of the interval outputs for rays that hit
     const float o0 = F.o[0];
-    float loss = fmaxf(o0, 0.0f) - y0 * o0 + log1pf(expf(-fabsf(o0)));
+    float loss = fmaxf(o0, 0.0f) - y0 * o0 + log1p_unit(expf(-fabsf(o0)));
     float go[3];
     go[0] = sigmoid_exact(o0) - y0;
     const bool hit = y0 > 0.5f;

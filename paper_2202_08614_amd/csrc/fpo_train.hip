@@ -205,15 +205,24 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(float4* p, float4* g, floa
 // Step count kept on the device: state = {int32 step, float c1, float c2, 0}.
 // One thread advances the step and writes the bias corrections for it, so a
 // captured graph that replays this launch and adam_kernel advances by one
-// step per replay.
+// step per replay.  Everything stays in FP32: b is an exact FP32 value, so
+// log(b) is the log of the exact argument, and 1 - b^t = -expm1(t log b)
+// avoids both the cancellation of forming b^t first and the t-fold rounding
+// of a running product; c is within a few FP32 ulps of 1 / (1 - b^t) at every
+// step.
+__device__ inline float adam_bias_correction(float b, int32_t t)
+{
+    return 1.0f / -expm1f((float)t * logf(b));
+}
+
 __global__ void adam_count_kernel(int32_t* state, float b1, float b2)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int32_t t = state[0] + 1;
     state[0] = t;
     float* cs = reinterpret_cast<float*>(state + 1);
-    cs[0] = (float)(1.0 / (1.0 - pow((double)b1, (double)t)));
-    cs[1] = (float)(1.0 / (1.0 - pow((double)b2, (double)t)));
+    cs[0] = b1 > 0.0f ? adam_bias_correction(b1, t) : 1.0f;
+    cs[1] = b2 > 0.0f ? adam_bias_correction(b2, t) : 1.0f;
 }
 
 }  // namespace dev

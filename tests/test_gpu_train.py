@@ -6,7 +6,7 @@ import pytest
 
 from oracle.optim import adam as adam_ref
 from paper_2202_08614_amd import _lib, synth
-from tests.gpu_util import note, require_gpu
+from tests.gpu_util import check_parity, conditioned_reference, note, perpendicular_pair, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -236,7 +236,12 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev, c4):
     """The fine-tune step at full size: the 500k-leaf depth-8 scene, one
     8192-ray batch drawn over its 24 cameras x 30 times at 800x800 (the
     benchmark's batch); forward colours and the gradient of every coefficient
-    against the FP64 oracle."""
+    against the FP64 oracle.  Colours go through the parity check (ties
+    exempt by their FP64 spread under a 2e-7 sideways shift).  The gradient
+    bar holds for every coefficient except those of leaves that an exempt ray
+    (a tie, or a ray whose early termination straddles the threshold, where
+    the two sides may stop after different segments) crosses, itself or
+    shifted sideways by 1e-6."""
     import torch
     sc, tree = c4
     cams = sc.cameras
@@ -256,8 +261,24 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev, c4):
     ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
     p = oracle_lib.make_params(stop_T=1e-3)
     want, rgb_ref = oracle_lib.render_grad(ot, sc.coeffs, p, times, o, d, t_idx, g_rgb.astype(np.float64))
+    ref = conditioned_reference(oracle_lib, ot, sc.coeffs, oracle_lib.make_params(stop_T=1e-3, band=1e-3), times,
+                                o, d, t_idx)
     gmax = np.abs(want).max()
     assert gmax > 0 and (np.abs(want) > 1e-3 * gmax).sum() > 10000
+    # exempt rays and the coefficients they reach
+    straddle = np.abs(ref["rgb"][:, 0] - ref["rgb"][:, 1]).max(axis=1) > 0
+    ill = ref["spread"] > 1e-4
+    exempt_rays = np.nonzero(straddle | ill)[0]
+    assert len(exempt_rays) <= 0.01 * 8192, len(exempt_rays)
+    u, v = perpendicular_pair(d)
+    touched = set()
+    for r in exempt_rays:
+        for shift in (0.0 * u[r], 1e-6 * u[r], -1e-6 * u[r], 1e-6 * v[r], -1e-6 * v[r]):
+            leaves, _, _ = ot.trace(o[r] + shift, d[r])
+            touched.update(int(x) for x in leaves)
+    exempt_coeffs = np.zeros(want.shape, dtype=bool)
+    if touched:
+        exempt_coeffs[np.array(sorted(touched))] = True
     # the plain backward (rays walked again) and the one from segment records (as the fine-tune runs)
     for name, opts in (("plain", plain), ("recorded", rec)):
         note(f"c4 render_rays + render_backward ({name}) 8192 rays, 500k leaves")
@@ -268,11 +289,12 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev, c4):
                              to(g_rgb), grad, opts)
         torch.cuda.synchronize()
         got = _unpack(grad.cpu().numpy(), tree.perm, sc.n_leaves)
-        # colours within 1e-4; a ray at a cell-face tie (about 2 in 10^5 on this scene) may differ
-        err = np.abs(rgb.cpu().numpy() - rgb_ref).max(axis=1)
-        assert (err > 1e-4).sum() <= 2, (name, np.sort(err)[-5:])
+        check_parity(rgb.cpu().numpy(), ref)
         bad = np.abs(got - want) > 1e-3 * np.abs(want) + 1e-5 * gmax
-        assert bad.sum() <= 1e-5 * bad.size, (name, bad.sum(), np.abs(got - want).max(), gmax)
+        assert not (bad & ~exempt_coeffs).any(), (name, int((bad & ~exempt_coeffs).sum()),
+                                                  np.abs(got - want)[~exempt_coeffs].max(), gmax)
+        print(f"[c4 {name}] exempt rays {len(exempt_rays)} ({int(straddle.sum())} straddle, {int(ill.sum())} ties), "
+              f"exempt leaves {len(touched)}, coefficients off the bar {int(bad.sum())}")
     assert (_lib.record_counts(ws, 8192) >= 0).all()
 
 
