@@ -227,6 +227,22 @@ fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leav
 fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
                       const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): fpo_render with
+ * the skip modes' scratch taken from a static device array of
+ * FPO_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * (until the process ends) instead of opts->workspace, which is ignored.
+ * Cameras go out in launches of as many as the array holds (at most 16).
+ * Allocates nothing.  Every call on one device shares that device's array:
+ * calls that overlap on one device (several streams or threads) race and must
+ * be serialised by the caller; each launch rewrites every pixel's scratch
+ * before reading it, so nothing needs clearing between calls.
+ * FPO_E_CAPACITY (nothing launched) if one camera's scratch, 8 W H bytes,
+ * exceeds FPO_NOALLOC_SCRATCH_BYTES.  Without a skip flag it is fpo_render. */
+#define FPO_NOALLOC_SCRATCH_BYTES (32ll << 20)
+fpo_status fpo_render_noalloc(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
+                              const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream);
+
 /* Generate rays for (camera, row, column) triples.
  *   cam_table device [n_cams][FPO_CAMERA_FLOATS] from fpo_camera_pack.
  *   cam, py, px device [n] int32; must index valid cameras / pixels.

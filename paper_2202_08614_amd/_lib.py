@@ -28,6 +28,7 @@ MAX_DEPTH = 10
 COEFFS_PER_WORD = {FPO_F32: 4, FPO_BF16: 8, FPO_FP8_E4M3: 16}
 RECORD_WORDS = {FPO_F32: 48, FPO_BF16: 24, FPO_FP8_E4M3: 16}   # 16-byte words per leaf record
 SNAP_VALUES = 32
+NOALLOC_SCRATCH_BYTES = 32 << 20   # fpo_render_noalloc's static device scratch
 
 
 def record_words(dtype: int) -> int:
@@ -92,6 +93,8 @@ _SIGS = {
     "fpo_pack_coeffs": [_P, _P, _I64, _I64, ctypes.POINTER(Layout), _P, _P],
     "fpo_render": [ctypes.POINTER(TreeView), ctypes.POINTER(CameraC), _I32,
                    ctypes.POINTER(RenderOpts), _P, _P, _P],
+    "fpo_render_noalloc": [ctypes.POINTER(TreeView), ctypes.POINTER(CameraC), _I32,
+                           ctypes.POINTER(RenderOpts), _P, _P, _P],
     "fpo_camera_rays": [_P, _I32, _P, _P, _P, _I64, _P, _P, _P],
     "fpo_render_rays": [ctypes.POINTER(TreeView), _P, _P, _P, _P, _I32, _I64,
                         ctypes.POINTER(RenderOpts), _P, _P, _P],
@@ -338,6 +341,25 @@ def render(tree: DeviceTree, cams, opts: Optional[RenderOpts] = None, rgb=None, 
     tv = tree.view()
     arr = camera_struct(cams)
     _check(lib().fpo_render(ctypes.byref(tv), arr, n, ctypes.byref(opts), _t_ptr(rgb), _t_ptr(T), _stream()))
+    return rgb, T
+
+
+def render_noalloc(tree: DeviceTree, cams, opts: Optional[RenderOpts] = None, rgb=None, T=None,
+                   want_T: bool = False):
+    """fpo_render_noalloc: fpo_render with the skip scratch in the library's
+    static device array (opts.workspace is ignored)."""
+    import torch
+    opts = opts or make_opts()
+    n, H, W = len(cams), int(cams[0].height), int(cams[0].width)
+    dev = tree.children.device
+    if rgb is None:
+        rgb = torch.empty((n, H, W, 3), dtype=torch.float32, device=dev)
+    if T is None and want_T:
+        T = torch.empty((n, H, W), dtype=torch.float32, device=dev)
+    tv = tree.view()
+    arr = camera_struct(cams)
+    _check(lib().fpo_render_noalloc(ctypes.byref(tv), arr, n, ctypes.byref(opts), _t_ptr(rgb), _t_ptr(T),
+                                    _stream()))
     return rgb, T
 
 

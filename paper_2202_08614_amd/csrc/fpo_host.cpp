@@ -61,7 +61,8 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_la
     return FPO_OK;
 }
 
-fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip, bool allow_record)
+fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip, bool allow_record,
+                      bool skip_workspace)
 {
     if (!opts) return fail(FPO_E_INVALID, "opts is NULL");
     for (int c = 0; c < 3; ++c)
@@ -77,7 +78,7 @@ fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bo
         if (!opts->coarse_bits) return fail(FPO_E_INVALID, "skip modes need opts->coarse_bits");
         if (opts->flags == FPO_RENDER_SKIP_PROPOSAL && !opts->proposal)
             return fail(FPO_E_INVALID, "FPO_RENDER_SKIP_PROPOSAL needs opts->proposal");
-        if (!opts->workspace || (reinterpret_cast<uintptr_t>(opts->workspace) & 7) != 0)
+        if (skip_workspace && (!opts->workspace || (reinterpret_cast<uintptr_t>(opts->workspace) & 7) != 0))
             return fail(FPO_E_INVALID, "skip modes need an 8-byte aligned opts->workspace");
         if ((reinterpret_cast<uintptr_t>(opts->proposal) & 15) != 0)
             return fail(FPO_E_INVALID, "opts->proposal must be 16-byte aligned");

@@ -42,9 +42,11 @@ inline int record_words(fpo_dtype dt, int n1, int n2)
 // handles every layout_supported() layout (else only the default one).
 fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_layouts = false);
 // allow_skip: the call accepts the skip flags (fpo_render only); allow_record:
-// it accepts FPO_RAYS_RECORD (fpo_render_rays, fpo_render_backward).
+// it accepts FPO_RAYS_RECORD (fpo_render_rays, fpo_render_backward);
+// skip_workspace: skip modes need opts->workspace (not so for a call that
+// brings its own scratch).
 fpo_status check_opts(const fpo_render_opts* opts, const fpo_tree_view* tree, bool allow_skip = false,
-                      bool allow_record = false);
+                      bool allow_record = false, bool skip_workspace = true);
 
 // Segment records in opts->workspace (FPO_RAYS_RECORD): per-ray counts at the
 // start, records of FPO_RECORD_BYTES from the next 256-byte boundary, cap

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "fpo.h"
@@ -420,8 +421,12 @@ static void launch_cam(const dev::CamLaunch& a, int grid, int skip, hipStream_t 
                            dim3(dev::kBlock), 0, s, a);
 }
 
-extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
-                                 const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
+// The body of fpo_render: cameras go out in launches of at most
+// cams_per_launch (<= 16); the skip modes' scratch (opts->workspace) holds
+// one launch's pixels and is reused by every launch of the call.
+static fpo_status render_impl(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
+                              const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream,
+                              int cams_per_launch)
 {
     fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr, true);
     if (st != FPO_OK) return st;
@@ -438,8 +443,9 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
             return fail(FPO_E_INVALID, "all cameras of one call must share width and height");
     if ((int64_t)W * H > (1ll << 30)) return fail(FPO_E_INVALID, "image too large");
     const int skip = opts->flags;
+    const int per_launch = std::max(1, std::min(cams_per_launch, dev::kCamsPerLaunch));
     if (skip != 0) {
-        const int64_t need = (int64_t)std::min(n_cams, dev::kCamsPerLaunch) * W * H * 8;
+        const int64_t need = (int64_t)std::min(n_cams, per_launch) * W * H * 8;
         if (opts->workspace_bytes < need)
             return fail(FPO_E_INVALID, "opts->workspace_bytes < min(n_cams, 16) * W * H * 8");
     }
@@ -464,8 +470,8 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
     const bool snap_buf = opts->snapshot && (uint64_t)tree->n_leaves * snap_rec <= 0xFFFFFFFFull;
     a.snap_bytes = snap_buf ? (uint32_t)((uint64_t)tree->n_leaves * snap_rec) : 0u;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int c0 = 0; c0 < n_cams; c0 += dev::kCamsPerLaunch) {
-        const int nc = std::min(dev::kCamsPerLaunch, n_cams - c0);
+    for (int c0 = 0; c0 < n_cams; c0 += per_launch) {
+        const int nc = std::min(per_launch, n_cams - c0);
         a.n_cams = nc;
         for (int i = 0; i < nc; ++i) {
             const fpo_camera& cam = cams[c0 + i];
@@ -534,6 +540,73 @@ extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* ca
         if ((st = launch_status("fpo_render")) != FPO_OK) return st;
     }
     return FPO_OK;
+}
+
+extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
+                                 const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
+{
+    return render_impl(tree, cams, n_cams, opts, rgb_out, T_out, stream, dev::kCamsPerLaunch);
+}
+
+// ---------------------------------------------------------------------------
+// fpo_render_noalloc: fpo_render whose skip-mode scratch is a file-scope
+// device array instead of a caller workspace.  Each device that loads the
+// library holds its own copy (kNoallocScratchBytes) until the process ends.
+// Host code never passes the array's name to a kernel: its device address
+// comes from hipGetSymbolAddress, once per device, with that device current.
+// ---------------------------------------------------------------------------
+namespace fpo {
+namespace dev {
+constexpr int64_t kNoallocScratchBytes = FPO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+}  // namespace dev
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call from that device).
+static fpo_status scratch_address(void** out)
+{
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kMaxDevices)
+        return fail(FPO_E_DEVICE, "fpo_render_noalloc: no current HIP device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[d]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(dev::scratch));
+        if (e != hipSuccess || !p)
+            return fail(FPO_E_DEVICE, std::string("fpo_render_noalloc: hipGetSymbolAddress failed: ") +
+                                          hipGetErrorString(e));
+        g_scratch_ptr[d] = p;
+    }
+    *out = g_scratch_ptr[d];
+    return FPO_OK;
+}
+}  // namespace fpo
+
+extern "C" fpo_status fpo_render_noalloc(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
+                                         const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
+{
+    // every host-side check before the device is touched
+    fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr, true);
+    if (st != FPO_OK) return st;
+    if ((st = check_opts(opts, tree, true, false, false)) != FPO_OK) return st;
+    if (opts->flags == 0) return render_impl(tree, cams, n_cams, opts, rgb_out, T_out, stream, dev::kCamsPerLaunch);
+    if (!cams || n_cams < 1) return fail(FPO_E_INVALID, "cams is NULL or n_cams < 1");
+    const int64_t per_cam = (int64_t)cams[0].width * cams[0].height * 8;
+    if (cams[0].width < 1 || cams[0].height < 1) return fail(FPO_E_INVALID, "bad image size");
+    if (per_cam > FPO_NOALLOC_SCRATCH_BYTES)
+        return fail(FPO_E_CAPACITY, "fpo_render_noalloc: one camera's skip scratch (8 W H bytes) exceeds "
+                                    "FPO_NOALLOC_SCRATCH_BYTES; use fpo_render with a workspace");
+    void* ptr = nullptr;
+    if ((st = scratch_address(&ptr)) != FPO_OK) return st;
+    fpo_render_opts o = *opts;
+    o.workspace = ptr;
+    o.workspace_bytes = FPO_NOALLOC_SCRATCH_BYTES;
+    const int per_launch = (int)std::min<int64_t>(dev::kCamsPerLaunch, FPO_NOALLOC_SCRATCH_BYTES / per_cam);
+    return render_impl(tree, cams, n_cams, &o, rgb_out, T_out, stream, per_launch);
 }
 
 template <int MODE>

@@ -398,3 +398,36 @@ def test_adam_step_dev_validates_on_host():
     assert L.fpo_adam_step_dev(p, p, p, p, 6, 0.01, 0.9, 0.999, 1e-8, p, None) == _lib.FPO_E_INVALID
     assert L.fpo_adam_step_dev(p, p, p, p, 8, 0.01, 1.0, 0.999, 1e-8, p, None) == _lib.FPO_E_INVALID
     assert L.fpo_adam_step_dev(p, p, p, p, 8, -1.0, 0.9, 0.999, 1e-8, p, None) == _lib.FPO_E_INVALID
+
+
+@host_only
+def test_render_noalloc_validates_on_host():
+    """fpo_render_noalloc rejects bad options and a camera whose skip scratch
+    exceeds its static array before it touches the device."""
+    L = _lib.lib()
+    view = _lib.TreeView()
+    view.children = 16
+    view.n_nodes = 1
+    view.max_depth = 3
+    view.n_leaves = 1
+    view.leaf_stride = 1
+    view.coeffs = 16
+    view.layout = _lib.make_layout()
+    opts = _lib.make_opts()
+    opts.flags = 3
+    cams = _lib.camera_struct([synth.ring_camera(0, 0, 1.5, 30, 4, 4, 0)])
+    st = L.fpo_render_noalloc(ctypes.byref(view), cams, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_INVALID and b"flags" in L.fpo_last_error()
+    opts.flags = _lib.FPO_RENDER_SKIP_COARSE
+    opts.coarse_bits = 64
+    # no workspace needed, but one camera's 8 W H bytes must fit the static array
+    side = int(math.isqrt(_lib.NOALLOC_SCRATCH_BYTES // 8)) + 1
+    big = _lib.camera_struct([synth.ring_camera(0, 0, 1.5, 30, side, side, 0)])
+    st = L.fpo_render_noalloc(ctypes.byref(view), big, 1, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_CAPACITY and b"FPO_NOALLOC_SCRATCH_BYTES" in L.fpo_last_error()
+    st = L.fpo_render_noalloc(ctypes.byref(view), None, 0, ctypes.byref(opts), ctypes.c_void_p(16), None, None)
+    assert st == _lib.FPO_E_INVALID
+    # the header's size and the binding's agree
+    src = open(os.path.join(ROOT, "include", "fpo.h")).read()
+    assert re.search(r"#define FPO_NOALLOC_SCRATCH_BYTES \(32ll << 20\)", src)
+    assert _lib.NOALLOC_SCRATCH_BYTES == 32 << 20
