@@ -8,7 +8,8 @@ import pytest
 
 from oracle import codec
 from paper_2202_08614_amd import _lib, synth
-from tests.gpu_util import check_parity, conditioned_reference, note, psnr, require_gpu, straddle_err
+from tests.gpu_util import (check_parity, conditioned_reference, note, perpendicular_pair, psnr, require_gpu,
+                            straddle_err)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -236,3 +237,125 @@ def test_c3_bake_sampled(oracle_lib, dev, store):
     mag[:, 0] = np.abs(B) @ ka[:, :31].T
     mag[:, 1:] = np.einsum("ti,lmi->tml", np.abs(B[:, :5]), ka[:, 31:].reshape(-1, 27, 5))
     assert np.all(np.abs(got - want) <= 2.0 ** -8 * np.abs(want) + 2.0 ** -19 * mag + 1e-7)
+
+
+def _bf16_round(x: np.ndarray) -> np.ndarray:
+    """FP64 values -> the FP64 values of their nearest BF16 (via FP32, RNE)."""
+    return codec.bf16_decode(codec.bf16_encode(np.asarray(x, np.float32))).astype(np.float64)
+
+
+def _bf16_records(vals: np.ndarray, perm: np.ndarray, stride: int) -> np.ndarray:
+    """[n_t][28][L] FP64 (caller order, BF16-exact) -> [n_t][stride][32] BF16
+    bit patterns as int16 (slot order, padding zero)."""
+    n_t, _, L = vals.shape
+    out = np.zeros((n_t, stride, _lib.SNAP_VALUES), np.uint16)
+    out[:, :L, :28] = codec.bf16_encode(vals[:, :, perm].transpose(0, 2, 1).astype(np.float32))
+    return out.view(np.int16)
+
+
+def test_bf16_snapshot_render_matches_oracle(oracle_lib, dev):
+    """BF16 snapshot records (the baked static PlenOctree at one time, stored
+    in BF16): the oracle's bake rounded to BF16 is rendered by the GPU (camera
+    render, one snapshot per camera, and the ray render) and by the oracle
+    from the same values; kernel error within 1e-4."""
+    import torch
+    sc = synth.c1_scene()
+    times = [5.0, 22.2, 47.5]
+    cams = [synth.ring_camera(0.4 + k, 0.3, 1.5, 45.0, 64, 48, times[k]) for k in range(3)]
+    p = oracle_lib.make_params(stop_T=1e-3)
+    snap = _bf16_round(oracle_lib.bake(sc.coeffs.astype(np.float64), p, times))      # [3][28][L]
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, 6, device=dev, leaf_stride=len(sc.leaf_dijk) + 9)
+    recs = torch.from_numpy(_bf16_records(snap, tree.perm, tree.leaf_stride)).to(dev).view(torch.bfloat16)
+    note("c1 snapshot render BF16 (camera and ray kernels)")
+    opts = _lib.make_opts(stop_T=1e-3, snapshot=recs, snapshot_dtype=_lib.FPO_BF16,
+                          snapshot_cam_stride=tree.leaf_stride)
+    rgb, _ = _lib.render(tree, cams, opts)
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
+    for k in range(3):
+        o, d = oracle_lib.camera_rays(cams[k])
+        z = np.zeros(len(o), np.int32)
+        ref = conditioned_reference(oracle_lib, ot, None, p, [times[k]], o, d, z, snapshot=snap[k])
+        check_parity(rgb[k].cpu().numpy().reshape(-1, 3), ref, TOL)
+        # the ray kernel on the same rays, time index k into the same records
+        o32, d32 = o.astype(np.float32), d.astype(np.float32)
+        t_idx = torch.full((len(o),), k, dtype=torch.int32, device=dev)
+        basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+        rgb_r, _ = _lib.render_rays(tree, torch.from_numpy(o32).to(dev), torch.from_numpy(d32).to(dev), t_idx,
+                                    basis, opts)
+        torch.cuda.synchronize()
+        check_parity(rgb_r.cpu().numpy(), ref, TOL)
+    assert float(rgb.max()) > 0.05
+
+
+def test_c3_bf16_snapshot_render_sampled(oracle_lib, dev):
+    """Config-3 size: the 2M-leaf scene quantised to BF16, 64 times baked into
+    BF16 snapshots, 64 views at 800x800 rendered in one call, view k from
+    snapshot k (the benchmark's launches).  Total error: PSNR of sampled
+    pixels against the FP64 oracle on the FP32 coefficients, >= 50 dB.
+    Kernel error: the leaves the sampled rays cross (also shifted sideways by
+    1e-6) get the oracle's bake of their dequantised coefficients rounded to
+    BF16, in the GPU's snapshots and in the oracle's; the render then matches
+    the oracle's within 1e-4."""
+    import torch
+    sc = synth.c2_scene()
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    qt = _lib.quantize(tree, _lib.FPO_BF16)
+    n_t, size = 64, 800
+    times = [k * synth.PERIOD / n_t for k in range(n_t)]
+    cams = synth.c3_cameras(size, size, n_t)
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    note("c3 bake 64 times BF16 + 64 views 800x800 BF16 snapshots")
+    snaps = _lib.bake_times(qt, basis, _lib.FPO_BF16)
+    opts = _lib.make_opts(stop_T=1e-3, snapshot=snaps, snapshot_dtype=_lib.FPO_BF16,
+                          snapshot_cam_stride=tree.leaf_stride)
+    frames, _ = _lib.render(qt, cams, opts)
+    torch.cuda.synchronize()
+    m = 3000
+    ci, py, px = synth.sample_pixels(m, n_t, size, size, seed=64)
+    idx = [torch.from_numpy(a.astype(np.int64)).to(dev) for a in (ci, py, px)]
+    got = frames[idx[0], idx[1], idx[2]].cpu().numpy().astype(np.float64)
+    o = np.zeros((m, 3)); d = np.zeros((m, 3))
+    for c in np.unique(ci):
+        sel = np.nonzero(ci == c)[0]
+        o[sel], d[sel] = oracle_lib.camera_rays(cams[c], px[sel], py[sel])
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
+    p = oracle_lib.make_params(stop_T=1e-3)
+    full = oracle_lib.render_rays(ot, sc.coeffs, p, times, o, d, ci, n_threads=8)["rgb"]
+    err_total = straddle_err(got, full)
+    mse = float(np.mean(np.min([((got - full[:, j]) ** 2).mean(1) for j in range(2)], axis=0)))
+    db = 10 * np.log10(1.0 / mse)
+    print(f"[c3 bf16] total error: PSNR {db:.2f} dB, max abs {err_total.max():.3e} over {m} sampled pixels")
+    assert db >= 50.0
+    # kernel error: the crossed leaves hold the oracle's BF16-rounded bake on both sides
+    codes, scale = codec.quantize(sc.coeffs, "bf16")
+    u, v = perpendicular_pair(d)
+    inv = np.empty_like(tree.perm)
+    inv[tree.perm] = np.arange(len(tree.perm))
+    refs = {}
+    for c in np.unique(ci):
+        sel = np.nonzero(ci == c)[0]
+        touched = set()
+        for r in sel:
+            for sh in (0.0 * u[r], 1e-6 * u[r], -1e-6 * u[r], 1e-6 * v[r], -1e-6 * v[r]):
+                touched.update(int(x) for x in ot.trace(o[r] + sh, d[r])[0])
+        leaves = np.array(sorted(touched), np.int64)
+        k_eff = codec.dequantize(codes[leaves], scale[leaves], "bf16")
+        vals = _bf16_round(oracle_lib.bake(k_eff, p, [times[c]]))[0]            # [28][n]
+        snap_o = np.zeros((28, sc.n_leaves))
+        snap_o[:, leaves] = vals
+        rec = np.zeros((len(leaves), _lib.SNAP_VALUES), np.uint16)
+        rec[:, :28] = codec.bf16_encode(vals.T.astype(np.float32))
+        slots = torch.from_numpy(inv[leaves]).to(dev)
+        snaps[c, slots] = torch.from_numpy(rec.view(np.int16)).to(dev).view(torch.bfloat16)
+        refs[c] = (sel, snap_o)
+    note("c3 BF16 snapshot render with the oracle's values on the sampled rays' leaves")
+    _lib.render(qt, cams, opts, rgb=frames)
+    torch.cuda.synchronize()
+    got = frames[idx[0], idx[1], idx[2]].cpu().numpy().astype(np.float64)
+    n_exempt = 0
+    for c, (sel, snap_o) in refs.items():
+        ref = conditioned_reference(oracle_lib, ot, None, p, [times[c]], o[sel], d[sel],
+                                    np.zeros(len(sel), np.int32), snapshot=snap_o)
+        _, ex = check_parity(got[sel], ref, TOL, max_exempt_frac=0.05)
+        n_exempt += int(ex.sum())
+    assert n_exempt <= 0.01 * m, n_exempt
