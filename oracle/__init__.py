@@ -77,9 +77,9 @@ def lib():
                                      _P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, _P, _P]
         L.or_render_rays.restype = ctypes.c_int32
         L.or_render_grad.argtypes = [ctypes.c_void_p, _P, ctypes.POINTER(_Params), _P, ctypes.c_int32,
-                                     _P, _P, _P, ctypes.c_int64, _P, _P, _P]
+                                     _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, _P, _P]
         L.or_render_grad.restype = ctypes.c_int32
-        L.or_bake.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(_Params), _P, ctypes.c_int32, _P]
+        L.or_bake.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(_Params), _P, ctypes.c_int32, ctypes.c_int32, _P]
         L.or_ray_labels.argtypes = [ctypes.c_void_p, _P, ctypes.POINTER(_Params), _P, ctypes.c_int32,
                                     _P, _P, _P, ctypes.c_int64, _P]
         L.or_ray_labels.restype = ctypes.c_int32
@@ -214,8 +214,9 @@ def render_rays(tree: OracleTree, coeffs: Optional[np.ndarray], params: _Params,
 
 
 def render_grad(tree: OracleTree, coeffs: np.ndarray, params: _Params, times: Sequence[float],
-                o: np.ndarray, d: np.ndarray, t_idx: np.ndarray, grad_rgb: np.ndarray):
-    """dL/dk for dL/dC = grad_rgb, FP64.  Returns (grad [L][ncoeff], rgb [n][3])."""
+                o: np.ndarray, d: np.ndarray, t_idx: np.ndarray, grad_rgb: np.ndarray, n_threads: int = 8):
+    """dL/dk for dL/dC = grad_rgb, FP64.  Returns (grad [L][ncoeff], rgb [n][3]).
+    The sums are formed in ray order for any thread count."""
     o = np.ascontiguousarray(o, dtype=np.float64)
     d = np.ascontiguousarray(d, dtype=np.float64)
     t_idx = np.ascontiguousarray(t_idx, dtype=np.int32)
@@ -225,18 +226,19 @@ def render_grad(tree: OracleTree, coeffs: np.ndarray, params: _Params, times: Se
     grad = np.zeros_like(c)
     rgb = np.zeros((o.shape[0], 3))
     st = lib().or_render_grad(tree._h, _ptr(c), ctypes.byref(params), _ptr(times), len(times),
-                              _ptr(o), _ptr(d), _ptr(t_idx), o.shape[0], _ptr(g), _ptr(grad), _ptr(rgb))
+                              _ptr(o), _ptr(d), _ptr(t_idx), o.shape[0], _ptr(g), int(n_threads), _ptr(grad),
+                              _ptr(rgb))
     if st != 0:
         raise MemoryError("oracle gradient failed")
     return grad, rgb
 
 
-def bake(coeffs: np.ndarray, params: _Params, times: Sequence[float]) -> np.ndarray:
+def bake(coeffs: np.ndarray, params: _Params, times: Sequence[float], n_threads: int = 1) -> np.ndarray:
     """Eq. 7 / Eq. 9 at every time: [n_t][28][L] FP64."""
     c = np.ascontiguousarray(coeffs, dtype=np.float64)
     times = np.ascontiguousarray(times, dtype=np.float64)
     out = np.zeros((len(times), 28, c.shape[0]))
-    lib().or_bake(_ptr(c), c.shape[0], ctypes.byref(params), _ptr(times), len(times), _ptr(out))
+    lib().or_bake(_ptr(c), c.shape[0], ctypes.byref(params), _ptr(times), len(times), int(n_threads), _ptr(out))
     return out
 
 

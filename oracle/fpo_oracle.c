@@ -488,30 +488,66 @@ int32_t or_render_rays(const or_tree* tr, const double* coeffs, const double* sn
 /* The analytic reverse of the per-ray compositing above, FP64, with the     */
 /* nominal early-termination rule (threshold tau).  grad_rgb: [n][3] = dL/dC */
 /* per ray.  grad: [L][ncoeff] caller order, accumulated (+=).               */
-/* Also writes the forward colour rgb [n][3].  Single-threaded.              */
+/* Also writes the forward colour rgb [n][3].                                */
+/* Threads take contiguous ranges of rays and list each composited segment's */
+/* ncoeff derivatives; the lists are added into grad in ray order, so the    */
+/* sums are formed in the same order for any thread count.                   */
 /* ------------------------------------------------------------------------ */
-int32_t or_render_grad(const or_tree* tr, const double* coeffs, const or_params* p,
-                       const double* times, int32_t n_t,
-                       const double* o, const double* d_in, const int32_t* t_idx, int64_t n,
-                       const double* grad_rgb, double* grad, double* rgb_out)
+typedef struct {
+    const or_tree* tr;
+    const double* coeffs;
+    const or_params* p;
+    const double* basis;     /* [n_t][nb] */
+    int32_t nb;
+    const double* o;
+    const double* d_in;
+    const int32_t* t_idx;
+    const double* grad_rgb;
+    double* rgb_out;
+    int64_t begin, end;
+    int64_t* leaves;         /* one per listed segment */
+    double* vals;            /* ncoeff per listed segment */
+    int64_t n_list, cap_list;
+    int32_t status;
+} or_grad_job;
+
+static int or_grad_push(or_grad_job* job, int64_t leaf, int32_t nc, double** row)
 {
+    if (job->n_list == job->cap_list) {
+        const int64_t cap = job->cap_list ? 2 * job->cap_list : 1024;
+        int64_t* l = (int64_t*)realloc(job->leaves, sizeof(int64_t) * cap);
+        if (!l) return 5;
+        job->leaves = l;
+        double* v = (double*)realloc(job->vals, sizeof(double) * cap * nc);
+        if (!v) return 5;
+        job->vals = v;
+        job->cap_list = cap;
+    }
+    job->leaves[job->n_list] = leaf;
+    *row = job->vals + job->n_list * nc;
+    for (int32_t q = 0; q < nc; ++q) (*row)[q] = 0.0;
+    ++job->n_list;
+    return 0;
+}
+
+static void* or_grad_worker(void* arg)
+{
+    or_grad_job* job = (or_grad_job*)arg;
+    const or_tree* tr = job->tr;
+    const or_params* p = job->p;
     const int32_t nc = or_ncoeff(p);
-    const int32_t nb = p->n_sigma > p->n_sh_fourier ? p->n_sigma : p->n_sh_fourier;
     const int64_t cap = 3 * ((int64_t)1 << tr->max_depth) + 8;
     int64_t* sl = (int64_t*)malloc(sizeof(int64_t) * cap);
     double* s0 = (double*)malloc(sizeof(double) * cap);
     double* s1 = (double*)malloc(sizeof(double) * cap);
     /* per segment: sigma_raw, sigma, delta, T_before, alpha, rgb[3] */
     double* st = (double*)malloc(sizeof(double) * cap * 8);
-    double* basis = (double*)malloc(sizeof(double) * (size_t)(n_t > 0 ? n_t : 1) * nb);
-    if (!sl || !s0 || !s1 || !st || !basis) { free(sl); free(s0); free(s1); free(st); free(basis); return 5; }
-    for (int32_t t = 0; t < n_t; ++t) or_basis(times[t], p->period, nb, basis + (int64_t)t * nb);
-
-    for (int64_t r = 0; r < n; ++r) {
-        const double* b = basis + (int64_t)t_idx[r] * nb;
-        double d[3] = {d_in[3 * r], d_in[3 * r + 1], d_in[3 * r + 2]};
+    if (!sl || !s0 || !s1 || !st) { job->status = 5; free(sl); free(s0); free(s1); free(st); return NULL; }
+    for (int64_t r = job->begin; r < job->end; ++r) {
+        const double* b = job->basis + (int64_t)job->t_idx[r] * job->nb;
+        double d[3] = {job->d_in[3 * r], job->d_in[3 * r + 1], job->d_in[3 * r + 2]};
         or_normalize(d);
-        const int64_t nseg = or_trace(tr, o + 3 * r, d, cap, sl, s0, s1);
+        const int64_t nseg = or_trace(tr, job->o + 3 * r, d, cap, sl, s0, s1);
         double Y[9];
         or_sh9(d, Y);
         double T = 1.0, C[3] = {0.0, 0.0, 0.0};
@@ -519,7 +555,7 @@ int32_t or_render_grad(const or_tree* tr, const double* coeffs, const or_params*
         for (int64_t s = 0; s < nseg; ++s) {
             const int64_t l = sl[s];
             double sraw, z[27];
-            or_leaf_values(p, coeffs + l * nc, b, NULL, l, tr->n_leaves, &sraw, z);
+            or_leaf_values(p, job->coeffs + l * nc, b, NULL, l, tr->n_leaves, &sraw, z);
             const double sigma = p->sigma_scale * (sraw > 0.0 ? sraw : 0.0);
             const double delta = s1[s] - s0[s];
             const double alpha = -expm1(-sigma * delta);
@@ -537,13 +573,12 @@ int32_t or_render_grad(const or_tree* tr, const double* coeffs, const or_params*
         }
         double Cf[3];
         for (int c = 0; c < 3; ++c) Cf[c] = C[c] + T * p->bg[c];
-        if (rgb_out) for (int c = 0; c < 3; ++c) rgb_out[3 * r + c] = Cf[c];
-        const double* g = grad_rgb + 3 * r;
+        if (job->rgb_out) for (int c = 0; c < 3; ++c) job->rgb_out[3 * r + c] = Cf[c];
+        const double* g = job->grad_rgb + 3 * r;
         /* R_i = C_final - sum_{j<=i} T_j alpha_j c_j */
         double acc[3] = {0.0, 0.0, 0.0};
         for (int64_t s = 0; s < used; ++s) {
             const double* e = st + 8 * s;
-            const int64_t l = sl[s];
             const double Tb = e[3], alpha = e[4], sigma_delta = e[1] * e[2];
             const double T_after = Tb * exp(-sigma_delta);
             double dsig = 0.0;
@@ -555,21 +590,69 @@ int32_t or_render_grad(const or_tree* tr, const double* coeffs, const or_params*
                 const double dc = g[c] * Tb * alpha;
                 dh[c] = dc * e[5 + c] * (1.0 - e[5 + c]);
             }
-            double* gl = grad + l * nc;
+            double* gl;
+            if ((job->status = or_grad_push(job, sl[s], nc, &gl)) != 0) break;
             if (e[0] > 0.0) {
                 const double ds_raw = dsig * p->sigma_scale;
-                for (int32_t i = 0; i < p->n_sigma; ++i) gl[i] += ds_raw * b[i];
+                for (int32_t i = 0; i < p->n_sigma; ++i) gl[i] = ds_raw * b[i];
             }
             for (int c = 0; c < 3; ++c)
                 for (int j = 0; j < 9; ++j) {
                     const double dz = dh[c] * Y[j];
                     double* gz = gl + p->n_sigma + (c * 9 + j) * p->n_sh_fourier;
-                    for (int32_t i = 0; i < p->n_sh_fourier; ++i) gz[i] += dz * b[i];
+                    for (int32_t i = 0; i < p->n_sh_fourier; ++i) gz[i] = dz * b[i];
                 }
         }
+        if (job->status) break;
     }
-    free(sl); free(s0); free(s1); free(st); free(basis);
-    return 0;
+    free(sl); free(s0); free(s1); free(st);
+    return NULL;
+}
+
+int32_t or_render_grad(const or_tree* tr, const double* coeffs, const or_params* p,
+                       const double* times, int32_t n_t,
+                       const double* o, const double* d_in, const int32_t* t_idx, int64_t n,
+                       const double* grad_rgb, int32_t n_threads, double* grad, double* rgb_out)
+{
+    const int32_t nc = or_ncoeff(p);
+    const int32_t nb = p->n_sigma > p->n_sh_fourier ? p->n_sigma : p->n_sh_fourier;
+    double* basis = (double*)malloc(sizeof(double) * (size_t)(n_t > 0 ? n_t : 1) * nb);
+    if (!basis) return 5;
+    for (int32_t t = 0; t < n_t; ++t) or_basis(times[t], p->period, nb, basis + (int64_t)t * nb);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    pthread_t th[256];
+    or_grad_job jobs[256];
+    memset(jobs, 0, sizeof(jobs));
+    int32_t status = 0;
+    /* rays in chunks, so that the segment lists stay small */
+    const int64_t chunk = (int64_t)n_threads * 2048;
+    for (int64_t c0 = 0; c0 < n && status == 0; c0 += chunk) {
+        const int64_t m = n - c0 < chunk ? n - c0 : chunk;
+        for (int32_t w = 0; w < n_threads; ++w) {
+            or_grad_job* j = &jobs[w];
+            j->tr = tr; j->coeffs = coeffs; j->p = p; j->basis = basis; j->nb = nb;
+            j->o = o; j->d_in = d_in; j->t_idx = t_idx; j->grad_rgb = grad_rgb; j->rgb_out = rgb_out;
+            j->begin = c0 + m * w / n_threads;
+            j->end = c0 + m * (w + 1) / n_threads;
+            j->n_list = 0;
+            j->status = 0;
+        }
+        for (int32_t w = 1; w < n_threads; ++w) pthread_create(&th[w], NULL, or_grad_worker, &jobs[w]);
+        or_grad_worker(&jobs[0]);
+        for (int32_t w = 1; w < n_threads; ++w) pthread_join(th[w], NULL);
+        for (int32_t w = 0; w < n_threads; ++w) {
+            if (jobs[w].status) { status = jobs[w].status; break; }
+            for (int64_t e = 0; e < jobs[w].n_list; ++e) {
+                double* gl = grad + jobs[w].leaves[e] * nc;
+                const double* v = jobs[w].vals + e * nc;
+                for (int32_t q = 0; q < nc; ++q) gl[q] += v[q];
+            }
+        }
+    }
+    for (int32_t w = 0; w < n_threads; ++w) { free(jobs[w].leaves); free(jobs[w].vals); }
+    free(basis);
+    return status;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -577,22 +660,55 @@ int32_t or_render_grad(const or_tree* tr, const double* coeffs, const or_params*
 /* out: [n_t][28][L]; row 0 = sigma(t) (before activation), row 1 + c*9 + j  */
 /* = z_{c,j}(t).  coeffs: [L][ncoeff].                                       */
 /* ------------------------------------------------------------------------ */
-void or_bake(const double* coeffs, int64_t n_leaves, const or_params* p,
-             const double* times, int32_t n_t, double* out)
+typedef struct {
+    const double* coeffs;
+    int64_t n_leaves;
+    const or_params* p;
+    const double* times;
+    int32_t n_t;
+    double* out;
+    int64_t begin, end;      /* leaf range of this thread */
+} or_bake_job;
+
+static void* or_bake_worker(void* arg)
 {
+    const or_bake_job* job = (const or_bake_job*)arg;
+    const or_params* p = job->p;
     const int32_t nc = or_ncoeff(p);
+    const int64_t L = job->n_leaves;
     double b[OR_MAX_COEFF];
     const int32_t nb = p->n_sigma > p->n_sh_fourier ? p->n_sigma : p->n_sh_fourier;
-    for (int32_t t = 0; t < n_t; ++t) {
-        or_basis(times[t], p->period, nb, b);
-        for (int64_t l = 0; l < n_leaves; ++l) {
+    for (int32_t t = 0; t < job->n_t; ++t) {
+        or_basis(job->times[t], p->period, nb, b);
+        double* o = job->out + (int64_t)t * 28 * L;
+        for (int64_t l = job->begin; l < job->end; ++l) {
             double sraw, z[27];
-            or_leaf_values(p, coeffs + l * nc, b, NULL, l, n_leaves, &sraw, z);
-            double* o = out + (int64_t)t * 28 * n_leaves;
+            or_leaf_values(p, job->coeffs + l * nc, b, NULL, l, L, &sraw, z);
             o[l] = sraw;
-            for (int q = 0; q < 27; ++q) o[(int64_t)(q + 1) * n_leaves + l] = z[q];
+            for (int q = 0; q < 27; ++q) o[(int64_t)(q + 1) * L + l] = z[q];
         }
     }
+    return NULL;
+}
+
+/* Leaves are independent: threads take contiguous leaf ranges. */
+void or_bake(const double* coeffs, int64_t n_leaves, const or_params* p,
+             const double* times, int32_t n_t, int32_t n_threads, double* out)
+{
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    if ((int64_t)n_threads > n_leaves) n_threads = (int32_t)(n_leaves > 0 ? n_leaves : 1);
+    pthread_t th[256];
+    or_bake_job jobs[256];
+    for (int32_t w = 0; w < n_threads; ++w) {
+        or_bake_job* j = &jobs[w];
+        j->coeffs = coeffs; j->n_leaves = n_leaves; j->p = p; j->times = times; j->n_t = n_t; j->out = out;
+        j->begin = n_leaves * w / n_threads;
+        j->end = n_leaves * (w + 1) / n_threads;
+    }
+    for (int32_t w = 1; w < n_threads; ++w) pthread_create(&th[w], NULL, or_bake_worker, &jobs[w]);
+    or_bake_worker(&jobs[0]);
+    for (int32_t w = 1; w < n_threads; ++w) pthread_join(th[w], NULL);
 }
 
 /* ------------------------------------------------------------------------ */

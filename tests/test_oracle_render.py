@@ -216,3 +216,24 @@ def test_gradient_matches_central_differences(oracle_lib):
         km = k.copy(); km[l, q] -= h
         fd = (loss(kp) - loss(km)) / (2 * h)
         assert abs(fd - g[l, q]) <= 1e-6 * abs(g[l, q]) + 1e-6 * np.max(np.abs(g)) * h, (l, q, fd, g[l, q])
+
+
+def test_threaded_gradient_and_bake_equal_serial(oracle_lib):
+    """The oracle's gradient sums are formed in ray order whatever the thread
+    count (bit-identical), and the threaded bake equals the serial one."""
+    dijk = synth.random_tree_leaves(21, 6, p_split=0.6)
+    k = _coeffs(len(dijk), seed=21)
+    tree = oracle_lib.OracleTree(dijk, 6)
+    o, d = synth.random_rays(5000, seed=21)
+    o = o.astype(np.float64); d = d.astype(np.float64)
+    times = [3.0, 41.5]
+    t_idx = (np.arange(len(o)) % 2).astype(np.int32)
+    g = np.random.default_rng(21).standard_normal((len(o), 3))
+    p = oracle_lib.make_params(stop_T=1e-2, sigma_scale=16.0)
+    g1, c1 = oracle_lib.render_grad(tree, k, p, times, o, d, t_idx, g, n_threads=1)
+    g7, c7 = oracle_lib.render_grad(tree, k, p, times, o, d, t_idx, g, n_threads=7)
+    assert np.abs(g1).max() > 0
+    assert np.array_equal(g1, g7) and np.array_equal(c1, c7)
+    b1 = oracle_lib.bake(k, p, times, n_threads=1)
+    b5 = oracle_lib.bake(k, p, times, n_threads=5)
+    assert np.array_equal(b1, b5)
