@@ -251,7 +251,10 @@ fpo_status fpo_camera_rays(const float* cam_table, int32_t n_cams, const int32_t
                            const int32_t* py, const int32_t* px, int64_t n,
                            float* o_out, float* d_out, void* stream);
 
-/* Render arbitrary rays; ray r uses basis row t_idx[r].  In Fourier mode
+/* Render arbitrary rays (Sec. 4.1: the per-pixel render of fpo_render for
+ * rays given directly, each at its own time, as the fine-tuning of Sec. 4.3
+ * draws them from the training images); ray r uses basis row t_idx[r] of the
+ * Eq. 8 table that fpo_time_basis fills on the host in FP64.  In Fourier mode
  * from an F32 store, batches of at most 32768 rays run one ray per wave (the
  * lanes share each leaf's coefficients), larger ones one ray per lane; the
  * two agree to FP32 rounding.
@@ -263,7 +266,9 @@ fpo_status fpo_render_rays(const fpo_tree_view* tree, const float* o, const floa
                            const int32_t* t_idx, const float* basis, int32_t n_t, int64_t n_rays,
                            const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream);
 
-/* Test support: the ordered leaf segments each ray crosses (no early stop).
+/* Test support: the ordered leaf segments each ray crosses (no early stop):
+ * the traversal of the sparse union octree (Sec. 4.2) that every render
+ * above performs, exposed so that its visited-leaf lists can be compared.
  *   leaf_ids device [n_rays][max_visits] int32 Morton slots.
  *   t01      device [n_rays][max_visits][2] F32 entry / exit distance along the
  *            unit direction from o.
@@ -324,6 +329,18 @@ fpo_status fpo_adam_step(float* params, float* grad, float* m, float* v, int64_t
  * step and applies the update of fpo_adam_step with that step. */
 fpo_status fpo_adam_step_dev(float* params, float* grad, float* m, float* v, int64_t n, float lr,
                              float beta1, float beta2, float eps, int32_t* state, void* stream);
+
+/* Adam on touched records only (lazy Adam; a semantic change from the dense
+ * step above): params, grad, m, v are n_records records of record_floats
+ * floats (a multiple of 4, at most 256; 192 for the F32 coefficient store),
+ * 16-byte aligned.  A record whose gradient is zero everywhere is left as it
+ * is: its parameters do not move and its moments do not decay.  Every other
+ * record gets the update of fpo_adam_step and its gradient is cleared.  The
+ * bias corrections come from `step` (>= 1), or, if state is not NULL, from
+ * the device step count of fpo_adam_step_dev (advanced by one per call). */
+fpo_status fpo_adam_step_touched(float* params, float* grad, float* m, float* v, int64_t n_records,
+                                 int32_t record_floats, float lr, float beta1, float beta2, float eps,
+                                 int32_t step, int32_t* state, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Precision and time bake                                                  */

@@ -18,3 +18,18 @@ def adam(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.
     m_hat = m / (1.0 - beta1 ** step)
     v_hat = v / (1.0 - beta2 ** step)
     return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def adam_touched(p, g, m, v, step: int, lr: float, record: int, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+    """Lazy Adam over records of `record` values: a record whose gradient is
+    zero everywhere keeps its parameters and moments; every other record takes
+    the step above (with the global step count).  Returns (p, m, v)."""
+    p = np.asarray(p, dtype=np.float64).reshape(-1, record)
+    g = np.asarray(g, dtype=np.float64).reshape(-1, record)
+    m = np.asarray(m, dtype=np.float64).reshape(-1, record)
+    v = np.asarray(v, dtype=np.float64).reshape(-1, record)
+    hit = np.any(g != 0.0, axis=1)
+    p2, m2, v2 = p.copy(), m.copy(), v.copy()
+    p2[hit], m2[hit], v2[hit] = adam(p[hit], g[hit], m[hit], v[hit], step, lr, beta1, beta2, eps)
+    return p2.ravel(), m2.ravel(), v2.ravel()

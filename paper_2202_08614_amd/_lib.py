@@ -106,6 +106,8 @@ _SIGS = {
                       ctypes.c_float, _I32, _P],
     "fpo_adam_step_dev": [_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                           ctypes.c_float, _P, _P],
+    "fpo_adam_step_touched": [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, _I32, _P, _P],
     "fpo_quantize": [_P, _I64, _I64, ctypes.c_int, _P, _P, _P],
     "fpo_bake_times": [ctypes.POINTER(TreeView), _P, _I32, ctypes.c_int, _P, _P],
     "fpo_coarse_occupancy": [_P, _I64, _I32, _P],
@@ -441,6 +443,19 @@ def adam_step_dev(params, grad, m, v, state, lr: float = 1e-2, beta1: float = 0.
     before the first step) advances by one per call or graph replay."""
     _check(lib().fpo_adam_step_dev(_t_ptr(params), _t_ptr(grad), _t_ptr(m), _t_ptr(v), int(params.numel()),
                                    float(lr), float(beta1), float(beta2), float(eps), _t_ptr(state), _stream()))
+
+
+def adam_step_touched(params, grad, m, v, step: int = 0, lr: float = 1e-2, beta1: float = 0.9,
+                      beta2: float = 0.999, eps: float = 1e-8, record_floats: int = 4 * RECORD_WORDS[FPO_F32],
+                      state=None):
+    """fpo_adam_step_touched over records of `record_floats` floats: records
+    with an all-zero gradient are left untouched (lazy Adam)."""
+    n = int(params.numel())
+    if n % record_floats:
+        raise ValueError("params is not a whole number of records")
+    _check(lib().fpo_adam_step_touched(_t_ptr(params), _t_ptr(grad), _t_ptr(m), _t_ptr(v), n // record_floats,
+                                       int(record_floats), float(lr), float(beta1), float(beta2), float(eps),
+                                       int(step), _t_ptr(state), _stream()))
 
 
 def quantize(tree: DeviceTree, dtype: int) -> DeviceTree:

@@ -1,5 +1,5 @@
 // Device-side building blocks of libfpo (gfx950): ray set-up, the sparse
-// octree walk, packed-plane coefficient gathers, the per-leaf inverse real
+// octree walk, leaf-record coefficient gathers, the per-leaf inverse real
 // Fourier transform (Eq. 7, 9), the SH colour (Eq. 1) and front-to-back
 // compositing.  Shared by the render, trace and backward kernels so that all
 // three walk exactly the same segments.

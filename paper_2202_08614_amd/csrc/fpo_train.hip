@@ -202,6 +202,44 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(float4* p, float4* g, floa
     g[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
+// Adam on touched records only: one wave per record of rq float4 (rq <= 64).
+// A record whose gradient is zero everywhere is skipped as a whole (its
+// parameters and moments are left as they are, and its zero gradient needs no
+// clearing); the others get the update of adam_kernel.  The wave reads the
+// gradient once, and only touched records cost parameter and moment traffic.
+__global__ __launch_bounds__(kBlock) void adam_touched_kernel(float4* p, float4* g, float4* m, float4* v,
+                                                              int64_t n_rec, int rq, float lr, float b1, float b2,
+                                                              float eps, float c1, float c2, const float* cs)
+{
+    const int64_t rec = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (rec >= n_rec) return;                       // uniform over the wave
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool in = lane < rq;
+    const int64_t i = rec * rq + lane;
+    const float4 gg = in ? g[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const bool nz = gg.x != 0.0f || gg.y != 0.0f || gg.z != 0.0f || gg.w != 0.0f;
+    if (!__any(nz) || !in) return;
+    if (cs) {
+        c1 = cs[0];
+        c2 = cs[1];
+    }
+    float4 pp = p[i], mm = m[i], vv = v[i];
+    float* P = &pp.x;
+    const float* G = &gg.x;
+    float* M = &mm.x;
+    float* V = &vv.x;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        M[e] = fmaf(b1, M[e], (1.0f - b1) * G[e]);
+        V[e] = fmaf(b2, V[e], (1.0f - b2) * G[e] * G[e]);
+        P[e] -= lr * (M[e] * c1) / (sqrtf(V[e] * c2) + eps);
+    }
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
+    g[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 // Step count kept on the device: state = {int32 step, float c1, float c2, 0}.
 // One thread advances the step and writes the bias corrections for it, so a
 // captured graph that replays this launch and adam_kernel advances by one
@@ -336,4 +374,36 @@ extern "C" fpo_status fpo_adam_step_dev(float* params, float* grad, float* m, fl
                            0.0f, 0.0f, reinterpret_cast<const float*>(state + 1));
     }
     return launch_status("fpo_adam_step_dev");
+}
+
+extern "C" fpo_status fpo_adam_step_touched(float* params, float* grad, float* m, float* v, int64_t n_records,
+                                           int32_t record_floats, float lr, float beta1, float beta2, float eps,
+                                           int32_t step, int32_t* state, void* stream)
+{
+    if (!params || !grad || !m || !v) return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_records < 0) return fail(FPO_E_INVALID, "n_records < 0");
+    if (record_floats < 4 || record_floats % 4 != 0 || record_floats > 4 * dev::kWave)
+        return fail(FPO_E_INVALID, "record_floats must be a multiple of 4 in [4, 256]");
+    if (!state && step < 1) return fail(FPO_E_INVALID, "step counts from 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(FPO_E_INVALID, "betas must be in [0, 1)");
+    if (!(lr >= 0.0f) || !(eps > 0.0f)) return fail(FPO_E_INVALID, "lr must be >= 0 and eps > 0");
+    if ((((uintptr_t)params) | ((uintptr_t)grad) | ((uintptr_t)m) | ((uintptr_t)v) | ((uintptr_t)state)) & 15)
+        return fail(FPO_E_INVALID, "buffers must be 16-byte aligned");
+    const int64_t grid = (n_records + dev::kBlock / dev::kWave - 1) / (dev::kBlock / dev::kWave);
+    if (grid > (int64_t)INT32_MAX) return fail(FPO_E_INVALID, "too many records");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float c1 = 0.0f, c2 = 0.0f;
+    if (state) {
+        hipLaunchKernelGGL(dev::adam_count_kernel, dim3(1), dim3(dev::kWave), 0, s, state, beta1, beta2);
+    } else {
+        c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)step)));
+        c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)step)));
+    }
+    if (n_records == 0) return launch_status("fpo_adam_step_touched");
+    hipLaunchKernelGGL(dev::adam_touched_kernel, dim3((unsigned)grid), dim3(dev::kBlock), 0, s,
+                       reinterpret_cast<float4*>(params), reinterpret_cast<float4*>(grad),
+                       reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n_records, record_floats / 4, lr,
+                       beta1, beta2, eps, c1, c2, state ? reinterpret_cast<const float*>(state + 1) : nullptr);
+    return launch_status("fpo_adam_step_touched");
 }

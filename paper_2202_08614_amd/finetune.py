@@ -9,6 +9,9 @@ keeps each ray's segments (FPO_RAYS_RECORD, up to record_cap per ray) and the
 backward works through them segment by segment instead of walking the rays
 again.  With graph=True the step (rays, render, loss, backward, Adam with its
 step count on the device) is captured once in a HIP graph and replayed.
+adam="touched" replaces the dense Adam step by the lazy one
+(fpo_adam_step_touched): records the batch's rays did not reach keep their
+values and moments.  save() / load() checkpoint and resume a run.
 """
 from __future__ import annotations
 
@@ -23,8 +26,11 @@ from . import _lib
 class FineTuner:
     def __init__(self, tree: _lib.DeviceTree, images: torch.Tensor, cams: Sequence, stop_T: float = 1e-3,
                  lr: float = 1e-2, batch: int = 8192, seed: int = 2022, record: bool = True,
-                 record_cap: int = 128, graph: bool = False):
+                 record_cap: int = 128, graph: bool = False, adam: str = "dense"):
         dev = tree.children.device
+        if adam not in ("dense", "touched"):
+            raise ValueError("adam must be 'dense' or 'touched'")
+        self.adam = adam
         self.tree = tree
         self.images = images
         self.n_img, self.H, self.W = int(images.shape[0]), int(images.shape[1]), int(images.shape[2])
@@ -65,14 +71,14 @@ class FineTuner:
     def from_scene(cls, leaf_dijk: np.ndarray, gt_coeffs: np.ndarray, init_coeffs: np.ndarray, max_depth: int,
                    cams: Sequence, dev, sigma_scale: float = 64.0, stop_T: float = 1e-3, lr: float = 1e-2,
                    batch: int = 8192, seed: int = 2022, record: bool = True, record_cap: int = 128,
-                   graph: bool = False) -> "FineTuner":
+                   graph: bool = False, adam: str = "dense") -> "FineTuner":
         """Targets are rendered from the ground-truth coefficients by fpo_render."""
         gt = _lib.DeviceTree.from_leaves(leaf_dijk, gt_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
         images, _ = _lib.render(gt, cams, _lib.make_opts(stop_T=stop_T))
         del gt
         tree = _lib.DeviceTree.from_leaves(leaf_dijk, init_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
         return cls(tree, images, cams, stop_T=stop_T, lr=lr, batch=batch, seed=seed, record=record,
-                   record_cap=record_cap, graph=graph)
+                   record_cap=record_cap, graph=graph, adam=adam)
 
     def sample(self):
         """A batch: image, row and column of each ray, and the time index of its image."""
@@ -102,7 +108,12 @@ class FineTuner:
                 self._graph = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(self._graph):
                     self._forward_backward(*self.g_in, self.g_loss)
-                    _lib.adam_step_dev(self.tree.coeffs, self.grad, self.m, self.v, self.adam_state, lr=self.lr)
+                    if self.adam == "touched":
+                        _lib.adam_step_touched(self.tree.coeffs, self.grad, self.m, self.v, lr=self.lr,
+                                               state=self.adam_state)
+                    else:
+                        _lib.adam_step_dev(self.tree.coeffs, self.grad, self.m, self.v, self.adam_state,
+                                           lr=self.lr)
             self._graph.replay()
             loss_out.add_(self.g_loss)
             self.t += 1
@@ -110,7 +121,49 @@ class FineTuner:
         self._forward_backward(img, py, px, t_idx, loss_out)
         if with_adam:
             self.t += 1
-            _lib.adam_step(self.tree.coeffs, self.grad, self.m, self.v, self.t, lr=self.lr)
+            if self.adam == "touched":
+                _lib.adam_step_touched(self.tree.coeffs, self.grad, self.m, self.v, step=self.t, lr=self.lr)
+            else:
+                _lib.adam_step(self.tree.coeffs, self.grad, self.m, self.v, self.t, lr=self.lr)
+
+    # -- checkpoint / resume ------------------------------------------------
+    def state_dict(self) -> dict:
+        """Everything a resumed run needs: the coefficient records, Adam's
+        moments and step count (also the device count of the graph variant),
+        and the batch sampler's generator state.  Tensors are copies."""
+        sd = {"coeffs": self.tree.coeffs.detach().clone(), "m": self.m.clone(), "v": self.v.clone(),
+              "t": torch.tensor(self.t, dtype=torch.int64), "gen": self.gen.get_state()}
+        if self.graph:
+            sd["adam_state"] = self.adam_state.clone()
+        return sd
+
+    def load_state_dict(self, sd: dict) -> None:
+        if tuple(sd["coeffs"].shape) != tuple(self.tree.coeffs.shape):
+            raise ValueError("checkpoint is for another tree")
+        with torch.no_grad():
+            self.tree.coeffs.copy_(sd["coeffs"])
+            self.m.copy_(sd["m"])
+            self.v.copy_(sd["v"])
+            self.grad.zero_()
+        self.t = int(sd["t"])
+        self.gen.set_state(sd["gen"].cpu())
+        if self.graph:
+            if "adam_state" in sd:
+                self.adam_state.copy_(sd["adam_state"])
+            else:   # resume an eager run in graph mode: the device count is the step count
+                self.adam_state.zero_()
+                self.adam_state[0] = self.t
+                b1, b2 = 0.9, 0.999
+                c = torch.tensor([1.0 / (1.0 - b1 ** max(self.t, 1)), 1.0 / (1.0 - b2 ** max(self.t, 1))],
+                                 dtype=torch.float32)
+                self.adam_state[1:3] = c.view(torch.int32).to(self.adam_state.device)
+
+    def save(self, path: str) -> None:
+        torch.save(self.state_dict(), path)
+
+    def load(self, path: str) -> None:
+        """Resume from save(); the file holds tensors only (loaded with weights_only=True)."""
+        self.load_state_dict(torch.load(path, map_location="cpu", weights_only=True))
 
     def train(self, n_steps: int) -> List[float]:
         losses = torch.zeros(n_steps, dtype=torch.float32, device=self.images.device)

@@ -206,6 +206,49 @@ def test_adam_kernel_matches_reference(dev):
         assert ratio[k] <= 1.0, (step, k, float(mg[k]), float(mq[k]), float(g0[k]), float(scale[k]))
 
 
+@pytest.mark.parametrize("device_step", [False, True])
+def test_adam_touched_matches_reference(dev, device_step):
+    """fpo_adam_step_touched against the lazy-Adam reference: records of 192
+    floats, a third of them with an all-zero gradient each step (one record
+    zero but for its last value); untouched records keep parameters and
+    moments bit for bit, touched ones follow Adam with the global step."""
+    import torch
+    from oracle.optim import adam_touched
+    rng = np.random.default_rng(6)
+    n_rec, rec = 3001, 192
+    n = n_rec * rec
+    p0 = rng.standard_normal(n).astype(np.float32)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    p, m, v = to(p0), torch.zeros(n, device=dev), torch.zeros(n, device=dev)
+    state = torch.zeros(4, dtype=torch.int32, device=dev) if device_step else None
+    q, mq, vq = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    scale = np.zeros(n)          # moving average of |g|: bounds the magnitude of every term in m
+    f32 = lambda x: float(np.float32(x))
+    note(f"fpo_adam_step_touched device_step={device_step}")
+    for step in range(1, 5):
+        g0 = (rng.standard_normal((n_rec, rec)) * 10.0 ** rng.integers(-3, 1, (n_rec, 1))).astype(np.float32)
+        g0[rng.random(n_rec) < 1 / 3] = 0.0
+        g0[7] = 0.0
+        g0[7, rec - 1] = 0.25
+        p_before, m_before, v_before = p.clone(), m.clone(), v.clone()
+        g = to(g0.ravel())
+        _lib.adam_step_touched(p, g, m, v, step=0 if device_step else step, lr=1e-2, state=state)
+        q, mq, vq = adam_touched(q, g0.ravel(), mq, vq, step, f32(1e-2), rec, f32(0.9), f32(0.999), f32(1e-8))
+        hit = np.repeat(np.any(g0 != 0, axis=1), rec)
+        scale[hit] = 0.9 * scale[hit] + 0.1 * np.abs(g0.ravel()[hit].astype(np.float64))
+        torch.cuda.synchronize()
+        assert float(g.abs().max()) == 0.0
+        untouched = torch.from_numpy(~np.any(g0 != 0, axis=1)).to(dev).repeat_interleave(rec)
+        assert untouched.any() and not untouched.all()
+        for now, before in ((p, p_before), (m, m_before), (v, v_before)):
+            assert torch.equal(now[untouched], before[untouched])
+        assert np.allclose(p.cpu().numpy(), q, rtol=1e-5, atol=1e-6)
+        # two FP32 roundings per step, accumulated over the steps so far
+        assert np.all(np.abs(m.cpu().numpy() - mq) <= 2 * step * 2.0 ** -23 * scale + 1e-30)
+        if device_step:
+            assert int(state[0]) == step
+
+
 def test_finetune_converges(dev):
     """A small fine-tune: targets rendered from a ground-truth tree, start from
     GT + N(0, 0.05) noise, 8192-ray batches, L2 loss, Adam; the loss falls."""
@@ -237,11 +280,18 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev, c4):
     8192-ray batch drawn over its 24 cameras x 30 times at 800x800 (the
     benchmark's batch); forward colours and the gradient of every coefficient
     against the FP64 oracle.  Colours go through the parity check (ties
-    exempt by their FP64 spread under a 2e-7 sideways shift).  The gradient
-    bar holds for every coefficient except those of leaves that an exempt ray
-    (a tie, or a ray whose early termination straddles the threshold, where
-    the two sides may stop after different segments) crosses, itself or
-    shifted sideways by 1e-6."""
+    exempt by their FP64 spread under a 2e-7 sideways shift, the placement
+    error of an FP32 camera ray).  The gradient gets the same rule per
+    coefficient: its FP64 spread is the largest change of the oracle's
+    gradient when every ray of the batch moves sideways by 2e-7; a
+    coefficient whose spread exceeds the bar is a tie and must stay within
+    its spread at 1e-6 plus the bar.  Leaves crossed by a ray whose early
+    termination straddles the threshold (the two sides may stop after
+    different segments) and density coefficients of leaves whose density sum
+    sits at the ReLU kink within FP32 rounding are exempt too; together the
+    exempt coefficients are at most 1% of the nonzero ones (about 0.3% here:
+    a 2e-7 shift moves the segment lengths of grazing crossings by more than
+    the 1e-3 relative gradient bar, while the colours barely move)."""
     import torch
     sc, tree = c4
     cams = sc.cameras
@@ -260,25 +310,53 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev, c4):
     rec = _lib.make_opts(stop_T=1e-3, flags=_lib.FPO_RAYS_RECORD, workspace=ws)
     ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
     p = oracle_lib.make_params(stop_T=1e-3)
-    want, rgb_ref = oracle_lib.render_grad(ot, sc.coeffs, p, times, o, d, t_idx, g_rgb.astype(np.float64))
+    g64 = g_rgb.astype(np.float64)
+    want, rgb_ref = oracle_lib.render_grad(ot, sc.coeffs, p, times, o, d, t_idx, g64)
     ref = conditioned_reference(oracle_lib, ot, sc.coeffs, oracle_lib.make_params(stop_T=1e-3, band=1e-3), times,
                                 o, d, t_idx)
     gmax = np.abs(want).max()
     assert gmax > 0 and (np.abs(want) > 1e-3 * gmax).sum() > 10000
-    # exempt rays and the coefficients they reach
-    straddle = np.abs(ref["rgb"][:, 0] - ref["rgb"][:, 1]).max(axis=1) > 0
-    ill = ref["spread"] > 1e-4
-    exempt_rays = np.nonzero(straddle | ill)[0]
-    assert len(exempt_rays) <= 0.01 * 8192, len(exempt_rays)
+    bar = 1e-3 * np.abs(want) + 1e-5 * gmax
+    # the gradient's FP64 spread under sideways shifts of every ray
     u, v = perpendicular_pair(d)
+    gspread = {}
+    for eps in (2e-7, 1e-6):
+        sp = np.zeros_like(want)
+        for sgn, w in ((1.0, u), (-1.0, u), (1.0, v), (-1.0, v)):
+            alt, _ = oracle_lib.render_grad(ot, sc.coeffs, p, times, o + sgn * eps * w, d, t_idx, g64)
+            sp = np.maximum(sp, np.abs(alt - want))
+        gspread[eps] = sp
+    tie = gspread[2e-7] > bar
+    # leaves of rays whose early termination straddles the threshold within the FP32 accuracy of
+    # the transmittance (a relative 1e-4: some 10 segments of FP32 exp and optical depth)
+    near = oracle_lib.render_rays(ot, sc.coeffs, oracle_lib.make_params(stop_T=1e-3, band=1e-4), times, o, d,
+                                  t_idx, n_threads=8)["rgb"]
+    straddle = np.nonzero(np.abs(near[:, 0] - near[:, 1]).max(axis=1) > 0)[0]
     touched = set()
-    for r in exempt_rays:
-        for shift in (0.0 * u[r], 1e-6 * u[r], -1e-6 * u[r], 1e-6 * v[r], -1e-6 * v[r]):
-            leaves, _, _ = ot.trace(o[r] + shift, d[r])
-            touched.update(int(x) for x in leaves)
-    exempt_coeffs = np.zeros(want.shape, dtype=bool)
+    for r in straddle:
+        touched.update(int(x) for x in ot.trace(o[r], d[r])[0])
+    exempt = tie.copy()
     if touched:
-        exempt_coeffs[np.array(sorted(touched))] = True
+        exempt[np.array(sorted(touched))] = True
+    # ReLU kinks: where a crossed leaf's density sum sigma_raw(t) lies within FP32 rounding of 0
+    # (|sigma_raw| <= 2^-18 sum_i |k_i b_i|, four times the 31-term bound), FP32 and FP64 may
+    # take different sides of the ReLU and the derivative of the density coefficients jumps by
+    # s b_i dL/dsigma (the derivative at the kink is 0); the colour is continuous there
+    kink = set()
+    B = np.stack([oracle_lib.basis(t, 60.0, 31) for t in times])
+    for ti in range(len(times)):
+        leaves = set()
+        for r in np.nonzero(t_idx == ti)[0]:
+            leaves.update(int(x) for x in ot.trace(o[r], d[r])[0])
+        if not leaves:
+            continue
+        lv = np.array(sorted(leaves), np.int64)
+        sraw = sc.coeffs[lv, :31].astype(np.float64) @ B[ti]
+        mag = np.abs(sc.coeffs[lv, :31].astype(np.float64)) @ np.abs(B[ti])
+        kink.update(int(x) for x in lv[np.abs(sraw) <= 2.0 ** -18 * mag])
+    if kink:
+        exempt[np.array(sorted(kink)), :31] = True
+    assert exempt.sum() <= 1e-2 * (want != 0).sum(), (int(exempt.sum()), int((want != 0).sum()))
     # the plain backward (rays walked again) and the one from segment records (as the fine-tune runs)
     for name, opts in (("plain", plain), ("recorded", rec)):
         note(f"c4 render_rays + render_backward ({name}) 8192 rays, 500k leaves")
@@ -290,11 +368,12 @@ def test_c4_batch_gradient_matches_oracle(oracle_lib, dev, c4):
         torch.cuda.synchronize()
         got = _unpack(grad.cpu().numpy(), tree.perm, sc.n_leaves)
         check_parity(rgb.cpu().numpy(), ref)
-        bad = np.abs(got - want) > 1e-3 * np.abs(want) + 1e-5 * gmax
-        assert not (bad & ~exempt_coeffs).any(), (name, int((bad & ~exempt_coeffs).sum()),
-                                                  np.abs(got - want)[~exempt_coeffs].max(), gmax)
-        print(f"[c4 {name}] exempt rays {len(exempt_rays)} ({int(straddle.sum())} straddle, {int(ill.sum())} ties), "
-              f"exempt leaves {len(touched)}, coefficients off the bar {int(bad.sum())}")
+        err = np.abs(got - want)
+        bad = err > bar
+        assert not (bad & ~exempt).any(), (name, int((bad & ~exempt).sum()), err[~exempt].max(), gmax)
+        assert not (tie & (err > gspread[1e-6] + bar)).any(), (name, "a tie coefficient beyond its 1e-6 spread")
+        print(f"[c4 {name}] gradient ties {int(tie.sum())} coefficients, straddle rays {len(straddle)} "
+              f"({len(touched)} leaves), ReLU-kink leaves {len(kink)}; off the bar {int(bad.sum())}, all exempt")
     assert (_lib.record_counts(ws, 8192) >= 0).all()
 
 
@@ -427,3 +506,52 @@ def test_finetune_graph_replays_match_eager_steps(dev):
         assert int(steady.sum()) > 1000
         assert torch.allclose(fe.tree.coeffs[steady], fg.tree.coeffs[steady], rtol=1e-5, atol=1e-5)
     assert torch.allclose(le, lg, rtol=1e-4)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_finetune_checkpoint_resume(dev, tmp_path, graph):
+    """N steps in one run equal N/2 steps, save, a fresh fine-tuner loading the
+    file, and N/2 more: the coefficients and Adam's moments agree (up to the
+    order of the backward's FP32 atomic additions), the step count and the
+    batch sampler continue where they stopped."""
+    import torch
+    from paper_2202_08614_amd.finetune import FineTuner
+    dijk = synth.blob_leaves(6, 6000, n_frames=8)
+    gt = synth.gaussian_coeffs(len(dijk), seed=1)
+    init = synth.perturb_coeffs(gt, 0.05, seed=2)
+    cams = [synth.ring_camera(2 * np.pi * k / 6, 0.26, 1.5, 30.0, 96, 96, t) for t in (1.0, 31.0) for k in range(6)]
+    note(f"fine-tune checkpoint/resume graph={graph}")
+    n = 6
+    full = FineTuner.from_scene(dijk, gt, init, 6, cams, dev, batch=4096, seed=3, graph=graph)
+    lf = torch.zeros(n, device=dev)
+    for k in range(n):
+        b = full.sample()
+        full.step(*b[:3], lf[k:k + 1], t_idx=b[3])
+    first = FineTuner.from_scene(dijk, gt, init, 6, cams, dev, batch=4096, seed=3, graph=graph)
+    lh = torch.zeros(n, device=dev)
+    for k in range(n // 2):
+        b = first.sample()
+        first.step(*b[:3], lh[k:k + 1], t_idx=b[3])
+    path = str(tmp_path / "ft.pt")
+    first.save(path)
+    del first
+    second = FineTuner.from_scene(dijk, gt, gt, 6, cams, dev, batch=4096, seed=99, graph=graph)   # other state
+    second.load(path)
+    assert second.t == n // 2
+    for k in range(n // 2, n):
+        b = second.sample()
+        second.step(*b[:3], lh[k:k + 1], t_idx=b[3])
+    torch.cuda.synchronize()
+    assert second.t == n
+    if graph:
+        assert int(second.adam_state[0]) == n and int(full.adam_state[0]) == n
+    for a, b_ in ((full.m, second.m), (full.v, second.v)):
+        scale = float(a.abs().max())
+        assert scale > 0 and float((a - b_).abs().max()) <= 1e-4 * scale
+    steady = full.m.abs() > 1e-3 * float(full.m.abs().max())
+    assert int(steady.sum()) > 1000
+    assert torch.allclose(full.tree.coeffs[steady], second.tree.coeffs[steady], rtol=1e-5, atol=1e-5)
+    assert torch.allclose(lf, lh, rtol=1e-4)
+    # the sampler continues identically
+    nb_f, nb_s = full.sample(), second.sample()
+    assert all(torch.equal(x, y) for x, y in zip(nb_f, nb_s))
