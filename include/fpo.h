@@ -40,7 +40,17 @@
  * - Errors: every call returns fpo_status.  On FPO_E_INVALID or
  *   FPO_E_UNSUPPORTED nothing is launched and outputs are untouched.
  *   FPO_E_DEVICE reports a HIP launch error.  fpo_last_error() returns a
- *   message for the last non-OK status on the calling thread.
+ *   message for the last non-OK status on the calling thread.  Host calls
+ *   that allocate host memory (fpo_build_tree, fpo_union_leaves,
+ *   fpo_coarse_occupancy) return FPO_E_NOMEM when an allocation fails.
+ * - Tracing: every call is a roctx range named after it (visible to
+ *   rocprofv3 --marker-trace; free when no tool is attached).
+ * - Debug switches (environment, read at each call):
+ *   FPO_FAULT=alloc makes the host calls above fail their first allocation
+ *   (FPO_E_NOMEM), to exercise callers' error paths;
+ *   FPO_FORCE_FALLBACK=1 makes fpo_render and fpo_render_noalloc ignore the
+ *   skip flags and walk every whole chord (plain traversal), which must give
+ *   the image of the skip modes.
  */
 #ifndef FPO_H
 #define FPO_H
@@ -56,7 +66,8 @@ typedef enum {
     FPO_E_INVALID = 1,      /* bad argument; nothing launched */
     FPO_E_UNSUPPORTED = 2,  /* valid but not compiled in (e.g. another layout) */
     FPO_E_DEVICE = 3,       /* HIP runtime error */
-    FPO_E_CAPACITY = 4      /* caller-provided capacity too small */
+    FPO_E_CAPACITY = 4,     /* caller-provided capacity too small */
+    FPO_E_NOMEM = 5         /* a host call could not allocate host memory */
 } fpo_status;
 
 typedef enum { FPO_F32 = 0, FPO_BF16 = 1, FPO_FP8_E4M3 = 2 } fpo_dtype;

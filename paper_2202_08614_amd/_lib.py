@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfpo.so")
 
-FPO_OK, FPO_E_INVALID, FPO_E_UNSUPPORTED, FPO_E_DEVICE, FPO_E_CAPACITY = range(5)
+FPO_OK, FPO_E_INVALID, FPO_E_UNSUPPORTED, FPO_E_DEVICE, FPO_E_CAPACITY, FPO_E_NOMEM = range(6)
 FPO_F32, FPO_BF16, FPO_FP8_E4M3 = 0, 1, 2
 N_SIGMA, N_SH_FOURIER, SH_DEGREE, N_SH = 31, 5, 2, 9
 N_COEFF = 166

@@ -473,6 +473,7 @@ static constexpr int32_t kMfmaMinTimes = 4;
 extern "C" fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride, fpo_dtype dtype,
                                    void* q_out, float* scale_out, void* stream)
 {
+    ApiRange api_range_("fpo_quantize");
     if (!coeffs || !q_out || !scale_out) return fail(FPO_E_INVALID, "NULL device pointer");
     if (dtype != FPO_BF16 && dtype != FPO_FP8_E4M3) return fail(FPO_E_INVALID, "dtype must be BF16 or FP8_E4M3");
     if (n_leaves < 1 || leaf_stride < n_leaves) return fail(FPO_E_INVALID, "bad n_leaves / leaf_stride");
@@ -493,6 +494,7 @@ extern "C" fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_
 extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t,
                                      fpo_dtype out_dtype, void* out, void* stream)
 {
+    ApiRange api_range_("fpo_bake_times");
     fpo_status st = check_tree(tree, true, true);
     if (st != FPO_OK) return st;
     if (!basis || !out) return fail(FPO_E_INVALID, "NULL device pointer");

@@ -213,6 +213,7 @@ extern "C" fpo_status fpo_frame_values(const fpo_tree_view* frame_tree, const in
                                        const float* frame_values, const int32_t* union_cells, int64_t n_union,
                                        float* out, int32_t* n_bad, void* stream)
 {
+    ApiRange api_range_("fpo_frame_values");
     fpo_status st = check_tree(frame_tree, false);
     if (st != FPO_OK) return st;
     if (n_union < 0) return fail(FPO_E_INVALID, "n_union < 0");
@@ -230,6 +231,7 @@ extern "C" fpo_status fpo_frame_values(const fpo_tree_view* frame_tree, const in
 extern "C" fpo_status fpo_dft_frames(const float* frames, int32_t n_frames, int64_t n_leaves, int64_t leaf_stride,
                                      int32_t literal, float* coeffs_out, float* sigma_max_out, void* stream)
 {
+    ApiRange api_range_("fpo_dft_frames");
     if (!frames || !coeffs_out) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_frames < 1 || n_frames > FPO_MAX_FRAMES) return fail(FPO_E_INVALID, "n_frames must be in 1..FPO_MAX_FRAMES");
     if (n_leaves < 0 || leaf_stride < n_leaves) return fail(FPO_E_INVALID, "need 0 <= n_leaves <= leaf_stride");

@@ -211,6 +211,7 @@ using namespace fpo;
 extern "C" fpo_status fpo_fusion_observe(const fpo_tree_view* tree, const float* values, const fpo_camera* cam,
                                          const fpo_field* field, float tau, float* acc, void* stream)
 {
+    ApiRange api_range_("fpo_fusion_observe");
     fpo_status st = check_tree(tree, false, true);
     if (st != FPO_OK) return st;
     if (!values || !acc) return fail(FPO_E_INVALID, "NULL device pointer");
@@ -249,6 +250,7 @@ extern "C" fpo_status fpo_fusion_observe(const fpo_tree_view* tree, const float*
 extern "C" fpo_status fpo_fusion_apply(float* values, float* weight, int32_t* count, float* acc, int64_t n_leaves,
                                        void* stream)
 {
+    ApiRange api_range_("fpo_fusion_apply");
     if (n_leaves < 0) return fail(FPO_E_INVALID, "n_leaves < 0");
     if (n_leaves == 0) return FPO_OK;
     if (!values || !weight || !count || !acc) return fail(FPO_E_INVALID, "NULL device pointer");

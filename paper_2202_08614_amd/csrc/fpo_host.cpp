@@ -1,10 +1,13 @@
 // Host side of libfpo: error reporting, octree construction, the FP64 time
 // basis and camera packing.  No device work happens here.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <new>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -23,6 +26,21 @@ fpo_status fail(fpo_status st, const std::string& msg)
 }
 
 fpo_status ok() { return FPO_OK; }
+
+ApiRange::ApiRange(const char* name) { roctxRangePushA(name); }
+ApiRange::~ApiRange() { roctxRangePop(); }
+
+void fault_point_alloc()
+{
+    const char* f = std::getenv("FPO_FAULT");
+    if (f && std::strcmp(f, "alloc") == 0) throw std::bad_alloc();
+}
+
+bool force_fallback()
+{
+    const char* f = std::getenv("FPO_FORCE_FALLBACK");
+    return f && f[0] == '1' && f[1] == '\0';
+}
 
 fpo_status launch_status(const char* what)
 {
@@ -173,12 +191,14 @@ extern "C" fpo_status fpo_build_tree(const int32_t* leaf_dijk, int64_t n_leaves,
                                      int32_t* children_out, int64_t cap_nodes, int64_t* n_nodes_out,
                                      int64_t* perm_out)
 {
+    ApiRange api_range_("fpo_build_tree");
     try {
         if (!leaf_dijk) return fail(FPO_E_INVALID, "leaf_dijk is NULL");
         if (!n_nodes_out) return fail(FPO_E_INVALID, "n_nodes_out is NULL");
         if (n_leaves < 1 || n_leaves > INT32_MAX - 1) return fail(FPO_E_INVALID, "n_leaves out of range");
         if (max_depth < 1 || max_depth > FPO_MAX_DEPTH) return fail(FPO_E_INVALID, "max_depth must be in 1..10");
         const int D = max_depth;
+        fault_point_alloc();
         std::vector<uint64_t> code(n_leaves);   // Morton code of the leaf's min corner on the finest lattice
         for (int64_t l = 0; l < n_leaves; ++l) {
             const int32_t d = leaf_dijk[4 * l], i = leaf_dijk[4 * l + 1], j = leaf_dijk[4 * l + 2],
@@ -248,7 +268,7 @@ extern "C" fpo_status fpo_build_tree(const int32_t* leaf_dijk, int64_t n_leaves,
         }
         return FPO_OK;
     } catch (const std::bad_alloc&) {
-        return fail(FPO_E_INVALID, "out of host memory");
+        return fail(FPO_E_NOMEM, "out of host memory");
     }
 }
 
@@ -295,11 +315,13 @@ uint64_t compact3(uint64_t v)
 extern "C" fpo_status fpo_union_leaves(const int32_t* leaf_dijk, int64_t n_cells, int32_t max_depth,
                                        int32_t* union_out, int64_t cap, int64_t* n_union_out)
 {
+    ApiRange api_range_("fpo_union_leaves");
     try {
         if (!leaf_dijk || !n_union_out) return fail(FPO_E_INVALID, "NULL argument");
         if (n_cells < 1) return fail(FPO_E_INVALID, "n_cells must be >= 1");
         if (max_depth < 1 || max_depth > FPO_MAX_DEPTH) return fail(FPO_E_INVALID, "max_depth must be in 1..10");
         const int D = max_depth;
+        fault_point_alloc();
         std::vector<Cell> cs((size_t)n_cells);
         for (int64_t l = 0; l < n_cells; ++l) {
             const int32_t d = leaf_dijk[4 * l], i = leaf_dijk[4 * l + 1], j = leaf_dijk[4 * l + 2],
@@ -328,13 +350,14 @@ extern "C" fpo_status fpo_union_leaves(const int32_t* leaf_dijk, int64_t n_cells
         }
         return FPO_OK;
     } catch (const std::bad_alloc&) {
-        return fail(FPO_E_INVALID, "out of host memory");
+        return fail(FPO_E_NOMEM, "out of host memory");
     }
 }
 
 extern "C" fpo_status fpo_prune_leaves(const float* sigma_max, int64_t n_leaves, float threshold, int64_t* keep_out,
                                        int64_t* n_keep_out)
 {
+    ApiRange api_range_("fpo_prune_leaves");
     if (!sigma_max || !keep_out || !n_keep_out) return fail(FPO_E_INVALID, "NULL argument");
     if (n_leaves < 0) return fail(FPO_E_INVALID, "n_leaves < 0");
     if (!std::isfinite(threshold)) return fail(FPO_E_INVALID, "threshold must be finite");
@@ -348,6 +371,7 @@ extern "C" fpo_status fpo_prune_leaves(const float* sigma_max, int64_t n_leaves,
 extern "C" fpo_status fpo_coarse_occupancy(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
                                            uint32_t* bits_out)
 {
+    ApiRange api_range_("fpo_coarse_occupancy");
     if (!leaf_dijk || !bits_out) return fail(FPO_E_INVALID, "NULL argument");
     if (n_leaves < 1) return fail(FPO_E_INVALID, "n_leaves must be >= 1");
     if (max_depth < 1 || max_depth > FPO_MAX_DEPTH) return fail(FPO_E_INVALID, "max_depth must be in 1..10");
@@ -361,7 +385,13 @@ extern "C" fpo_status fpo_coarse_occupancy(const int32_t* leaf_dijk, int64_t n_l
             if (leaf_dijk[4 * l + a] < 0 || leaf_dijk[4 * l + a] >= g)
                 return fail(FPO_E_INVALID, "leaf " + std::to_string(l) + ": coordinate out of range");
     }
-    std::vector<uint8_t> occ((size_t)N * N * N, 0);
+    std::vector<uint8_t> occ;
+    try {
+        fault_point_alloc();
+        occ.assign((size_t)N * N * N, 0);
+    } catch (const std::bad_alloc&) {
+        return fail(FPO_E_NOMEM, "out of host memory");
+    }
     for (int64_t l = 0; l < n_leaves; ++l) {
         const int d = leaf_dijk[4 * l];
         int lo[3], hi[3];
@@ -400,6 +430,7 @@ extern "C" fpo_status fpo_coarse_occupancy(const int32_t* leaf_dijk, int64_t n_l
 
 extern "C" fpo_status fpo_time_basis(const double* times, int32_t n_t, const fpo_layout* layout, float* basis_out)
 {
+    ApiRange api_range_("fpo_time_basis");
     if (!times || !layout || !basis_out) return fail(FPO_E_INVALID, "NULL argument");
     if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
     if (layout->n_sigma < 1 || layout->n_sigma > FPO_BASIS_STRIDE || layout->n_sh_fourier > layout->n_sigma)
@@ -414,6 +445,7 @@ extern "C" fpo_status fpo_time_basis(const double* times, int32_t n_t, const fpo
 
 extern "C" fpo_status fpo_camera_pack(const fpo_camera* cams, int32_t n_cams, float* table_out)
 {
+    ApiRange api_range_("fpo_camera_pack");
     if (!cams || !table_out) return fail(FPO_E_INVALID, "NULL argument");
     if (n_cams < 1) return fail(FPO_E_INVALID, "n_cams must be >= 1");
     for (int32_t c = 0; c < n_cams; ++c) {

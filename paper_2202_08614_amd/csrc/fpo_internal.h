@@ -67,4 +67,18 @@ void basis_row(double t, double period, int n, float* out);
 // FPO_E_DEVICE with the HIP error string if the last launch failed, else FPO_OK.
 fpo_status launch_status(const char* what);
 
+// A roctx range around one library call (push on construction, pop on
+// destruction), so that a profiler's marker trace shows each call.
+struct ApiRange {
+    explicit ApiRange(const char* name);
+    ~ApiRange();
+    ApiRange(const ApiRange&) = delete;
+    ApiRange& operator=(const ApiRange&) = delete;
+};
+
+// Debug switches from the environment: FPO_FAULT=alloc (host allocations
+// fail: throws std::bad_alloc) and FPO_FORCE_FALLBACK=1 (skip flags ignored).
+void fault_point_alloc();
+bool force_fallback();
+
 }  // namespace fpo

@@ -430,6 +430,7 @@ static int64_t mlp_splits(int64_t n) { return (mlp_ld(n) + dev::kSplit - 1) / de
 
 extern "C" int64_t fpo_mlp_workspace_floats(int64_t n)
 {
+    ApiRange api_range_("fpo_mlp_workspace_floats");
     if (n < 1) return 0;
     return (int64_t)dev::kRows * mlp_ld(n) + mlp_splits(n) * dev::kParamsPad;
 }
@@ -444,6 +445,7 @@ extern "C" fpo_status fpo_ray_labels(const fpo_tree_view* tree, const float* o, 
                                      const float* basis, const float* tau, int32_t n_t, int64_t n_rays,
                                      const fpo_render_opts* opts, float* labels, float* inputs, void* stream)
 {
+    ApiRange api_range_("fpo_ray_labels");
     fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr);
     if (st != FPO_OK) return st;
     if ((st = check_opts(opts, tree)) != FPO_OK) return st;
@@ -477,6 +479,7 @@ extern "C" fpo_status fpo_ray_labels(const fpo_tree_view* tree, const float* o, 
 
 extern "C" fpo_status fpo_mlp_forward(const float* params, const float* inputs, int64_t n, float* out, void* stream)
 {
+    ApiRange api_range_("fpo_mlp_forward");
     if (n < 0) return fail(FPO_E_INVALID, "n < 0");
     if (n == 0) return FPO_OK;
     if (!params || !inputs || !out) return fail(FPO_E_INVALID, "NULL device pointer");
@@ -491,6 +494,7 @@ extern "C" fpo_status fpo_mlp_loss_grad(const float* params, const float* inputs
                                         const int32_t* idx, int64_t n, float* workspace, float* grad, float* loss,
                                         void* stream)
 {
+    ApiRange api_range_("fpo_mlp_loss_grad");
     if (n < 1) return fail(FPO_E_INVALID, "n must be >= 1");
     if (!params || !inputs || !labels || !workspace || !grad || !loss) return fail(FPO_E_INVALID, "NULL device pointer");
     if ((reinterpret_cast<uintptr_t>(workspace) & 15) != 0) return fail(FPO_E_INVALID, "workspace must be 16-byte aligned");
@@ -514,6 +518,7 @@ extern "C" fpo_status fpo_mlp_loss_grad(const float* params, const float* inputs
 
 extern "C" fpo_status fpo_mlp_pack(const float* params, void* packed_out, void* stream)
 {
+    ApiRange api_range_("fpo_mlp_pack");
     if (!params || !packed_out) return fail(FPO_E_INVALID, "NULL device pointer");
     if ((reinterpret_cast<uintptr_t>(packed_out) & 15) != 0) return fail(FPO_E_INVALID, "packed_out must be 16-byte aligned");
     const int n = dev::kFrags * 64 + 132;
@@ -524,6 +529,7 @@ extern "C" fpo_status fpo_mlp_pack(const float* params, void* packed_out, void* 
 
 extern "C" fpo_status fpo_mlp_infer(const void* packed, const float* inputs, int64_t n, float* out, void* stream)
 {
+    ApiRange api_range_("fpo_mlp_infer");
     if (n < 0) return fail(FPO_E_INVALID, "n < 0");
     if (n == 0) return FPO_OK;
     if (!packed || !inputs || !out) return fail(FPO_E_INVALID, "NULL device pointer");

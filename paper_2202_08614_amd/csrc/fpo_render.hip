@@ -442,7 +442,7 @@ static fpo_status render_impl(const fpo_tree_view* tree, const fpo_camera* cams,
         if (cams[i].width != W || cams[i].height != H)
             return fail(FPO_E_INVALID, "all cameras of one call must share width and height");
     if ((int64_t)W * H > (1ll << 30)) return fail(FPO_E_INVALID, "image too large");
-    const int skip = opts->flags;
+    const int skip = force_fallback() ? 0 : opts->flags;     // FPO_FORCE_FALLBACK=1: plain traversal
     const int per_launch = std::max(1, std::min(cams_per_launch, dev::kCamsPerLaunch));
     if (skip != 0) {
         const int64_t need = (int64_t)std::min(n_cams, per_launch) * W * H * 8;
@@ -545,6 +545,7 @@ static fpo_status render_impl(const fpo_tree_view* tree, const fpo_camera* cams,
 extern "C" fpo_status fpo_render(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
                                  const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
 {
+    ApiRange api_range_("fpo_render");
     return render_impl(tree, cams, n_cams, opts, rgb_out, T_out, stream, dev::kCamsPerLaunch);
 }
 
@@ -589,6 +590,7 @@ static fpo_status scratch_address(void** out)
 extern "C" fpo_status fpo_render_noalloc(const fpo_tree_view* tree, const fpo_camera* cams, int32_t n_cams,
                                          const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
 {
+    ApiRange api_range_("fpo_render_noalloc");
     // every host-side check before the device is touched
     fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr, true);
     if (st != FPO_OK) return st;
@@ -619,6 +621,7 @@ extern "C" fpo_status fpo_render_rays(const fpo_tree_view* tree, const float* o,
                                       const int32_t* t_idx, const float* basis, int32_t n_t, int64_t n_rays,
                                       const fpo_render_opts* opts, float* rgb_out, float* T_out, void* stream)
 {
+    ApiRange api_range_("fpo_render_rays");
     fpo_status st = check_tree(tree, opts == nullptr || opts->snapshot == nullptr);
     if (st != FPO_OK) return st;
     const bool record = opts && opts->flags == FPO_RAYS_RECORD;
@@ -674,6 +677,7 @@ extern "C" fpo_status fpo_trace_rays(const fpo_tree_view* tree, const float* o, 
                                      int32_t max_visits, int32_t* leaf_ids, float* t01, int32_t* n_visits,
                                      void* stream)
 {
+    ApiRange api_range_("fpo_trace_rays");
     fpo_status st = check_tree(tree, false);
     if (st != FPO_OK) return st;
     if (n_rays < 0 || max_visits < 0) return fail(FPO_E_INVALID, "negative size");
@@ -694,6 +698,7 @@ extern "C" fpo_status fpo_camera_rays(const float* cam_table, int32_t n_cams, co
                                       const int32_t* py, const int32_t* px, int64_t n,
                                       float* o_out, float* d_out, void* stream)
 {
+    ApiRange api_range_("fpo_camera_rays");
     if (n < 0) return fail(FPO_E_INVALID, "n < 0");
     if (n == 0) return FPO_OK;
     if (!cam_table || !cam || !py || !px || !o_out || !d_out) return fail(FPO_E_INVALID, "NULL device pointer");
@@ -708,6 +713,7 @@ extern "C" fpo_status fpo_camera_rays(const float* cam_table, int32_t n_cams, co
 extern "C" fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
                                       int64_t leaf_stride, const fpo_layout* layout, float* dst, void* stream)
 {
+    ApiRange api_range_("fpo_pack_coeffs");
     if (!src || !perm || !dst) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_leaves < 1 || leaf_stride < n_leaves) return fail(FPO_E_INVALID, "bad n_leaves / leaf_stride");
     const int n1 = layout ? layout->n_sigma : FPO_N_SIGMA;

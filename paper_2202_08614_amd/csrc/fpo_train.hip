@@ -274,6 +274,7 @@ extern "C" fpo_status fpo_render_backward(const fpo_tree_view* tree, const float
                                           const fpo_render_opts* opts, const float* rgb_fwd,
                                           const float* grad_rgb, float* grad_coeffs, void* stream)
 {
+    ApiRange api_range_("fpo_render_backward");
     fpo_status st = check_tree(tree, true);
     if (st != FPO_OK) return st;
     if ((st = check_opts(opts, tree, false, true)) != FPO_OK) return st;
@@ -315,6 +316,7 @@ extern "C" fpo_status fpo_l2_loss(const float* rgb, const float* images, int32_t
                                   int32_t height, const int32_t* image_idx, const int32_t* py, const int32_t* px,
                                   int64_t n_rays, float* grad_rgb, float* loss, void* stream)
 {
+    ApiRange api_range_("fpo_l2_loss");
     if (n_rays < 0) return fail(FPO_E_INVALID, "n_rays < 0");
     if (n_rays == 0) return FPO_OK;
     if (!rgb || !images || !image_idx || !py || !px || !grad_rgb || !loss)
@@ -331,6 +333,7 @@ extern "C" fpo_status fpo_l2_loss(const float* rgb, const float* images, int32_t
 extern "C" fpo_status fpo_adam_step(float* params, float* grad, float* m, float* v, int64_t n, float lr,
                                     float beta1, float beta2, float eps, int32_t step, void* stream)
 {
+    ApiRange api_range_("fpo_adam_step");
     if (!params || !grad || !m || !v) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n < 0 || n % 4 != 0) return fail(FPO_E_INVALID, "n must be a non-negative multiple of 4");
     if (step < 1) return fail(FPO_E_INVALID, "step counts from 1");
@@ -355,6 +358,7 @@ extern "C" fpo_status fpo_adam_step(float* params, float* grad, float* m, float*
 extern "C" fpo_status fpo_adam_step_dev(float* params, float* grad, float* m, float* v, int64_t n, float lr,
                                         float beta1, float beta2, float eps, int32_t* state, void* stream)
 {
+    ApiRange api_range_("fpo_adam_step_dev");
     if (!params || !grad || !m || !v || !state) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n < 0 || n % 4 != 0) return fail(FPO_E_INVALID, "n must be a non-negative multiple of 4");
     if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
@@ -380,6 +384,7 @@ extern "C" fpo_status fpo_adam_step_touched(float* params, float* grad, float* m
                                            int32_t record_floats, float lr, float beta1, float beta2, float eps,
                                            int32_t step, int32_t* state, void* stream)
 {
+    ApiRange api_range_("fpo_adam_step_touched");
     if (!params || !grad || !m || !v) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_records < 0) return fail(FPO_E_INVALID, "n_records < 0");
     if (record_floats < 4 || record_floats % 4 != 0 || record_floats > 4 * dev::kWave)

@@ -387,3 +387,31 @@ def test_c5_skip_renders_sampled_parity(oracle_lib, dev):
     assert (ref["n_seg"][:, 0] > 0).sum() > m // 3
     for name in ("plain", "coarse", "untrained", "overshoot"):
         check_parity(imgs[name][ci, py, px], ref, 1e-4)
+
+
+def test_forced_fallback_gives_plain_image(dev, blob_scene, monkeypatch):
+    """FPO_FORCE_FALLBACK=1: the skip modes fall back to plain traversal for
+    every ray (fpo_render and fpo_render_noalloc); the image is the plain
+    one bit for bit, and without the switch the skip image is within FP32
+    rounding of it."""
+    import torch
+    dijk, k = blob_scene
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev)
+    bits = torch.from_numpy(_lib.coarse_occupancy(dijk, 7).view(np.int32)).to(dev)
+    packed = _lib.mlp_pack(torch.from_numpy(_params(41)).to(dev))
+    cams = [synth.ring_camera(0.7 + 1.3 * j, math.radians(9 + 5 * j), 1.5, 30.0, 96, 64, 11.0 + 17.0 * j)
+            for j in range(2)]
+    ws = _lib.skip_workspace(len(cams), 64, 96, dev)
+    note("forced proposal fallback")
+    plain, _ = _lib.render(tree, cams, _lib.make_opts(stop_T=1e-3))
+    skip = _lib.make_opts(stop_T=1e-3, flags=_lib.FPO_RENDER_SKIP_PROPOSAL, coarse_bits=bits, proposal=packed,
+                          workspace=ws)
+    normal, _ = _lib.render(tree, cams, skip)
+    monkeypatch.setenv("FPO_FORCE_FALLBACK", "1")
+    forced, _ = _lib.render(tree, cams, skip)
+    forced_na, _ = _lib.render_noalloc(tree, cams, skip)
+    monkeypatch.delenv("FPO_FORCE_FALLBACK")
+    torch.cuda.synchronize()
+    assert torch.equal(forced, plain) and torch.equal(forced_na, plain)
+    assert float(plain.max()) > 0.05
+    assert float((normal - plain).abs().max()) < 1e-4

@@ -431,3 +431,22 @@ def test_render_noalloc_validates_on_host():
     src = open(os.path.join(ROOT, "include", "fpo.h")).read()
     assert re.search(r"#define FPO_NOALLOC_SCRATCH_BYTES \(32ll << 20\)", src)
     assert _lib.NOALLOC_SCRATCH_BYTES == 32 << 20
+
+
+def test_fault_injection_alloc(monkeypatch):
+    """FPO_FAULT=alloc: the host calls that allocate fail cleanly with
+    FPO_E_NOMEM and a message, and work again once it is unset."""
+    dijk = synth.random_tree_leaves(3, 4)
+    monkeypatch.setenv("FPO_FAULT", "alloc")
+    L = _lib.lib()
+    n_nodes = ctypes.c_int64(0)
+    arr = np.ascontiguousarray(dijk, dtype=np.int32)
+    p = arr.ctypes.data_as(ctypes.c_void_p)
+    assert L.fpo_build_tree(p, len(arr), 4, None, 0, ctypes.byref(n_nodes), None) == _lib.FPO_E_NOMEM
+    assert b"host memory" in L.fpo_last_error()
+    assert L.fpo_union_leaves(p, len(arr), 4, None, 0, ctypes.byref(n_nodes)) == _lib.FPO_E_NOMEM
+    bits = np.zeros(_lib.COARSE_WORDS if hasattr(_lib, "COARSE_WORDS") else 8192, np.uint32)
+    assert L.fpo_coarse_occupancy(p, len(arr), 4, bits.ctypes.data_as(ctypes.c_void_p)) == _lib.FPO_E_NOMEM
+    monkeypatch.delenv("FPO_FAULT")
+    children, perm = _lib.build_tree(dijk, 4)
+    assert children.shape[0] > 0 and len(perm) == len(dijk)

@@ -32,7 +32,7 @@ def test_host_code_and_oracle_under_asan_ubsan(tmp_path):
         objs.append(obj)
     exe = str(tmp_path / "sanitize_host")
     subprocess.run(["g++", *SAN, *objs, "-o", exe, f"-L{ROCM_LIB}", f"-Wl,-rpath,{ROCM_LIB}", "-lamdhip64",
-                    "-lpthread", "-lm"], check=True, capture_output=True, text=True)
+                    "-lrocprofiler-sdk-roctx", "-lpthread", "-lm"], check=True, capture_output=True, text=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
     res = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
