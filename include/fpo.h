@@ -381,6 +381,41 @@ fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t
                           void* out, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Occupancy at one time                                                    */
+/* ---------------------------------------------------------------------- */
+/* The union octree (Sec. 4.2) keeps every cell occupied in some frame; at a
+ * time t a leaf whose sigma(t) (Eq. 7) is <= 0 has sigma_eff = 0 and adds
+ * nothing to the image.  These calls read sigma(t) from snapshot records
+ * (fpo_bake_times output) so that they agree with the snapshot render.
+ * A leaf is opaque at t iff sigma_scale * max(sigma(t), 0) > 0. */
+
+/* Per-time child tables: children_out[t] is tree->children with every child
+ * slot whose subtree holds no opaque leaf at time t set empty (0).  Rendering
+ * snapshot t through a tree view whose children point at children_out[t]
+ * walks fewer slots; every segment with positive optical depth is the same,
+ * so the image equals the unpruned one up to FP32 rounding of segment ends at
+ * ties.
+ *   snapshots      device [n_t] snapshot records of snapshot_dtype,
+ *                  snapshot_stride leaf records apart (>= n_leaves if n_t > 1).
+ *   children_out   device [n_t][n_nodes][8] int32, 16-byte aligned.
+ * Launches max_depth kernels; no allocation. */
+fpo_status fpo_prune_at(const fpo_tree_view* tree, const void* snapshots, fpo_dtype snapshot_dtype,
+                        int64_t snapshot_stride, int32_t n_t, int32_t* children_out, void* stream);
+
+/* The coarse occupancy of fpo_coarse_occupancy (64^3 cells, dilated by one
+ * cell) over the leaves that are opaque at the snapshot's time only: the skip
+ * modes of fpo_render accept it as opts->coarse_bits for renders of that
+ * snapshot.
+ *   leaf_cells device [n_leaves][4] int32 (depth, i, j, k) in slot order
+ *              (the union leaves permuted by fpo_build_tree's perm), 16-byte
+ *              aligned.
+ *   snapshot   device snapshot records of one time.
+ *   bits_out   device [FPO_COARSE_WORDS] uint32, overwritten. */
+fpo_status fpo_coarse_occupancy_at(const int32_t* leaf_cells, int64_t n_leaves, int32_t max_depth,
+                                   const void* snapshot, fpo_dtype snapshot_dtype, float sigma_scale,
+                                   uint32_t* bits_out, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Building a Fourier PlenOctree from per-frame PlenOctrees (Sec. 4.2)      */
 /* ---------------------------------------------------------------------- */
 /* Frames t = 0 .. T-1 sit at times t of Eq. 8 with period T (the basis is

@@ -124,6 +124,8 @@ _SIGS = {
     "fpo_fusion_observe": [ctypes.POINTER(TreeView), _P, ctypes.POINTER(CameraC), ctypes.POINTER(FieldC),
                            ctypes.c_float, _P, _P],
     "fpo_fusion_apply": [_P, _P, _P, _P, _I64, _P],
+    "fpo_prune_at": [ctypes.POINTER(TreeView), _P, ctypes.c_int, _I64, _I32, _P, _P],
+    "fpo_coarse_occupancy_at": [_P, _I64, _I32, _P, ctypes.c_int, ctypes.c_float, _P, _P],
 }
 # functions with another return type
 _OTHER = {"fpo_mlp_workspace_floats": ([_I64], ctypes.c_int64)}
@@ -660,3 +662,46 @@ def fusion_apply(values, weight, count, acc, n_leaves: int):
     """fpo_fusion_apply over the first n_leaves slots."""
     _check(lib().fpo_fusion_apply(_t_ptr(values), _t_ptr(weight), _t_ptr(count), _t_ptr(acc), int(n_leaves),
                                   _stream()))
+
+
+# ---------------------------------------------------------------------------
+# occupancy at one time
+# ---------------------------------------------------------------------------
+def prune_at(tree: DeviceTree, snapshots, snapshot_dtype: int = FPO_F32, out=None):
+    """fpo_prune_at: per-time child tables [n_t][n_nodes][8] from snapshots
+    [n_t][leaf_stride][32] (or one [leaf_stride][32])."""
+    import torch
+    snaps = snapshots if snapshots.dim() == 3 else snapshots[None]
+    n_t = int(snaps.shape[0])
+    if out is None:
+        out = torch.empty((n_t, tree.n_nodes, 8), dtype=torch.int32, device=snaps.device)
+    tv = tree.view()
+    _check(lib().fpo_prune_at(ctypes.byref(tv), _t_ptr(snaps), int(snapshot_dtype), int(snaps.shape[1]), n_t,
+                              _t_ptr(out), _stream()))
+    return out
+
+
+def tree_with_children(tree: DeviceTree, children) -> "DeviceTree":
+    """The same tree (coefficients, leaves) walked through another child table
+    of the same shape, e.g. one time of prune_at's output."""
+    if tuple(children.shape) != (tree.n_nodes, 8):
+        raise ValueError("child table shape differs")
+    return DeviceTree(children, tree.n_nodes, tree.max_depth, tree.coeffs, tree.scale, tree.dtype, tree.n_leaves,
+                      tree.leaf_stride, tree.perm, tree.layout)
+
+
+def leaf_cells_slot_order(leaf_dijk: np.ndarray, perm: np.ndarray, device):
+    """(depth, i, j, k) of every leaf slot, as fpo_coarse_occupancy_at takes them."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(leaf_dijk, np.int32)[perm])).to(device)
+
+
+def coarse_occupancy_at(leaf_cells, max_depth: int, snapshot, snapshot_dtype: int = FPO_F32,
+                        sigma_scale: float = 64.0, out=None):
+    import torch
+    if out is None:
+        out = torch.empty((8192,), dtype=torch.int32, device=snapshot.device)
+    _check(lib().fpo_coarse_occupancy_at(_t_ptr(leaf_cells), int(leaf_cells.shape[0]), int(max_depth),
+                                         _t_ptr(snapshot), int(snapshot_dtype), float(sigma_scale), _t_ptr(out),
+                                         _stream()))
+    return out

@@ -24,6 +24,7 @@ SOURCES = [
     "fpo_proposal.hip",
     "fpo_construct.hip",
     "fpo_fusion.hip",
+    "fpo_occupancy.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

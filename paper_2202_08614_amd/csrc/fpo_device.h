@@ -173,8 +173,10 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 // Every axis the ray runs down is mirrored (lattice coordinate x -> G - x,
 // octant bit flipped), so that in the walk's frame all direction components
 // are >= 0 and a cell is always left through its upper faces.  The walk keeps
-// the chain of internal nodes above the current cell (a per-lane stack in
-// LDS) and the cell's corner on the finest lattice (G = 2^D cells per axis).
+// the chain of internal nodes above the current cell, each with the octant of
+// its child the ray is in (a per-lane stack in LDS), and the cell's corner on
+// the finest lattice (G = 2^D cells per axis), held as exact small integers in
+// FP32 so that a plane's crossing time (p - x) k needs no conversion.
 // One iteration:
 //   - descend while the current slot holds an internal node, taking the child
 //     whose half the ray is in at t_cur on each axis (t_cur against the time
@@ -182,8 +184,10 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 //   - report a leaf segment [t_cur, t_exit), t_exit the first upper face the
 //     ray reaches (ties x < y < z);
 //   - step to the neighbouring slot of the same size across that face (the
-//     other coordinates are unchanged) and pop to the deepest node that still
-//     contains it, found from the highest bit the step changed.
+//     other coordinates are unchanged): a sibling in the same node flips one
+//     octant bit; otherwise pop to the deepest node that still contains it,
+//     found from the highest bit the step changed, whose stacked octant flips
+//     the same bit.
 // The step and the load of the next slot's child-table entry come before the
 // current leaf is shaded (they do not depend on it), so that load and the
 // leaf's own loads are in flight together.
@@ -227,51 +231,52 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
         const float p = r.o[a] * fG;
         xf[a] = neg ? fG - p : p;
     }
-    int lvl = 0;
+    // current slot: a child of `node` at table octant `oct`, corner pos
+    // (mirrored lattice, exact in FP32), edge 2^csh; the node sits at stack
+    // level D - 1 - csh
     int node = 0;
-    stk[0] = 0;
+    int csh = D - 1;
     float t_cur = 0.0f;
-    int pos[3];          // corner of the current slot (a child of stk[lvl]), mirrored lattice
+    float pos[3];
+    int oct = mirror;
     {
-        const int S = G >> 1;
+        const float half = (float)(G >> 1);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) pos[a] = ((float)S - xf[a]) * k[a] <= t_cur ? S : 0;
+        for (int a = 0; a < 3; ++a) {
+            const bool up = (half - xf[a]) * k[a] <= t_cur;
+            pos[a] = up ? half : 0.0f;
+            oct ^= up ? (1 << a) : 0;
+        }
     }
-    // entry of the current slot (a child of node), requested one step ahead
-    int ch_next;
-    {
-        const int csh = D - 1 - lvl;
-        const int oct = (((pos[0] >> csh) & 1) | (((pos[1] >> csh) & 1) << 1) | (((pos[2] >> csh) & 1) << 2)) ^ mirror;
-        ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
-    }
+    int ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
     const int max_steps = 3 * G + 4;
     for (int it = 0; it < max_steps; ++it) {
         int ch = ch_next;
-        int csh = D - 1 - lvl;
         for (;;) {
-            if (ch > 0 && ch < T.n_nodes && lvl < D - 1) {
-                ++lvl;
+            if (ch > 0 && ch < T.n_nodes && csh > 0) {
+                stk[(D - 1 - csh) * kBlock] = (node << 3) | oct;    // the node and the child the ray is in
                 node = ch;
-                stk[lvl * kBlock] = node;
-                const int S = 1 << (csh - 1);
+                csh -= 1;
+                const float half = __builtin_ldexpf(1.0f, csh);
                 // the child's octant is the half the ray is in on each axis
-                int oct = mirror;
+                oct = mirror;
+#pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const bool up = ((float)(pos[a] + S) - xf[a]) * k[a] <= t_cur;
-                    pos[a] += up ? S : 0;
+                    const float c = pos[a] + half;
+                    const bool up = (c - xf[a]) * k[a] <= t_cur;
+                    pos[a] = up ? c : pos[a];
                     oct ^= up ? (1 << a) : 0;
                 }
-                csh -= 1;
                 ch = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
                 continue;
             }
             if (ch > 0) ch = 0;   // malformed table: treat as empty
             break;
         }
-        const int size = 1 << csh;
+        const float sz = __builtin_ldexpf(1.0f, csh);
         float te[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) te[a] = ((float)(pos[a] + size) - xf[a]) * k[a];
+        for (int a = 0; a < 3; ++a) te[a] = (pos[a] + sz - xf[a]) * k[a];
         int ax = 0;
         float t_exit = te[0];
         if (te[1] < t_exit) { t_exit = te[1]; ax = 1; }
@@ -279,23 +284,26 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
         t_exit = fmaxf(t_exit, t_cur);
         if (ch < 0 && -ch - 1 < T.n_leaves) prefetch_leaf(vis, -ch - 1);
         // step to the next slot and request its entry before shading this one
-        const int old = ax == 0 ? pos[0] : ax == 1 ? pos[1] : pos[2];
-        const int nw = old + size;
-        const bool more = nw < G;
+        const float old = ax == 0 ? pos[0] : ax == 1 ? pos[1] : pos[2];
+        const float nwf = old + sz;
+        const bool more = nwf < fG;
         if (more) {
-            const int h = 31 - __builtin_clz((unsigned)(old ^ nw));
-            const int keep = D - 1 - h;     // deepest stack level whose node contains the new slot
-            pos[0] = ax == 0 ? nw : pos[0];
-            pos[1] = ax == 1 ? nw : pos[1];
-            pos[2] = ax == 2 ? nw : pos[2];
-            if (keep < lvl) {
-                lvl = keep;
-                node = stk[lvl * kBlock];
-                const int m = ~((1 << h) - 1);
-                pos[0] &= m; pos[1] &= m; pos[2] &= m;
+            pos[0] = ax == 0 ? nwf : pos[0];
+            pos[1] = ax == 1 ? nwf : pos[1];
+            pos[2] = ax == 2 ? nwf : pos[2];
+            // highest bit the step changes: csh plus the run of ones above it in the old corner
+            const int h = csh + __builtin_ctz(~((int)old >> csh));
+            if (h > csh) {
+                // pop to the deepest node that contains the new slot (stack level D - 1 - h)
+                csh = h;
+                const int e = stk[(D - 1 - h) * kBlock];
+                node = e >> 3;
+                oct = (e & 7) ^ (1 << ax);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pos[a] = __builtin_ldexpf(floorf(__builtin_ldexpf(pos[a], -h)), h);
+            } else {
+                oct ^= 1 << ax;
             }
-            const int cs = D - 1 - lvl;
-            const int oct = (((pos[0] >> cs) & 1) | (((pos[1] >> cs) & 1) << 1) | (((pos[2] >> cs) & 1) << 2)) ^ mirror;
             ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
         }
         if (ch < 0) {

@@ -69,89 +69,112 @@ __device__ inline int xcd_band(int bid, int nblocks)
 // clear, else the walk starts at the first set cell that scan met; its exit
 // guess is accepted if the backward scan from the cube exit down to it is
 // clear, else the walk ends at the exit of the last set cell; a predicted
-// miss is checked like the coarse variant.  (inf, inf) marks a ray with
-// nothing to walk.
+// miss is checked like the coarse variant (forward scan only).  (inf, inf)
+// marks a ray with nothing to walk.
 //
-// The proposal variant keeps the network's fragments in LDS and loops over
-// tiles (grid-stride, XCD-banded), so each block reads the weights once.
-template <bool MLP>
-__global__ __launch_bounds__(kBlock) void skip_prepass_kernel(SkipLaunch a)
+// The proposal variant runs in two kernels: proposal_infer_kernel evaluates
+// the network (FP16 matrix cores, its fragments in LDS, grid-stride over
+// tiles so each block reads the weights once) and leaves each pixel's
+// prediction (s_in, s_out as fractions of the chord, s_in < 0 for a predicted
+// miss) in the skip buffer; skip_scan_kernel<true> then turns it into the
+// proven interval.  The scans are latency-bound and run at the occupancy of a
+// small kernel instead of the network's.
+struct PixelRay {
+    int ci, px, py;
+    bool inside;
+};
+
+__device__ inline PixelRay pixel_of(const SkipLaunch& a, int lin)
 {
-    __shared__ uint2 s_frag[MLP ? kFrags * 64 : 1];
-    __shared__ float s_bias[MLP ? 132 : 1];
-    if constexpr (MLP) {
-        const uint2* F = reinterpret_cast<const uint2*>(a.packed);
-        for (int i = threadIdx.x; i < kFrags * 64; i += kBlock) s_frag[i] = F[i];
-        if (threadIdx.x < 132) s_bias[threadIdx.x] = reinterpret_cast<const float*>(a.packed + kPackedBias)[threadIdx.x];
-        __syncthreads();
-    }
+    PixelRay p;
+    p.ci = lin / a.blocks_per_cam;
+    const int tb = lin - p.ci * a.blocks_per_cam;
+    const int bx = tb % a.bx_per_cam;
+    const int by = tb / a.bx_per_cam;
+    const int wv = threadIdx.x >> 6;
+    const int ln = threadIdx.x & 63;
+    p.px = bx * 16 + (wv & 1) * 8 + (ln & 7);
+    p.py = by * 16 + (wv >> 1) * 8 + (ln >> 3);
+    p.inside = p.px < a.W && p.py < a.H;
+    return p;
+}
+
+__device__ inline bool pixel_ray(const SkipLaunch& a, const PixelRay& p, Ray& r)
+{
+    const float* fr = a.frame[p.ci];
+    const float sx = (float)(2 * p.px + 1 - a.W) / (float)a.W;
+    const float sy = (float)(a.H - 2 * p.py - 1) / (float)a.H;
+    const float dx = fr[3] + sx * fr[6] + sy * fr[9];
+    const float dy = fr[4] + sx * fr[7] + sy * fr[10];
+    const float dz = fr[5] + sx * fr[8] + sy * fr[11];
+    return setup_ray(fr[0], fr[1], fr[2], dx, dy, dz, r) && p.inside;
+}
+
+__global__ __launch_bounds__(kBlock) void proposal_infer_kernel(SkipLaunch a)
+{
+    __shared__ uint2 s_frag[kFrags * 64];
+    __shared__ float s_bias[132];
+    const uint2* F = reinterpret_cast<const uint2*>(a.packed);
+    for (int i = threadIdx.x; i < kFrags * 64; i += kBlock) s_frag[i] = F[i];
+    if (threadIdx.x < 132) s_bias[threadIdx.x] = reinterpret_cast<const float*>(a.packed + kPackedBias)[threadIdx.x];
+    __syncthreads();
     const int total = a.n_cams * a.blocks_per_cam;
     const int padded = (total + 7) / 8 * 8;
     for (int it = blockIdx.x; it < padded; it += gridDim.x) {
         const int lin = xcd_band(it, padded);
         if (lin >= total) continue;                     // whole blocks: every wave stays complete
-        const int ci = lin / a.blocks_per_cam;
-        const int tb = lin - ci * a.blocks_per_cam;
-        const int bx = tb % a.bx_per_cam;
-        const int by = tb / a.bx_per_cam;
-        const int wv = threadIdx.x >> 6;
-        const int ln = threadIdx.x & 63;
-        const int px = bx * 16 + (wv & 1) * 8 + (ln & 7);
-        const int py = by * 16 + (wv >> 1) * 8 + (ln >> 3);
-        const bool inside = px < a.W && py < a.H;
-        const float* fr = a.frame[ci];
-        const float sx = (float)(2 * px + 1 - a.W) / (float)a.W;
-        const float sy = (float)(a.H - 2 * py - 1) / (float)a.H;
-        const float dx = fr[3] + sx * fr[6] + sy * fr[9];
-        const float dy = fr[4] + sx * fr[7] + sy * fr[10];
-        const float dz = fr[5] + sx * fr[8] + sy * fr[11];
+        const PixelRay p = pixel_of(a, lin);
         Ray r;
-        const bool ok = setup_ray(fr[0], fr[1], fr[2], dx, dy, dz, r) && inside;
-        float ts = __builtin_inff(), te = __builtin_inff();
+        const bool ok = pixel_ray(a, p, r);
+        float x[kMlpIn];
+        proposal_inputs(r, a.tau[p.ci], x);
+        if (!ok)
+            for (int c = 0; c < kMlpIn; ++c) x[c] = 0.0f;
         float o3[3] = {0.0f, 0.0f, 0.0f};
-        if constexpr (MLP) {
-            float x[kMlpIn];
-            proposal_inputs(r, a.tau[ci], x);
-            if (!ok)
-                for (int c = 0; c < kMlpIn; ++c) x[c] = 0.0f;
-            mlp_infer_wave(s_frag, s_bias, x, o3);      // wave-wide: every lane is active here
-        }
-        if (ok) {
-            const float len = r.t_len;
-            if (!MLP || !(o3[0] > 0.0f)) {
-                const float f = coarse_scan(a.bits, r.o, r.d, len);
-                if (f < len) {
-                    ts = f;
-                    te = len;
-                    if (!MLP) {
-                        float pe[3], nd[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            pe[c] = fmaf(len, r.d[c], r.o[c]);
-                            nd[c] = -r.d[c];
-                        }
-                        te = len - coarse_scan(a.bits, pe, nd, len - f);
-                    }
-                }
-            } else {
-                // entry: accept the guess if the chord up to it is clear;
-                // exit: accept the guess if the chord after it is clear, else
-                // take the exit of the last set cell
-                const float s_in = sigmoidf_(o3[1]);
-                const float s_out = sigmoidf_(o3[2]);
-                ts = coarse_scan(a.bits, r.o, r.d, s_in * len);
-                const float span = len - fmaxf(s_out * len, ts);
-                float pe[3], nd[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    pe[c] = fmaf(len, r.d[c], r.o[c]);
-                    nd[c] = -r.d[c];
-                }
-                te = span > 0.0f ? len - coarse_scan(a.bits, pe, nd, span) : len;
-            }
-        }
-        if (inside) a.skip[((int64_t)ci * a.H + py) * a.W + px] = make_float2(ts, te);
+        mlp_infer_wave(s_frag, s_bias, x, o3);          // wave-wide: every lane is active here
+        if (p.inside)
+            a.skip[((int64_t)p.ci * a.H + p.py) * a.W + p.px] =
+                o3[0] > 0.0f ? make_float2(sigmoidf_(o3[1]), sigmoidf_(o3[2])) : make_float2(-1.0f, 0.0f);
     }
+}
+
+template <bool PROP>
+__global__ __launch_bounds__(kBlock) void skip_scan_kernel(SkipLaunch a)
+{
+    const int total = a.n_cams * a.blocks_per_cam;
+    const int lin = xcd_band(blockIdx.x, gridDim.x);
+    if (lin >= total) return;
+    const PixelRay p = pixel_of(a, lin);
+    if (!p.inside) return;
+    Ray r;
+    const bool ok = pixel_ray(a, p, r);
+    const int64_t pix = ((int64_t)p.ci * a.H + p.py) * a.W + p.px;
+    float ts = __builtin_inff(), te = __builtin_inff();
+    if (ok) {
+        const float len = r.t_len;
+        const float2 pred = PROP ? a.skip[pix] : make_float2(-1.0f, 0.0f);
+        float pe[3], nd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pe[c] = fmaf(len, r.d[c], r.o[c]);
+            nd[c] = -r.d[c];
+        }
+        if (!PROP || pred.x < 0.0f) {
+            const float f = coarse_scan(a.bits, r.o, r.d, len);
+            if (f < len) {
+                ts = f;
+                te = PROP ? len : len - coarse_scan(a.bits, pe, nd, len - f);
+            }
+        } else {
+            // entry: accept the guess if the chord up to it is clear; exit:
+            // accept the guess if the chord after it is clear, else take the
+            // exit of the last set cell
+            ts = coarse_scan(a.bits, r.o, r.d, pred.x * len);
+            const float span = len - fmaxf(pred.y * len, ts);
+            te = span > 0.0f ? len - coarse_scan(a.bits, pe, nd, span) : len;
+        }
+    }
+    a.skip[pix] = make_float2(ts, te);
 }
 
 // SKIP: walk only the proven part [t_start, t_end] of each chord that the
@@ -504,10 +527,12 @@ static fpo_status render_impl(const fpo_tree_view* tree, const fpo_camera* cams,
             sk.skip = static_cast<float2*>(opts->workspace);
             a.skip = sk.skip;
             a.bits = opts->coarse_bits;
-            if (skip == FPO_RENDER_SKIP_PROPOSAL)
-                hipLaunchKernelGGL(dev::skip_prepass_kernel<true>, dim3(std::min(grid, 1024)), dim3(dev::kBlock), 0, s, sk);
-            else
-                hipLaunchKernelGGL(dev::skip_prepass_kernel<false>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
+            if (skip == FPO_RENDER_SKIP_PROPOSAL) {
+                hipLaunchKernelGGL(dev::proposal_infer_kernel, dim3(std::min(grid, 1024)), dim3(dev::kBlock), 0, s, sk);
+                hipLaunchKernelGGL(dev::skip_scan_kernel<true>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
+            } else {
+                hipLaunchKernelGGL(dev::skip_scan_kernel<false>, dim3(grid), dim3(dev::kBlock), 0, s, sk);
+            }
             if ((st = launch_status("fpo_render (skip pre-pass)")) != FPO_OK) return st;
         }
         if (variant) {

@@ -312,6 +312,68 @@ def c4_scene(n_leaves: int = 500_000) -> Scene:
     return Scene("c4_blob_d8_500k", 8, dijk, coeffs, c4_cameras(), stop_T=1e-3)
 
 
+def blob_peak_frames(leaf_dijk: np.ndarray, params: BlobParams, n_frames: int = 60,
+                     period: float = PERIOD, chunk: int = 1 << 19) -> np.ndarray:
+    """For every leaf, the frame (0..n_frames-1) at which the moving blob's
+    density rho(x, t) at the leaf's centre is largest."""
+    import torch  # CPU only
+    d = leaf_dijk[:, 0].astype(np.float64)
+    centre = (leaf_dijk[:, 1:4].astype(np.float64) + 0.5) / (2.0 ** d)[:, None]
+    inv = torch.from_numpy(1.0 / (2.0 * params.w ** 2))
+    a = torch.from_numpy(params.a)
+    out = np.empty(len(leaf_dijk), np.int32)
+    mus = [torch.from_numpy(0.5 + params.A * np.sin(2.0 * math.pi * params.f[:, None] * t / period + params.phi))
+           for t in range(n_frames)]
+    for s in range(0, len(leaf_dijk), chunk):
+        x = torch.from_numpy(centre[s:s + chunk])                              # [n][3]
+        best = torch.full((x.shape[0],), -1.0, dtype=torch.float64)
+        arg = torch.zeros((x.shape[0],), dtype=torch.int32)
+        for t, mu in enumerate(mus):
+            r2 = ((x[:, None, :] - mu[None, :, :]) ** 2).sum(-1)                # [n][8]
+            rho = (a[None, :] * torch.exp(-r2 * inv[None, :])).sum(-1)
+            better = rho > best
+            best = torch.where(better, rho, best)
+            arg = torch.where(better, torch.full_like(arg, t), arg)
+        out[s:s + chunk] = arg.numpy()
+    return out
+
+
+def pulse_coeffs(leaf_dijk: np.ndarray, seed: int = COEFF_SEED, geometry_seed: int = GEOMETRY_SEED,
+                 n_frames: int = 60, width: float = 3.0, threshold: float = 0.5) -> np.ndarray:
+    """Coefficients whose density follows the moving blob in time: each
+    leaf's density is a periodic pulse centred on its peak frame tau (the frame
+    at which the blob is densest there), negative elsewhere,
+        sigma(t) = A (P(t - tau) - threshold),
+        P(u) = sum_{m <= 15} g_m cos(2 pi m u / T) / sum_m g_m,  g_m = exp(-m^2 / (2 width^2)),
+    with A ~ U[1, 3] per leaf, so that a leaf is dense for a few frames around
+    tau and transparent (sigma <= 0) the rest of the period, as a region of a
+    moving object is.  In the coefficient order of Eq. 8 a harmonic m is the
+    pair (sin, cos) at indices (2m - 1, 2m): k_{2m-1} = A g_m sin(2 pi m tau / T)
+    / Z, k_{2m} = A g_m cos(2 pi m tau / T) / Z.  The SH colour coefficients are
+    N(0, 1/(i+1)^2) as elsewhere."""
+    tau = blob_peak_frames(leaf_dijk, blob_params(geometry_seed), n_frames=n_frames).astype(np.float64)
+    k = gaussian_coeffs(len(leaf_dijk), seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 101))
+    amp = rng.uniform(1.0, 3.0, size=len(leaf_dijk))
+    n_harm = (N_SIGMA - 1) // 2
+    g = np.exp(-np.arange(n_harm + 1) ** 2 / (2.0 * width ** 2))
+    Z = g.sum()
+    k[:, 0] = (amp * (g[0] / Z - threshold)).astype(np.float32)
+    for m in range(1, n_harm + 1):
+        ph = 2.0 * math.pi * m * tau / PERIOD
+        k[:, 2 * m - 1] = (amp * g[m] / Z * np.sin(ph)).astype(np.float32)
+        k[:, 2 * m] = (amp * g[m] / Z * np.cos(ph)).astype(np.float32)
+    return k
+
+
+def c5_pulse_scene() -> Scene:
+    """The depth-9 blob union (2.0 M leaves, as in the headline scene) with
+    pulse densities (pulse_coeffs): at any time only the part of the union the
+    blob occupies then is dense, the rest of its trail is transparent."""
+    dijk = blob_leaves(9, 2_000_000)
+    return Scene("c5_blob_d9_pulse", 9, dijk, pulse_coeffs(dijk), c5_test_cameras(), stop_T=1e-3)
+
+
 def sample_pixels(n: int, n_cams: int, width: int, height: int, seed: int = RAY_SEED):
     """Uniform (camera, row, column) triples."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -1,0 +1,176 @@
+"""GPU tests of the occupancy at one time: fpo_prune_at (per-time child tables
+in which subtrees without an opaque leaf are empty) and
+fpo_coarse_occupancy_at (the dilated 64^3 grid over the leaves opaque at
+that time).  Inputs that decide opacity are the oracle's bake, rounded to the
+snapshot's precision, so the expected tables follow from the paper's Eq. 7
+and the ReLU by a plain recursion; renders through the pruned tables are
+checked against the oracle and against the unpruned render."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import codec, occupancy
+from paper_2202_08614_amd import _lib, synth
+from tests.gpu_util import check_parity, conditioned_reference, note, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def _oracle_snapshots(oracle_lib, coeffs, times, perm, stride, dtype):
+    """The oracle's bake [n_t][28][L] rounded to F32 or BF16, as snapshot
+    records [n_t][stride][32] in slot order, plus the rounded values."""
+    import torch
+    vals = oracle_lib.bake(coeffs.astype(np.float64), oracle_lib.make_params(), times)       # [n_t][28][L]
+    if dtype == _lib.FPO_F32:
+        vals = vals.astype(np.float32).astype(np.float64)
+        recs = np.zeros((len(times), stride, 32), np.float32)
+        recs[:, :vals.shape[2], :28] = vals[:, :, perm].transpose(0, 2, 1)
+        return torch.from_numpy(recs), vals
+    vals = codec.bf16_decode(codec.bf16_encode(vals.astype(np.float32))).astype(np.float64)
+    recs = np.zeros((len(times), stride, 32), np.uint16)
+    recs[:, :vals.shape[2], :28] = codec.bf16_encode(vals[:, :, perm].transpose(0, 2, 1).astype(np.float32))
+    return torch.from_numpy(recs.view(np.int16)).view(torch.bfloat16), vals
+
+
+def _expected_pruned(children: np.ndarray, opaque_slot: np.ndarray) -> np.ndarray:
+    """Child slots whose subtree holds an opaque leaf, by a bottom-up recursion
+    over the table (nodes are numbered breadth first, children after parents)."""
+    n = children.shape[0]
+    has = np.zeros(n, bool)
+    out = children.copy()
+    for node in range(n - 1, -1, -1):
+        for c in range(8):
+            e = int(children[node, c])
+            if e < 0:
+                keep = bool(opaque_slot[-e - 1])
+            elif e > 0:
+                keep = bool(has[e])
+            else:
+                keep = False
+            if not keep:
+                out[node, c] = 0
+            has[node] |= keep
+    return out
+
+
+@pytest.mark.parametrize("dtype", [_lib.FPO_F32, _lib.FPO_BF16])
+def test_prune_and_occupancy_at_match_definitions(oracle_lib, dev, dtype):
+    import torch
+    dijk = synth.random_tree_leaves(31, 6, p_split=0.6)
+    k = synth.gaussian_coeffs(len(dijk), seed=31)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=len(dijk) + 5)
+    times = [2.0, 19.5, 44.4]
+    snaps, vals = _oracle_snapshots(oracle_lib, k, times, tree.perm, tree.leaf_stride, dtype)
+    snaps = snaps.to(dev)
+    note(f"fpo_prune_at / fpo_coarse_occupancy_at dtype={dtype}")
+    pruned = _lib.prune_at(tree, snaps, dtype)
+    cells = _lib.leaf_cells_slot_order(dijk, tree.perm, dev)
+    bits = [_lib.coarse_occupancy_at(cells, 6, snaps[t], dtype, 64.0).cpu().numpy().view(np.uint32)
+            for t in range(len(times))]
+    torch.cuda.synchronize()
+    children = tree.children.cpu().numpy()
+    got = pruned.cpu().numpy()
+    for t in range(len(times)):
+        opaque_caller = vals[t, 0] > 0.0                       # sigma_scale 64 > 0: opaque iff sigma(t) > 0
+        assert 0.2 < opaque_caller.mean() < 0.8
+        opaque_slot = opaque_caller[tree.perm]
+        want = _expected_pruned(children, opaque_slot)
+        assert np.array_equal(got[t], want), int((got[t] != want).sum())
+        assert (want != 0).sum() < (children != 0).sum()
+        want_bits = occupancy.to_words(occupancy.dilated(dijk[opaque_caller]))
+        assert np.array_equal(bits[t], want_bits), int(np.unpackbits((bits[t] ^ want_bits).view(np.uint8)).sum())
+
+
+@pytest.mark.parametrize("dtype", [_lib.FPO_F32, _lib.FPO_BF16])
+def test_render_through_pruned_tables(oracle_lib, dev, dtype):
+    """Snapshot renders through the pruned table of their time equal the
+    unpruned renders (segments with positive optical depth are the same) and
+    pass the oracle parity; the skip modes (coarse, and proposal with an
+    untrained network) also accept the per-time grid."""
+    import torch
+    dijk = synth.blob_leaves(7, 40000)
+    k = synth.gaussian_coeffs(len(dijk), seed=77)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev)
+    times = [7.0, 33.3]
+    snaps, vals = _oracle_snapshots(oracle_lib, k, times, tree.perm, tree.leaf_stride, dtype)
+    snaps = snaps.to(dev)
+    cams = [synth.ring_camera(0.3 + 1.1 * j, math.radians(5 + 7 * j), 1.5, 30.0, 72, 40, times[j % 2])
+            for j in range(4)]
+    note(f"renders through pruned tables dtype={dtype}")
+    pruned = _lib.prune_at(tree, snaps, dtype)
+    cells = _lib.leaf_cells_slot_order(dijk, tree.perm, dev)
+    ot = oracle_lib.OracleTree(dijk, 7)
+    p = oracle_lib.make_params(stop_T=1e-3)
+    ws = _lib.skip_workspace(1, 40, 72, dev)
+    packed = _lib.mlp_pack(torch.from_numpy(synth.mlp_init(19)).to(dev))
+    for j, cam in enumerate(cams):
+        t = j % 2
+        opts = _lib.make_opts(stop_T=1e-3, snapshot=snaps[t], snapshot_dtype=dtype)
+        plain, _ = _lib.render(tree, [cam], opts)
+        pt = _lib.tree_with_children(tree, pruned[t])
+        got, _ = _lib.render(pt, [cam], opts)
+        bits_t = _lib.coarse_occupancy_at(cells, 7, snaps[t], dtype, 64.0)
+        skip = _lib.make_opts(stop_T=1e-3, snapshot=snaps[t], snapshot_dtype=dtype,
+                              flags=_lib.FPO_RENDER_SKIP_COARSE, coarse_bits=bits_t, workspace=ws)
+        got_skip, _ = _lib.render(pt, [cam], skip)
+        prop = _lib.make_opts(stop_T=1e-3, snapshot=snaps[t], snapshot_dtype=dtype,
+                              flags=_lib.FPO_RENDER_SKIP_PROPOSAL, coarse_bits=bits_t, proposal=packed,
+                              workspace=ws)
+        got_prop, _ = _lib.render(tree, [cam], prop)
+        torch.cuda.synchronize()
+        diff = (got - plain).abs().amax(-1).cpu().numpy().ravel()
+        assert float(plain.max()) > 0.05
+        assert (diff > 0).mean() <= 0.02 and diff.max() <= 2e-5, (float((diff > 0).mean()), float(diff.max()))
+        o, d = oracle_lib.camera_rays(cam)
+        ref = conditioned_reference(oracle_lib, ot, None, p, [times[t]], o, d, np.zeros(len(o), np.int32),
+                                    snapshot=vals[t])
+        check_parity(got.cpu().numpy().reshape(-1, 3), ref, 1e-4)
+        check_parity(got_skip.cpu().numpy().reshape(-1, 3), ref, 1e-4)
+        check_parity(got_prop.cpu().numpy().reshape(-1, 3), ref, 1e-4)
+
+
+def test_c2_pruned_decode_sampled(oracle_lib, dev):
+    """The pruned decode path at full size: the 2M-leaf scene, the step's 10
+    times baked into F32 snapshots and pruned in one call each, 16 cameras of
+    1080p per time through the pruned tables (the benchmark's launches); 3000
+    sampled pixels of every launch against the oracle, and the images against
+    the unpruned renders."""
+    import torch
+    sc = synth.c2_scene()
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    cams = sc.cameras
+    n_t, per = 10, 16
+    times = [cams[j * per].time for j in range(n_t)]
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    note("c2 decode + prune at 10 times")
+    snap = _lib.bake_times(tree, basis, _lib.FPO_F32)
+    pruned = _lib.prune_at(tree, snap, _lib.FPO_F32)
+    torch.cuda.synchronize()
+    kept = (pruned != 0).sum(dim=(1, 2)).cpu().numpy() / float((tree.children != 0).sum())
+    assert np.all(kept < 0.95), kept
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
+    p = oracle_lib.make_params(stop_T=1e-3)
+    rng = np.random.default_rng(10)
+    for j in (0, 5, 9):
+        opts = _lib.make_opts(stop_T=1e-3, snapshot=snap[j], snapshot_dtype=_lib.FPO_F32)
+        note(f"c2 pruned render time index {j}")
+        got, _ = _lib.render(_lib.tree_with_children(tree, pruned[j]), cams[j * per:(j + 1) * per], opts)
+        plain, _ = _lib.render(tree, cams[j * per:(j + 1) * per], opts)
+        torch.cuda.synchronize()
+        diff = (got - plain).abs().amax(-1)
+        assert float((diff > 0).float().mean()) <= 1e-3 and float(diff.max()) <= 2e-5
+        m = 3000
+        ci = rng.integers(0, per, m); py = rng.integers(0, 1080, m); px = rng.integers(0, 1920, m)
+        vals = got[torch.from_numpy(ci).to(dev), torch.from_numpy(py).to(dev), torch.from_numpy(px).to(dev)]
+        o = np.zeros((m, 3)); d = np.zeros((m, 3))
+        for c in np.unique(ci):
+            sel = np.nonzero(ci == c)[0]
+            o[sel], d[sel] = oracle_lib.camera_rays(cams[j * per + c], px[sel], py[sel])
+        ref = conditioned_reference(oracle_lib, ot, sc.coeffs, p, [times[j]], o, d, np.zeros(m, np.int32))
+        check_parity(vals.cpu().numpy().astype(np.float64), ref, 1e-4)
