@@ -57,7 +57,8 @@ def log(msg):
 # for the sources it was measured on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_traffic.json")
 RENDER_SOURCES = ["include/fpo.h", "paper_2202_08614_amd/csrc/fpo_device.h", "paper_2202_08614_amd/csrc/fpo_render.hip",
-                  "paper_2202_08614_amd/csrc/fpo_proposal.h", "paper_2202_08614_amd/csrc/fpo_internal.h"]
+                  "paper_2202_08614_amd/csrc/fpo_proposal.h", "paper_2202_08614_amd/csrc/fpo_internal.h",
+                  "paper_2202_08614_amd/csrc/fpo_occupancy.hip"]
 
 
 def render_source_hash() -> str:
@@ -894,6 +895,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2000000,
                     help="rays rendered by the oracle (quality check and CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--render-modes", default="fourier,decode,decode_pruned",
+                    help="comma-separated render paths to time (with --no-cpu, e.g. one path for a clean profile)")
     ap.add_argument("--no-finetune", action="store_true")
     ap.add_argument("--no-bake", action="store_true")
     ap.add_argument("--ft-steps", type=int, default=40)
@@ -1020,7 +1023,11 @@ def main():
             f"render launch {r_ms:.3f} ms" + (f", bake (and prune) of {n_t} times {b_ms:.3f} ms" if b_ms else ""))
         return ms, r_ms, b_ms
 
-    MODES = ("fourier", "decode", "decode_pruned")
+    MODES = tuple(m for m in args.render_modes.split(",") if m)
+    if not set(MODES) <= {"fourier", "decode", "decode_pruned"} or not MODES:
+        raise SystemExit("--render-modes takes fourier, decode and decode_pruned")
+    if not args.no_cpu and len(MODES) < 3:
+        raise SystemExit("the full run times every render path; restrict --render-modes with --no-cpu only")
     frames = {m: torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=dev) for m in MODES}
     timing = {m: run_mode(m, frames[m], args.steps, args.warmup) for m in MODES}
 
