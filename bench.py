@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -61,12 +62,21 @@ RENDER_SOURCES = ["include/fpo.h", "paper_2202_08614_amd/csrc/fpo_device.h", "pa
                   "paper_2202_08614_amd/csrc/fpo_occupancy.hip"]
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace runs collapsed: edits
+    to documentation leave the counters of unchanged code valid."""
+    text = re.sub(r"//[^\n]*|/\*.*?\*/", " ", text, flags=re.S)
+    return " ".join(text.split())
+
+
 def render_source_hash() -> str:
+    """SHA-256 over the code (comments stripped) of the render sources."""
     import hashlib
     h = hashlib.sha256()
     for rel in RENDER_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            h.update(_code_only(f.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()
 
 

@@ -34,7 +34,8 @@
  *   leaf_stride >= n_leaves.
  * - Ownership: the caller owns every buffer.  The library allocates no
  *   device memory, creates no streams and keeps no global state except the
- *   thread-local error message.  Device work is enqueued on `stream` (a
+ *   thread-local error message and, for fpo_render_noalloc, a static scratch
+ *   array on each device with its address cached per device.  Device work is enqueued on `stream` (a
  *   hipStream_t passed as void*, NULL = the null stream) and is
  *   asynchronous; kernel faults surface at the caller's next synchronisation.
  * - Errors: every call returns fpo_status.  On FPO_E_INVALID or
