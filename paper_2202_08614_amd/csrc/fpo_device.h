@@ -178,9 +178,10 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 // the finest lattice (G = 2^D cells per axis), held as exact small integers in
 // FP32 so that a plane's crossing time (p - x) k needs no conversion.
 // One iteration:
-//   - descend while the current slot holds an internal node, taking the child
-//     whose half the ray is in at t_cur on each axis (t_cur against the time
-//     the ray crosses the node's centre plane);
+//   - descend while the current slot holds an internal node: the ray's cell
+//     on the finest lattice at t_cur (x + t_cur / k per axis, clamped into
+//     the slot) is found once, and each level's octant is one bit of it per
+//     axis;
 //   - report a leaf segment [t_cur, t_exit), t_exit the first upper face the
 //     ray reaches (ties x < y < z);
 //   - step to the neighbouring slot of the same size across that face (the
@@ -231,48 +232,54 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
         const float p = r.o[a] * fG;
         xf[a] = neg ? fG - p : p;
     }
-    // current slot: a child of `node` at table octant `oct`, corner pos
-    // (mirrored lattice, exact in FP32), edge 2^csh; the node sits at stack
-    // level D - 1 - csh
-    int node = 0;
+    // current slot: table entry `no` = (node << 3) | octant of the child table,
+    // corner pos (mirrored lattice, exact in FP32), edge 2^csh; each stacked
+    // entry is kept under the edge exponent of its child slot
     int csh = D - 1;
     float t_cur = 0.0f;
     float pos[3];
-    int oct = mirror;
+    int no = 0;
     {
         const float half = (float)(G >> 1);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool up = (half - xf[a]) * k[a] <= t_cur;
             pos[a] = up ? half : 0.0f;
-            oct ^= up ? (1 << a) : 0;
+            no |= (up ? 1 : 0) << a;
         }
     }
-    int ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
+    no ^= mirror;
+    int ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, no * 4, 0, 0);
     const int max_steps = 3 * G + 4;
     for (int it = 0; it < max_steps; ++it) {
         int ch = ch_next;
-        for (;;) {
-            if (ch > 0 && ch < T.n_nodes && csh > 0) {
-                stk[(D - 1 - csh) * kBlock] = (node << 3) | oct;    // the node and the child the ray is in
-                node = ch;
-                csh -= 1;
-                const float half = __builtin_ldexpf(1.0f, csh);
-                // the child's octant is the half the ray is in on each axis
-                oct = mirror;
+        if (ch > 0 && ch < T.n_nodes && csh > 0) {
+            // The finest-lattice cell q the ray is in at t_cur (mirrored
+            // frame), clamped into the current slot: every level below takes
+            // its octant from one bit of q per axis.  A point that rounds
+            // across an inner plane only moves the walk by a zero-length
+            // segment or a sliver of one.
+            int q[3];
+            {
+                const float top = __builtin_ldexpf(1.0f, csh) - 1.0f;
+                const float tg = t_cur * fG;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float c = pos[a] + half;
-                    const bool up = (c - xf[a]) * k[a] <= t_cur;
-                    pos[a] = up ? c : pos[a];
-                    oct ^= up ? (1 << a) : 0;
-                }
-                ch = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
-                continue;
+                for (int a = 0; a < 3; ++a)
+                    q[a] = (int)__builtin_amdgcn_fmed3f(fmaf(tg, fabsf(r.d[a]), xf[a]), pos[a], pos[a] + top);
             }
-            if (ch > 0) ch = 0;   // malformed table: treat as empty
-            break;
+            do {
+                stk[csh * kBlock] = no;    // the node and the child the ray is in
+                csh -= 1;
+                const int bits = __builtin_amdgcn_ubfe(q[0], csh, 1) | (__builtin_amdgcn_ubfe(q[1], csh, 1) << 1) |
+                                 (__builtin_amdgcn_ubfe(q[2], csh, 1) << 2);
+                no = (ch << 3) | (bits ^ mirror);
+                ch = __builtin_amdgcn_raw_buffer_load_b32(ct, no * 4, 0, 0);
+            } while (ch > 0 && ch < T.n_nodes && csh > 0);
+            const int m = -1 << csh;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) pos[a] = (float)(q[a] & m);
         }
+        if (ch > 0) ch = 0;   // malformed table or past the deepest level: treat as empty
         const float sz = __builtin_ldexpf(1.0f, csh);
         float te[3];
 #pragma unroll
@@ -294,17 +301,15 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
             // highest bit the step changes: csh plus the run of ones above it in the old corner
             const int h = csh + __builtin_ctz(~((int)old >> csh));
             if (h > csh) {
-                // pop to the deepest node that contains the new slot (stack level D - 1 - h)
+                // pop to the deepest node that contains the new slot (stacked under the slot size h)
                 csh = h;
-                const int e = stk[(D - 1 - h) * kBlock];
-                node = e >> 3;
-                oct = (e & 7) ^ (1 << ax);
+                no = stk[h * kBlock] ^ (1 << ax);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) pos[a] = __builtin_ldexpf(floorf(__builtin_ldexpf(pos[a], -h)), h);
             } else {
-                oct ^= 1 << ax;
+                no ^= 1 << ax;
             }
-            ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, (node * 8 + oct) * 4, 0, 0);
+            ch_next = __builtin_amdgcn_raw_buffer_load_b32(ct, no * 4, 0, 0);
         }
         if (ch < 0) {
             const int leaf = -ch - 1;
