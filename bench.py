@@ -588,6 +588,7 @@ def _proposal_scene(dev, sc, tree, oracle_mod, n_train, train_steps, batch, orac
     snap = torch.empty((1, tree.leaf_stride, _lib.SNAP_VALUES), dtype=torch.float32, device=dev)
     bits_t = torch.empty((8192,), dtype=torch.int32, device=dev)
     pruned = torch.empty((1, tree.n_nodes, 8), dtype=torch.int32, device=dev)
+    sig1 = torch.empty((1, tree.leaf_stride), dtype=torch.float32, device=dev)
     cells = _lib.leaf_cells_slot_order(sc.leaf_dijk, tree.perm, dev)
     ws = _lib.skip_workspace(per, H, W, dev)
     # (name, store, decode, grid: None | "union" | "time", proposal, pruned)
@@ -614,13 +615,13 @@ def _proposal_scene(dev, sc, tree, oracle_mod, n_train, train_steps, batch, orac
             rt = tr
             bits = bits_union
             if decode:
-                _lib.bake_times(tr, basis[j:j + 1], _lib.FPO_F32, out=snap)
+                _lib.bake_times(tr, basis[j:j + 1], _lib.FPO_F32, out=snap, sigma_out=sig1 if use_pruned else None)
                 if grid == "time":
                     _lib.coarse_occupancy_at(cells, sc.max_depth, snap[0], _lib.FPO_F32,
                                              tr.layout.sigma_scale, out=bits_t)
                     bits = bits_t
                 if use_pruned:
-                    _lib.prune_at(tr, snap, _lib.FPO_F32, out=pruned)
+                    _lib.prune_at_sigma(tr, sig1, out=pruned)
                     rt = _lib.tree_with_children(tr, pruned[0])
             kw = {}
             if grid is not None:
@@ -984,6 +985,7 @@ def main():
 
     pruned = torch.empty((n_t, tree.n_nodes, 8), dtype=torch.int32, device=dev)
     pruned_trees = [_lib.tree_with_children(tree, pruned[j]) for j in range(n_t)]
+    sigma_plane = torch.empty((n_t, tree.leaf_stride), dtype=torch.float32, device=dev)
 
     def run_mode(mode, frames, steps, warmup):
         """Time `steps` steps of 160 frames.  mode 'fourier': one fpo_render
@@ -991,17 +993,20 @@ def main():
         one fpo_bake_times of the step's 10 time points into F32 snapshots (the
         IDFT once per leaf and time, the coefficients read once), then one
         snapshot-mode fpo_render launch per time point for its 16 cameras.
-        mode 'decode_pruned': the decode step plus one fpo_prune_at of the 10
-        snapshots (per-time child tables without the subtrees that are
-        transparent at that time), each time's cameras walking its table."""
+        mode 'decode_pruned': the decode step, the bake also writing its density
+        plane, plus one fpo_prune_at_sigma of the 10 times (per-time child
+        tables without the subtrees that are transparent at that time), each
+        time's cameras walking its table."""
         decode = mode.startswith("decode")
         def step(ev_r=None, ev_b=None):
             if decode:
                 if ev_b is not None:
                     ev_b[0][0].record(stream)
-                _lib.bake_times(tree, basis_j, _lib.FPO_F32, out=snap)
                 if mode == "decode_pruned":
-                    _lib.prune_at(tree, snap, _lib.FPO_F32, out=pruned)
+                    _lib.bake_times(tree, basis_j, _lib.FPO_F32, out=snap, sigma_out=sigma_plane)
+                    _lib.prune_at_sigma(tree, sigma_plane, out=pruned)
+                else:
+                    _lib.bake_times(tree, basis_j, _lib.FPO_F32, out=snap)
                 if ev_b is not None:
                     ev_b[0][1].record(stream)
             for j in range(n_t):

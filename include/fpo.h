@@ -377,9 +377,13 @@ fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stri
  *   out     device [n_t][leaf_stride] snapshot records of out_dtype (F32 or
  *           BF16, RNE), multiplied by the leaf scale for quantised stores;
  *           slots >= n_leaves are not written.  Record t is a snapshot for
- *           fpo_render / fpo_render_rays with snapshot_cam_stride = leaf_stride. */
+ *           fpo_render / fpo_render_rays with snapshot_cam_stride = leaf_stride.
+ *   sigma_out  device [n_t][leaf_stride] F32, or NULL: value 0 (sigma(t)) of
+ *           each record written, as FP32 (the BF16 value itself for BF16
+ *           records): the 4-byte plane fpo_prune_at_sigma reads instead of
+ *           a whole record line per leaf.  Slots >= n_leaves are not written. */
 fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t, fpo_dtype out_dtype,
-                          void* out, void* stream);
+                          void* out, float* sigma_out, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Occupancy at one time                                                    */
@@ -387,7 +391,8 @@ fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t
 /* The union octree (Sec. 4.2) keeps every cell occupied in some frame; at a
  * time t a leaf whose sigma(t) (Eq. 7) is <= 0 has sigma_eff = 0 and adds
  * nothing to the image.  These calls read sigma(t) from snapshot records
- * (fpo_bake_times output) so that they agree with the snapshot render.
+ * (fpo_bake_times output), or its density plane, so that they agree with
+ * the snapshot render.
  * A leaf is opaque at t iff sigma_scale * max(sigma(t), 0) > 0. */
 
 /* Per-time child tables: children_out[t] is tree->children with every child
@@ -402,6 +407,14 @@ fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t
  * Launches max_depth kernels; no allocation. */
 fpo_status fpo_prune_at(const fpo_tree_view* tree, const void* snapshots, fpo_dtype snapshot_dtype,
                         int64_t snapshot_stride, int32_t n_t, int32_t* children_out, void* stream);
+
+/* fpo_prune_at with sigma(t) read from a density plane (fpo_bake_times
+ * sigma_out) instead of the records: the same tables, from 4 bytes per leaf
+ * and time instead of a record line.
+ *   sigma         device [n_t][sigma_stride] F32 (>= n_leaves if n_t > 1).
+ *   children_out  as fpo_prune_at. */
+fpo_status fpo_prune_at_sigma(const fpo_tree_view* tree, const float* sigma, int64_t sigma_stride, int32_t n_t,
+                              int32_t* children_out, void* stream);
 
 /* The coarse occupancy of fpo_coarse_occupancy (64^3 cells, dilated by one
  * cell) over the leaves that are opaque at the snapshot's time only: the skip

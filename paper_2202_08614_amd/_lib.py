@@ -109,7 +109,7 @@ _SIGS = {
     "fpo_adam_step_touched": [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, _I32, _P, _P],
     "fpo_quantize": [_P, _I64, _I64, ctypes.c_int, _P, _P, _P],
-    "fpo_bake_times": [ctypes.POINTER(TreeView), _P, _I32, ctypes.c_int, _P, _P],
+    "fpo_bake_times": [ctypes.POINTER(TreeView), _P, _I32, ctypes.c_int, _P, _P, _P],
     "fpo_coarse_occupancy": [_P, _I64, _I32, _P],
     "fpo_ray_labels": [ctypes.POINTER(TreeView), _P, _P, _P, _P, _P, _I32, _I64,
                        ctypes.POINTER(RenderOpts), _P, _P, _P],
@@ -125,6 +125,7 @@ _SIGS = {
                            ctypes.c_float, _P, _P],
     "fpo_fusion_apply": [_P, _P, _P, _P, _I64, _P],
     "fpo_prune_at": [ctypes.POINTER(TreeView), _P, ctypes.c_int, _I64, _I32, _P, _P],
+    "fpo_prune_at_sigma": [ctypes.POINTER(TreeView), _P, _I64, _I32, _P, _P],
     "fpo_coarse_occupancy_at": [_P, _I64, _I32, _P, ctypes.c_int, ctypes.c_float, _P, _P],
 }
 # functions with another return type
@@ -473,15 +474,21 @@ def quantize(tree: DeviceTree, dtype: int) -> DeviceTree:
     return tree.with_store(q, scale, dtype)
 
 
-def bake_times(tree: DeviceTree, basis, out_dtype: int = FPO_F32, out=None):
-    """fpo_bake_times -> out [n_t][leaf_stride][32] snapshot records (float32 or bfloat16)."""
+def bake_times(tree: DeviceTree, basis, out_dtype: int = FPO_F32, out=None, sigma_out=None):
+    """fpo_bake_times -> out [n_t][leaf_stride][32] snapshot records (float32 or
+    bfloat16).  sigma_out: None, or a float32 [n_t][leaf_stride] tensor that
+    receives value 0 of every record as FP32 (the density plane)."""
     import torch
     n_t = int(basis.shape[0])
     if out is None:
         dt = torch.float32 if out_dtype == FPO_F32 else torch.bfloat16
         out = torch.empty((n_t, tree.leaf_stride, SNAP_VALUES), dtype=dt, device=basis.device)
+    if sigma_out is not None and (sigma_out.dtype != torch.float32 or tuple(sigma_out.shape) != (n_t, tree.leaf_stride)
+                                  or not sigma_out.is_contiguous()):
+        raise ValueError("sigma_out must be a contiguous float32 [n_t][leaf_stride] tensor")
     tv = tree.view()
-    _check(lib().fpo_bake_times(ctypes.byref(tv), _t_ptr(basis), n_t, int(out_dtype), _t_ptr(out), _stream()))
+    _check(lib().fpo_bake_times(ctypes.byref(tv), _t_ptr(basis), n_t, int(out_dtype), _t_ptr(out),
+                                None if sigma_out is None else _t_ptr(sigma_out), _stream()))
     return out
 
 
@@ -678,6 +685,19 @@ def prune_at(tree: DeviceTree, snapshots, snapshot_dtype: int = FPO_F32, out=Non
     tv = tree.view()
     _check(lib().fpo_prune_at(ctypes.byref(tv), _t_ptr(snaps), int(snapshot_dtype), int(snaps.shape[1]), n_t,
                               _t_ptr(out), _stream()))
+    return out
+
+
+def prune_at_sigma(tree: DeviceTree, sigma, out=None):
+    """fpo_prune_at_sigma: per-time child tables [n_t][n_nodes][8] from a
+    density plane [n_t][stride] float32 (bake_times sigma_out)."""
+    import torch
+    sg = sigma if sigma.dim() == 2 else sigma[None]
+    n_t = int(sg.shape[0])
+    if out is None:
+        out = torch.empty((n_t, tree.n_nodes, 8), dtype=torch.int32, device=sg.device)
+    tv = tree.view()
+    _check(lib().fpo_prune_at_sigma(ctypes.byref(tv), _t_ptr(sg), int(sg.shape[1]), n_t, _t_ptr(out), _stream()))
     return out
 
 

@@ -122,6 +122,15 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi)
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
 }
 
+// The density value a snapshot record holds, as FP32: itself for F32
+// records, its BF16 rounding (the same RNE conversion) for BF16 records.
+template <int OUT_BF16>
+__device__ inline float stored_sigma(float v)
+{
+    if constexpr (OUT_BF16) return __uint_as_float(pack_bf16x2(v, 0.0f) << 16);
+    else return v;
+}
+
 constexpr int kBakeLeaves = 16;           // leaves per wave group (one MFMA N tile)
 constexpr int kBakeWaves = kBlock / kWave;
 constexpr int kCoefPad = 169;             // LDS row stride, F32 rows (odd: spreads banks)
@@ -133,6 +142,7 @@ struct BakeLaunch {
     int32_t n_t;
     int64_t n_leaves;
     void* out;             // [n_t][stride][32] records
+    float* sigma;          // [n_t][stride] value 0 of each record as FP32, or null
 };
 
 // One wave per group of 16 leaves.  The 16 records (pad words included:
@@ -242,6 +252,10 @@ __global__ __launch_bounds__(kBlock, (DT != FPO_F32 && OUT_BF16) ? 3 : 2) void b
                 float v[32];
 #pragma unroll
                 for (int q = 0; q < 32; ++q) v[q] = q < FPO_N_BAKED ? acc[q][r] * s : 0.0f;
+                if (a.sigma) {
+                    const int t = t0 + 4 * kq + r;
+                    if (t < a.n_t && n < n_valid) a.sigma[t * a.tree.stride + my_leaf] = stored_sigma<OUT_BF16>(v[0]);
+                }
                 uint4* st = stage[wv][kq][n];
                 if constexpr (OUT_BF16) {
 #pragma unroll
@@ -284,7 +298,7 @@ __global__ __launch_bounds__(kBlock, (DT != FPO_F32 && OUT_BF16) ? 3 : 2) void b
 // and FP8 records are small enough that per-thread reads stream well).
 template <int DT, int OUT_BF16>
 __global__ __launch_bounds__(kBlock) void eval_times_kernel(TreeDev tree, const float* basis, int32_t n_t,
-                                                            int64_t n_leaves, void* out)
+                                                            int64_t n_leaves, void* out, float* sigma)
 {
     constexpr int W = Pack<DT>::W;
     constexpr int R = Pack<DT>::R;
@@ -312,6 +326,7 @@ __global__ __launch_bounds__(kBlock) void eval_times_kernel(TreeDev tree, const 
         }
         v[28] = v[29] = v[30] = v[31] = 0.0f;
         const int64_t r = (int64_t)t * tree.stride + l;
+        if (sigma) sigma[r] = stored_sigma<OUT_BF16>(v[0]);
         if (OUT_BF16) {
             uint4* o = static_cast<uint4*>(out) + r * 4;
 #pragma unroll
@@ -340,7 +355,7 @@ constexpr int kEvalOutPad = 33;           // LDS floats per staged output record
 
 template <int OUT_BF16>
 __global__ __launch_bounds__(kBlock) void eval_times_f32_kernel(TreeDev tree, const float* basis, int32_t n_t,
-                                                                int64_t n_leaves, void* out)
+                                                                int64_t n_leaves, void* out, float* sigma)
 {
     constexpr int DT = FPO_F32;
     constexpr int W = Pack<DT>::W;
@@ -389,6 +404,7 @@ __global__ __launch_bounds__(kBlock) void eval_times_f32_kernel(TreeDev tree, co
 #pragma unroll
             for (int i = 0; i < FPO_N_SIGMA; ++i) sg = fmaf(k[i], b[i], sg);
             rs[0] = sg;
+            if (sigma && n < n_valid) sigma[(int64_t)t * tree.stride + leaf0 + n] = stored_sigma<OUT_BF16>(sg);
         } else {
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
@@ -432,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void eval_times_f32_kernel(TreeDev tree, co
 // whole record in registers.
 template <int N1, int N2>
 __global__ __launch_bounds__(kBlock) void eval_times_layout_kernel(TreeDev tree, const float* basis, int32_t n_t,
-                                                                   int64_t n_leaves, float* out)
+                                                                   int64_t n_leaves, float* out, float* sigma)
 {
     using RC = Rec<FPO_F32, N1, N2>;
     constexpr int kWords = (RC::kCoeff + 3) / 4;
@@ -455,6 +471,7 @@ __global__ __launch_bounds__(kBlock) void eval_times_layout_kernel(TreeDev tree,
                 else if (q < RC::kCoeff) v[1 + (q - N1) / N2] = fmaf(k[e], b[(q - N1) % N2], v[1 + (q - N1) / N2]);
             }
         }
+        if (sigma) sigma[(int64_t)t * tree.stride + l] = v[0];
         float4* o = reinterpret_cast<float4*>(out) + ((int64_t)t * tree.stride + l) * 8;
 #pragma unroll
         for (int w = 0; w < 8; ++w) o[w] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
@@ -492,7 +509,7 @@ extern "C" fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_
 }
 
 extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t n_t,
-                                     fpo_dtype out_dtype, void* out, void* stream)
+                                     fpo_dtype out_dtype, void* out, float* sigma_out, void* stream)
 {
     ApiRange api_range_("fpo_bake_times");
     fpo_status st = check_tree(tree, true, true);
@@ -509,7 +526,7 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
         float* o = static_cast<float*>(out);
         switch (tree->layout.n_sigma * 100 + tree->layout.n_sh_fourier) {
 #define FPO_EVL(A, B) case A * 100 + B: \
-            hipLaunchKernelGGL((dev::eval_times_layout_kernel<A, B>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td, basis, n_t, tree->n_leaves, o); break
+            hipLaunchKernelGGL((dev::eval_times_layout_kernel<A, B>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td, basis, n_t, tree->n_leaves, o, sigma_out); break
             FPO_EVL(11, 5); FPO_EVL(21, 5); FPO_EVL(11, 11); FPO_EVL(21, 11); FPO_EVL(31, 11);
 #undef FPO_EVL
             default: return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
@@ -526,6 +543,7 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
     a.n_t = n_t;
     a.n_leaves = tree->n_leaves;
     a.out = out;
+    a.sigma = sigma_out;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool bf = out_dtype == FPO_BF16;
     if (n_t < kMfmaMinTimes) {
@@ -534,16 +552,16 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
             const int64_t g16 = (tree->n_leaves + per_block - 1) / per_block;
             if (bf)
                 hipLaunchKernelGGL((dev::eval_times_f32_kernel<1>), dim3((unsigned)g16), dim3(dev::kBlock), 0, s, td,
-                                   basis, n_t, tree->n_leaves, out);
+                                   basis, n_t, tree->n_leaves, out, sigma_out);
             else
                 hipLaunchKernelGGL((dev::eval_times_f32_kernel<0>), dim3((unsigned)g16), dim3(dev::kBlock), 0, s, td,
-                                   basis, n_t, tree->n_leaves, out);
+                                   basis, n_t, tree->n_leaves, out, sigma_out);
             return launch_status("fpo_bake_times");
         }
         const int64_t g1 = (tree->n_leaves + dev::kBlock - 1) / dev::kBlock;
 #define FPO_EVAL(DT, BF)                                                                                   \
     hipLaunchKernelGGL((dev::eval_times_kernel<DT, BF>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td,  \
-                       basis, n_t, tree->n_leaves, out)
+                       basis, n_t, tree->n_leaves, out, sigma_out)
         switch (tree->dtype) {
             case FPO_BF16: if (bf) FPO_EVAL(FPO_BF16, 1); else FPO_EVAL(FPO_BF16, 0); break;
             default: if (bf) FPO_EVAL(FPO_FP8_E4M3, 1); else FPO_EVAL(FPO_FP8_E4M3, 0); break;

@@ -3,8 +3,9 @@
 // every cell that is occupied in some frame; at a given time many of its
 // leaves have sigma(t) <= 0 (Eq. 7 through the ReLU), contribute nothing to
 // the image, and need not be walked.  Both passes read sigma(t) from a
-// snapshot (the decode pass's fpo_bake_times output), so they agree with the
-// snapshot render that consumes them.
+// snapshot (the decode pass's fpo_bake_times output), or from the density
+// plane the same call writes beside it, so they agree with the snapshot
+// render that consumes them.
 //
 //   fpo_prune_at: a copy of the child table per time in which every child
 //   slot whose subtree holds no leaf with sigma_eff(t) > 0 is empty.  Rows are
@@ -31,11 +32,18 @@
 namespace fpo {
 namespace dev {
 
-// sigma(t) of one leaf from a snapshot record (value 0), as the render reads it.
+// Source of sigma(t) besides F32 and BF16 snapshot records: a density plane
+// of one FP32 per leaf (fpo_bake_times sigma_out).
+constexpr int kSigmaPlane = 100;
+
+// sigma(t) of one leaf from a snapshot record (value 0), as the render reads
+// it, or from a density plane.
 template <int SDT>
 __device__ inline float snapshot_sigma(const void* snap, int64_t leaf)
 {
-    if constexpr (SDT == FPO_F32) {
+    if constexpr (SDT == kSigmaPlane) {
+        return static_cast<const float*>(snap)[leaf];
+    } else if constexpr (SDT == FPO_F32) {
         return static_cast<const float*>(snap)[leaf * 32];
     } else {
         const uint16_t b = static_cast<const uint16_t*>(snap)[leaf * 32];
@@ -63,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void prune_leaves_kernel(PruneLaunch a)
     if (id >= a.n_nodes * a.n_t) return;
     const int t = (int)(id / a.n_nodes);
     const int64_t node = id - (int64_t)t * a.n_nodes;
-    const size_t rec = SDT == FPO_F32 ? 128 : 64;
+    const size_t rec = SDT == kSigmaPlane ? 4 : SDT == FPO_F32 ? 128 : 64;
     const void* snap = static_cast<const char*>(a.snap) + (size_t)t * (size_t)a.snap_stride * rec;
     const int4* row = reinterpret_cast<const int4*>(a.children + node * 8);
     int e[8];
@@ -200,17 +208,18 @@ __global__ __launch_bounds__(1024) void occupancy_dilate_kernel(uint32_t* bits)
 
 using namespace fpo;
 
-extern "C" fpo_status fpo_prune_at(const fpo_tree_view* tree, const void* snapshots, fpo_dtype snapshot_dtype,
-                                   int64_t snapshot_stride, int32_t n_t, int32_t* children_out, void* stream)
+namespace {
+
+// Shared body of fpo_prune_at and fpo_prune_at_sigma: src holds n_t sources of
+// sigma(t) (records of `kind` or a density plane), `stride` leaves apart.
+fpo_status prune_impl(const fpo_tree_view* tree, const void* src, int kind, int64_t stride, int32_t n_t,
+                      int32_t* children_out, void* stream, const char* name)
 {
     fpo_status st = check_tree(tree, false, true);
     if (st != FPO_OK) return st;
-    if (!snapshots || !children_out) return fail(FPO_E_INVALID, "NULL device pointer");
-    if (snapshot_dtype != FPO_F32 && snapshot_dtype != FPO_BF16)
-        return fail(FPO_E_INVALID, "snapshot_dtype must be F32 or BF16");
+    if (!src || !children_out) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
-    if (n_t > 1 && snapshot_stride < tree->n_leaves)
-        return fail(FPO_E_INVALID, "snapshot_stride < n_leaves");
+    if (n_t > 1 && stride < tree->n_leaves) return fail(FPO_E_INVALID, "stride between times < n_leaves");
     if ((((uintptr_t)tree->children) | ((uintptr_t)children_out)) & 15)
         return fail(FPO_E_INVALID, "children and children_out must be 16-byte aligned");
     const int64_t rows = tree->n_nodes * (int64_t)n_t;
@@ -218,30 +227,51 @@ extern "C" fpo_status fpo_prune_at(const fpo_tree_view* tree, const void* snapsh
     dev::PruneLaunch a;
     a.children = tree->children;
     a.out = children_out;
-    a.snap = snapshots;
-    a.snap_stride = snapshot_stride;
+    a.snap = src;
+    a.snap_stride = stride;
     a.n_nodes = tree->n_nodes;
     a.n_t = n_t;
     a.n_leaves = (int32_t)tree->n_leaves;
     a.sigma_scale = tree->layout.sigma_scale;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const unsigned grid = (unsigned)((rows + dev::kBlock - 1) / dev::kBlock);
-    if (snapshot_dtype == FPO_F32)
+    if (kind == FPO_F32)
         hipLaunchKernelGGL(dev::prune_leaves_kernel<FPO_F32>, dim3(grid), dim3(dev::kBlock), 0, s, a);
-    else
+    else if (kind == FPO_BF16)
         hipLaunchKernelGGL(dev::prune_leaves_kernel<FPO_BF16>, dim3(grid), dim3(dev::kBlock), 0, s, a);
-    if ((st = launch_status("fpo_prune_at")) != FPO_OK) return st;
+    else
+        hipLaunchKernelGGL(dev::prune_leaves_kernel<dev::kSigmaPlane>, dim3(grid), dim3(dev::kBlock), 0, s, a);
+    if ((st = launch_status(name)) != FPO_OK) return st;
     for (int pass = 1; pass < tree->max_depth; ++pass) {
         hipLaunchKernelGGL(dev::prune_nodes_kernel, dim3(grid), dim3(dev::kBlock), 0, s, a);
-        if ((st = launch_status("fpo_prune_at")) != FPO_OK) return st;
+        if ((st = launch_status(name)) != FPO_OK) return st;
     }
     return FPO_OK;
+}
+
+}  // namespace
+
+extern "C" fpo_status fpo_prune_at(const fpo_tree_view* tree, const void* snapshots, fpo_dtype snapshot_dtype,
+                                   int64_t snapshot_stride, int32_t n_t, int32_t* children_out, void* stream)
+{
+    ApiRange api_range_("fpo_prune_at");
+    if (snapshot_dtype != FPO_F32 && snapshot_dtype != FPO_BF16)
+        return fail(FPO_E_INVALID, "snapshot_dtype must be F32 or BF16");
+    return prune_impl(tree, snapshots, snapshot_dtype, snapshot_stride, n_t, children_out, stream, "fpo_prune_at");
+}
+
+extern "C" fpo_status fpo_prune_at_sigma(const fpo_tree_view* tree, const float* sigma, int64_t sigma_stride,
+                                         int32_t n_t, int32_t* children_out, void* stream)
+{
+    ApiRange api_range_("fpo_prune_at_sigma");
+    return prune_impl(tree, sigma, dev::kSigmaPlane, sigma_stride, n_t, children_out, stream, "fpo_prune_at_sigma");
 }
 
 extern "C" fpo_status fpo_coarse_occupancy_at(const int32_t* leaf_cells, int64_t n_leaves, int32_t max_depth,
                                               const void* snapshot, fpo_dtype snapshot_dtype, float sigma_scale,
                                               uint32_t* bits_out, void* stream)
 {
+    ApiRange api_range_("fpo_coarse_occupancy_at");
     if (!leaf_cells || !snapshot || !bits_out) return fail(FPO_E_INVALID, "NULL device pointer");
     if (n_leaves < 1 || n_leaves > INT32_MAX - 1) return fail(FPO_E_INVALID, "n_leaves out of range");
     if (max_depth < 1 || max_depth > FPO_MAX_DEPTH) return fail(FPO_E_INVALID, "max_depth must be in 1..10");

@@ -1,5 +1,6 @@
-"""GPU tests of the occupancy at one time: fpo_prune_at (per-time child tables
-in which subtrees without an opaque leaf are empty) and
+"""GPU tests of the occupancy at one time: fpo_prune_at and
+fpo_prune_at_sigma (per-time child tables in which subtrees without an opaque
+leaf are empty, from snapshot records or the bake's density plane) and
 fpo_coarse_occupancy_at (the dilated 64^3 grid over the leaves opaque at
 that time).  Inputs that decide opacity are the oracle's bake, rounded to the
 snapshot's precision, so the expected tables follow from the paper's Eq. 7
@@ -135,6 +136,68 @@ def test_render_through_pruned_tables(oracle_lib, dev, dtype):
         check_parity(got_prop.cpu().numpy().reshape(-1, 3), ref, 1e-4)
 
 
+# (store, n_t): each bake kernel (per-frame FMA kernels below 4 times, MFMA
+# tiles from 4 on, ragged 16-time tiles; F32, BF16 and FP8 stores) and the
+# layout kernel
+SIGMA_PLANE_CASES = [(_lib.FPO_F32, 1), (_lib.FPO_F32, 3), (_lib.FPO_F32, 10), (_lib.FPO_F32, 21),
+                     (_lib.FPO_BF16, 2), (_lib.FPO_BF16, 5), (_lib.FPO_FP8_E4M3, 2), (_lib.FPO_FP8_E4M3, 17),
+                     ("layout_21_11", 2)]
+
+
+@pytest.mark.parametrize("store,n_t", SIGMA_PLANE_CASES)
+@pytest.mark.parametrize("out_dtype", [_lib.FPO_F32, _lib.FPO_BF16])
+def test_bake_sigma_plane_is_record_value(dev, store, n_t, out_dtype):
+    """fpo_bake_times sigma_out holds value 0 of every record it writes, as
+    FP32, bit for bit; slots past n_leaves are left alone."""
+    import torch
+    if store == "layout_21_11" and out_dtype != _lib.FPO_F32:
+        pytest.skip("other layouts bake into F32 snapshots only")
+    dijk = synth.random_tree_leaves(13, 6, p_split=0.6)
+    n = len(dijk)
+    if store == "layout_21_11":
+        k = synth.gaussian_coeffs(n, seed=13, n_sigma=21, n_sh_fourier=11)
+        tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=n + 7, n_sigma=21, n_sh_fourier=11)
+        layout = _lib.make_layout(n_sigma=21)
+    else:
+        k = synth.gaussian_coeffs(n, seed=13)
+        tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=n + 7)
+        if store != _lib.FPO_F32:
+            tree = _lib.quantize(tree, store)
+        layout = _lib.make_layout()
+    times = [0.7 + i * 59.0 / n_t for i in range(n_t)]
+    basis = torch.from_numpy(_lib.time_basis(times, layout)).to(dev)
+    sigma = torch.full((n_t, tree.leaf_stride), float("nan"), dtype=torch.float32, device=dev)
+    note(f"fpo_bake_times sigma_out store={store} n_t={n_t} out={out_dtype}")
+    out = _lib.bake_times(tree, basis, out_dtype, sigma_out=sigma)
+    torch.cuda.synchronize()
+    rec0 = out[:, :n, 0].float().cpu().numpy()
+    got = sigma.cpu().numpy()
+    assert np.array_equal(got[:, :n].view(np.uint32), rec0.view(np.uint32))
+    assert np.isnan(got[:, n:]).all()
+    assert (rec0 > 0).any() and (rec0 <= 0).any()
+
+
+def test_prune_at_sigma_equals_prune_at(dev):
+    """Tables pruned from the density plane equal those pruned from the
+    records (F32 and BF16 snapshots, 12 times of a depth-7 blob scene)."""
+    import torch
+    dijk = synth.blob_leaves(7, 40000)
+    k = synth.gaussian_coeffs(len(dijk), seed=5)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev, leaf_stride=len(dijk) + 9)
+    times = [2.5 * i + 0.1 for i in range(12)]
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    for dt in (_lib.FPO_F32, _lib.FPO_BF16):
+        sigma = torch.empty((len(times), tree.leaf_stride), dtype=torch.float32, device=dev)
+        note(f"fpo_prune_at_sigma against fpo_prune_at dtype={dt}")
+        snaps = _lib.bake_times(tree, basis, dt, sigma_out=sigma)
+        a = _lib.prune_at(tree, snaps, dt)
+        b = _lib.prune_at_sigma(tree, sigma)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        kept = (a != 0).sum().item() / (len(times) * (tree.children != 0).sum().item())
+        assert 0.2 < kept < 0.95, kept
+
+
 def test_c2_pruned_decode_sampled(oracle_lib, dev):
     """The pruned decode path at full size: the 2M-leaf scene, the step's 10
     times baked into F32 snapshots and pruned in one call each, 16 cameras of
@@ -149,8 +212,10 @@ def test_c2_pruned_decode_sampled(oracle_lib, dev):
     times = [cams[j * per].time for j in range(n_t)]
     basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
     note("c2 decode + prune at 10 times")
-    snap = _lib.bake_times(tree, basis, _lib.FPO_F32)
-    pruned = _lib.prune_at(tree, snap, _lib.FPO_F32)
+    sigma = torch.empty((n_t, tree.leaf_stride), dtype=torch.float32, device=dev)
+    snap = _lib.bake_times(tree, basis, _lib.FPO_F32, sigma_out=sigma)
+    pruned = _lib.prune_at_sigma(tree, sigma)
+    assert torch.equal(pruned, _lib.prune_at(tree, snap, _lib.FPO_F32))
     torch.cuda.synchronize()
     kept = (pruned != 0).sum(dim=(1, 2)).cpu().numpy() / float((tree.children != 0).sum())
     assert np.all(kept < 0.95), kept

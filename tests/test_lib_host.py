@@ -265,6 +265,30 @@ def test_prune_leaves():
 
 
 @host_only
+def test_prune_entries_validate_before_launching():
+    """fpo_prune_at and fpo_prune_at_sigma reject bad arguments on the host
+    (nothing is launched: the pointers are fake)."""
+    L = _lib.lib()
+    view = _lib.TreeView()
+    view.children = 16
+    view.n_nodes = 4
+    view.max_depth = 3
+    view.n_leaves = 10
+    view.leaf_stride = 10
+    view.layout = _lib.make_layout()
+    p = ctypes.c_void_p(64)
+    tv = ctypes.byref(view)
+    assert L.fpo_prune_at_sigma(tv, None, 10, 1, p, None) == _lib.FPO_E_INVALID              # no plane
+    assert L.fpo_prune_at_sigma(tv, p, 10, 0, p, None) == _lib.FPO_E_INVALID                 # n_t < 1
+    assert L.fpo_prune_at_sigma(tv, p, 9, 2, p, None) == _lib.FPO_E_INVALID                  # times overlap
+    assert L.fpo_prune_at_sigma(tv, p, 10, 1, ctypes.c_void_p(72), None) == _lib.FPO_E_INVALID   # unaligned out
+    assert L.fpo_prune_at_sigma(None, p, 10, 1, p, None) == _lib.FPO_E_INVALID
+    assert L.fpo_prune_at(tv, p, _lib.FPO_FP8_E4M3, 10, 1, p, None) == _lib.FPO_E_INVALID      # record dtype
+    assert L.fpo_prune_at(tv, p, _lib.FPO_F32, 9, 2, p, None) == _lib.FPO_E_INVALID
+    assert "stride" in L.fpo_last_error().decode()
+
+
+@host_only
 def test_other_layouts_are_limited_to_render_pack_and_bake():
     """Layouts (n1, n2) other than (31, 5) pass validation only where they are
     compiled; unknown layouts are rejected everywhere."""
@@ -284,7 +308,7 @@ def test_other_layouts_are_limited_to_render_pack_and_bake():
     assert st == _lib.FPO_E_UNSUPPORTED
     st = L.fpo_render_backward(ctypes.byref(view), p, p, p, p, 1, 1, ctypes.byref(opts), p, p, p, None)
     assert st == _lib.FPO_E_UNSUPPORTED
-    st = L.fpo_bake_times(ctypes.byref(view), p, 1, _lib.FPO_BF16, p, None)
+    st = L.fpo_bake_times(ctypes.byref(view), p, 1, _lib.FPO_BF16, p, None, None)
     assert st == _lib.FPO_E_UNSUPPORTED
     # a skipping render or a quantised store with the layout
     o2 = _lib.make_opts(flags=_lib.FPO_RENDER_SKIP_COARSE)
