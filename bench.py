@@ -909,6 +909,8 @@ def main():
     ap.add_argument("--render-modes", default="fourier,decode,decode_pruned",
                     help="comma-separated render paths to time (with --no-cpu, e.g. one path for a clean profile)")
     ap.add_argument("--no-finetune", action="store_true")
+    ap.add_argument("--no-grandchild", action="store_true",
+                    help="decode modes: walk the child tables one level per read (no two-level tables)")
     ap.add_argument("--no-bake", action="store_true")
     ap.add_argument("--ft-steps", type=int, default=40)
     ap.add_argument("--no-proposal", action="store_true")
@@ -984,8 +986,15 @@ def main():
     rays_step = len(cams) * W * H
 
     pruned = torch.empty((n_t, tree.n_nodes, 8), dtype=torch.int32, device=dev)
-    pruned_trees = [_lib.tree_with_children(tree, pruned[j]) for j in range(n_t)]
     sigma_plane = torch.empty((n_t, tree.leaf_stride), dtype=torch.float32, device=dev)
+    # two-level tables: the union table's once (a static companion of the child
+    # table), the pruned tables' in every step
+    two = not args.no_grandchild
+    gc_union = _lib.grandchild_tables(tree) if two else None
+    gc_pruned = (torch.empty((n_t, tree.upper(), 64, 2), dtype=torch.int32, device=dev) if two else None)
+    union_tree = _lib.tree_with_children(tree, tree.children, None if gc_union is None else gc_union[0])
+    pruned_trees = [_lib.tree_with_children(tree, pruned[j], None if gc_pruned is None else gc_pruned[j])
+                    for j in range(n_t)]
 
     def run_mode(mode, frames, steps, warmup):
         """Time `steps` steps of 160 frames.  mode 'fourier': one fpo_render
@@ -995,8 +1004,10 @@ def main():
         snapshot-mode fpo_render launch per time point for its 16 cameras.
         mode 'decode_pruned': the decode step, the bake also writing its density
         plane, plus one fpo_prune_at_sigma of the 10 times (per-time child
-        tables without the subtrees that are transparent at that time), each
-        time's cameras walking its table."""
+        tables without the subtrees that are transparent at that time) and one
+        fpo_grandchild_tables of them, each time's cameras walking its table.
+        The decode modes descend two levels per read (two-level tables) unless
+        --no-grandchild."""
         decode = mode.startswith("decode")
         def step(ev_r=None, ev_b=None):
             if decode:
@@ -1005,6 +1016,8 @@ def main():
                 if mode == "decode_pruned":
                     _lib.bake_times(tree, basis_j, _lib.FPO_F32, out=snap, sigma_out=sigma_plane)
                     _lib.prune_at_sigma(tree, sigma_plane, out=pruned)
+                    if two:
+                        _lib.grandchild_tables(tree, pruned, out=gc_pruned)
                 else:
                     _lib.bake_times(tree, basis_j, _lib.FPO_F32, out=snap)
                 if ev_b is not None:
@@ -1012,7 +1025,7 @@ def main():
             for j in range(n_t):
                 if ev_r is not None:
                     ev_r[j][0].record(stream)
-                tr = pruned_trees[j] if mode == "decode_pruned" else tree
+                tr = pruned_trees[j] if mode == "decode_pruned" else union_tree if decode else tree
                 _lib.render(tr, cams[j * per:(j + 1) * per], opts_s[j] if decode else opts_f,
                             rgb=frames[j * per:(j + 1) * per])
                 if ev_r is not None:
@@ -1171,7 +1184,9 @@ def main():
             "workload": "depth-9 union octree, 2.0M leaves x 166 FP32 coeffs (moving 8-Gaussian blob over 60 frames); "
                         "16 ring cameras x 10 times, 1920x1080, early termination T<1e-3",
             "rays_per_step": rays_step,
-            "launches_per_step": {"fourier": n_t, "decode": n_t + 1, "decode_pruned": n_t + 1 + sc.max_depth}[best],
+            "launches_per_step": {"fourier": n_t, "decode": n_t + 1,
+                                  "decode_pruned": n_t + 1 + sc.max_depth + (1 if two else 0)}[best],
+            "two_level_tables": two and best != "fourier",
         },
         "fps_1080p": round(fps, 2),
         "render_path": best,

@@ -121,6 +121,11 @@ typedef struct {
     int64_t n_leaves;
     int64_t leaf_stride;
     fpo_layout layout;
+    const int32_t* grandchildren; /* device [n_grandchild_rows][64][2] int32 from fpo_grandchild_tables
+                                     of this view's children, or NULL.  Walks then descend two levels per
+                                     read from the nodes it covers.  8-byte aligned. */
+    int64_t n_grandchild_rows;    /* rows of grandchildren: nodes 0 .. n - 1 (1 .. min(n_nodes, 2^22 - 1));
+                                     ignored when grandchildren is NULL */
 } fpo_tree_view;
 
 /* Pinhole camera: ray through pixel centre (u + 0.5, v + 0.5), row 0 at the
@@ -407,6 +412,22 @@ fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* basis, int32_t
  * Launches max_depth kernels; no allocation. */
 fpo_status fpo_prune_at(const fpo_tree_view* tree, const void* snapshots, fpo_dtype snapshot_dtype,
                         int64_t snapshot_stride, int32_t n_t, int32_t* children_out, void* stream);
+
+/* Two-level child tables for the walks' descents: one 8-byte read per two
+ * levels instead of one 4-byte read per level.  Any child table (the union
+ * octree's or a per-time table of fpo_prune_at) may be expanded; a view that
+ * carries the result (fpo_tree_view.grandchildren) walks exactly the slots of
+ * its children table, so every result is the same.
+ *   children  device [n_t][n_nodes][8] int32, 16-byte aligned.
+ *   n_rows    nodes 0 .. n_rows - 1 expanded (1 .. min(n_nodes, 2^22 - 1)).
+ *             Nodes are numbered breadth first, so the nodes that have an
+ *             internal child come first; expanding just those is enough.
+ *   out       device [n_t][n_rows][64][2] int32, 16-byte aligned:
+ *             out[t][x][8a + b] = (c, g) with c = children[t][x][a] and g =
+ *             children[t][c][b] if 0 < c < n_nodes, else 0.
+ * One kernel; no allocation. */
+fpo_status fpo_grandchild_tables(const int32_t* children, int64_t n_nodes, int32_t n_t, int64_t n_rows,
+                                 int32_t* out, void* stream);
 
 /* fpo_prune_at with sigma(t) read from a density plane (fpo_bake_times
  * sigma_out) instead of the records: the same tables, from 4 bytes per leaf

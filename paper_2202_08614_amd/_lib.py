@@ -52,7 +52,7 @@ class TreeView(ctypes.Structure):
                 ("max_depth", ctypes.c_int32), ("coeffs", ctypes.c_void_p),
                 ("leaf_scale", ctypes.c_void_p), ("dtype", ctypes.c_int),
                 ("n_leaves", ctypes.c_int64), ("leaf_stride", ctypes.c_int64),
-                ("layout", Layout)]
+                ("layout", Layout), ("grandchildren", ctypes.c_void_p), ("n_grandchild_rows", ctypes.c_int64)]
 
 
 class CameraC(ctypes.Structure):
@@ -126,6 +126,7 @@ _SIGS = {
     "fpo_fusion_apply": [_P, _P, _P, _P, _I64, _P],
     "fpo_prune_at": [ctypes.POINTER(TreeView), _P, ctypes.c_int, _I64, _I32, _P, _P],
     "fpo_prune_at_sigma": [ctypes.POINTER(TreeView), _P, _I64, _I32, _P, _P],
+    "fpo_grandchild_tables": [_P, _I64, _I32, _I64, _P, _P],
     "fpo_coarse_occupancy_at": [_P, _I64, _I32, _P, ctypes.c_int, ctypes.c_float, _P, _P],
 }
 # functions with another return type
@@ -276,8 +277,13 @@ class DeviceTree:
     scales."""
 
     def __init__(self, children, n_nodes: int, max_depth: int, coeffs, scale, dtype: int,
-                 n_leaves: int, leaf_stride: int, perm: np.ndarray, layout: Layout):
+                 n_leaves: int, leaf_stride: int, perm: np.ndarray, layout: Layout,
+                 n_upper: Optional[int] = None, grandchildren=None):
         self.children = children
+        # nodes that have an internal child (numbered first, breadth first); None: not known yet
+        self.n_upper = n_upper
+        # two-level table of `children` (fpo_grandchild_tables), or None
+        self.grandchildren = grandchildren
         self.n_nodes = int(n_nodes)
         self.max_depth = int(max_depth)
         self.coeffs = coeffs
@@ -305,11 +311,18 @@ class DeviceTree:
         pack_coeffs(src, perm_d, n, stride, recs, layout)
         del src
         return cls(torch.from_numpy(children).to(device), children.shape[0], max_depth, recs, None,
-                   FPO_F32, n, stride, perm, layout)
+                   FPO_F32, n, stride, perm, layout, n_upper=upper_rows(children))
 
     def with_store(self, coeffs, scale, dtype: int) -> "DeviceTree":
         return DeviceTree(self.children, self.n_nodes, self.max_depth, coeffs, scale, dtype,
-                          self.n_leaves, self.leaf_stride, self.perm, self.layout)
+                          self.n_leaves, self.leaf_stride, self.perm, self.layout, self.n_upper,
+                          self.grandchildren)
+
+    def upper(self) -> int:
+        """Nodes with an internal child (computed from the child table once)."""
+        if self.n_upper is None:
+            self.n_upper = upper_rows(self.children.cpu().numpy())
+        return self.n_upper
 
     def view(self) -> TreeView:
         v = TreeView()
@@ -322,7 +335,18 @@ class DeviceTree:
         v.n_leaves = self.n_leaves
         v.leaf_stride = self.leaf_stride
         v.layout = self.layout
+        if self.grandchildren is not None:
+            v.grandchildren = self.grandchildren.data_ptr()
+            v.n_grandchild_rows = int(self.grandchildren.shape[-3])
         return v
+
+
+def upper_rows(children: np.ndarray) -> int:
+    """1 + the last node that has an internal child: with breadth-first
+    numbering those nodes are exactly 0 .. n - 1 (a child table of a pruned
+    time has no more of them)."""
+    has = (np.asarray(children) > 0).any(axis=1)
+    return int(np.nonzero(has)[0][-1]) + 1 if has.any() else 0
 
 
 # ---------------------------------------------------------------------------
@@ -701,13 +725,33 @@ def prune_at_sigma(tree: DeviceTree, sigma, out=None):
     return out
 
 
-def tree_with_children(tree: DeviceTree, children) -> "DeviceTree":
+def tree_with_children(tree: DeviceTree, children, grandchildren=None) -> "DeviceTree":
     """The same tree (coefficients, leaves) walked through another child table
-    of the same shape, e.g. one time of prune_at's output."""
+    of the same shape, e.g. one time of prune_at's output, and optionally that
+    table's two-level table (one time of grandchild_tables' output)."""
     if tuple(children.shape) != (tree.n_nodes, 8):
         raise ValueError("child table shape differs")
+    if grandchildren is not None and (grandchildren.dim() != 3 or tuple(grandchildren.shape[1:]) != (64, 2)):
+        raise ValueError("grandchildren must be [rows][64][2]")
     return DeviceTree(children, tree.n_nodes, tree.max_depth, tree.coeffs, tree.scale, tree.dtype, tree.n_leaves,
-                      tree.leaf_stride, tree.perm, tree.layout)
+                      tree.leaf_stride, tree.perm, tree.layout, tree.n_upper, grandchildren)
+
+
+def grandchild_tables(tree: DeviceTree, children=None, n_rows: Optional[int] = None, out=None):
+    """fpo_grandchild_tables of `children` ([n_t][n_nodes][8], default: the
+    tree's own table) over its first n_rows nodes (default: the nodes with an
+    internal child) -> [n_t][n_rows][64][2] int32."""
+    import torch
+    ch = tree.children if children is None else children
+    ch3 = ch if ch.dim() == 3 else ch[None]
+    n_t = int(ch3.shape[0])
+    rows = int(n_rows if n_rows is not None else tree.upper())
+    if rows < 1:
+        raise ValueError("no node has an internal child")
+    if out is None:
+        out = torch.empty((n_t, rows, 64, 2), dtype=torch.int32, device=ch3.device)
+    _check(lib().fpo_grandchild_tables(_t_ptr(ch3), tree.n_nodes, n_t, rows, _t_ptr(out), _stream()))
+    return out
 
 
 def leaf_cells_slot_order(leaf_dijk: np.ndarray, perm: np.ndarray, device):

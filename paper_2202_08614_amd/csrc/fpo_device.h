@@ -28,6 +28,8 @@ struct TreeDev {
     int32_t n_leaves;
     int32_t max_depth;
     float sigma_scale;
+    const int2* gc;         // two-level table [n_gc][64] (children, grandchild), or null
+    int32_t n_gc;           // rows of gc (0 without one)
 };
 
 // Host helper: the kernel-side view of a validated fpo_tree_view.
@@ -35,6 +37,8 @@ inline TreeDev tree_dev(const fpo_tree_view* t)
 {
     TreeDev d;
     d.children = t->children;
+    d.gc = reinterpret_cast<const int2*>(t->grandchildren);
+    d.n_gc = t->grandchildren ? (int32_t)t->n_grandchild_rows : 0;
     d.recs = static_cast<const uint4*>(t->coeffs);
     d.scale = t->leaf_scale;
     d.stride = t->leaf_stride;
@@ -181,7 +185,8 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 //   - descend while the current slot holds an internal node: the ray's cell
 //     on the finest lattice at t_cur (x + t_cur / k per axis, clamped into
 //     the slot) is found once, and each level's octant is one bit of it per
-//     axis;
+//     axis; from a node the two-level table covers, one read gives both the
+//     child's and the grandchild's entries;
 //   - report a leaf segment [t_cur, t_exit), t_exit the first upper face the
 //     ray reaches (ties x < y < z);
 //   - step to the neighbouring slot of the same size across that face (the
@@ -210,7 +215,9 @@ struct NoStop {
     __device__ inline bool more(float, float&) { return false; }
 };
 
-template <class Visitor, class Stop>
+// TWO: descend through the two-level table where the tree has one (the
+// snapshot camera renders; elsewhere the extra registers cost occupancy).
+template <bool TWO = false, class Visitor, class Stop>
 __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop)
 {
     // The child table is read through a buffer resource: 32-bit byte offsets
@@ -218,6 +225,9 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
     // returns 0 (an empty slot).
     const __amdgpu_buffer_rsrc_t ct =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(T.children), (short)0, T.n_nodes * 32, 0x00020000);
+    // the two-level table, 512 bytes per row (absent: no rows, never read)
+    const __amdgpu_buffer_rsrc_t gt =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<int2*>(T.gc), (short)0, T.n_gc * 512, 0x00020000);
     const int D = T.max_depth;
     const int G = 1 << D;
     const float fG = (float)G;
@@ -270,10 +280,26 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
             do {
                 stk[csh * kBlock] = no;    // the node and the child the ray is in
                 csh -= 1;
-                const int bits = __builtin_amdgcn_ubfe(q[0], csh, 1) | (__builtin_amdgcn_ubfe(q[1], csh, 1) << 1) |
-                                 (__builtin_amdgcn_ubfe(q[2], csh, 1) << 2);
-                no = (ch << 3) | (bits ^ mirror);
-                ch = __builtin_amdgcn_raw_buffer_load_b32(ct, no * 4, 0, 0);
+                const int bits = (__builtin_amdgcn_ubfe(q[0], csh, 1) | (__builtin_amdgcn_ubfe(q[1], csh, 1) << 1) |
+                                  (__builtin_amdgcn_ubfe(q[2], csh, 1) << 2)) ^ mirror;
+                if (TWO && ch < T.n_gc && csh > 0) {
+                    // two levels in one read: (child entry, grandchild entry)
+                    const int b2 = (__builtin_amdgcn_ubfe(q[0], csh - 1, 1) |
+                                    (__builtin_amdgcn_ubfe(q[1], csh - 1, 1) << 1) |
+                                    (__builtin_amdgcn_ubfe(q[2], csh - 1, 1) << 2)) ^ mirror;
+                    const auto e = __builtin_amdgcn_raw_buffer_load_b64(gt, (ch * 64 + bits * 8 + b2) * 8, 0, 0);
+                    no = (ch << 3) | bits;
+                    ch = e[0];
+                    if (ch > 0 && ch < T.n_nodes) {
+                        stk[csh * kBlock] = no;
+                        csh -= 1;
+                        no = (ch << 3) | b2;
+                        ch = e[1];
+                    }
+                } else {
+                    no = (ch << 3) | bits;
+                    ch = __builtin_amdgcn_raw_buffer_load_b32(ct, no * 4, 0, 0);
+                }
             } while (ch > 0 && ch < T.n_nodes && csh > 0);
             const int m = -1 << csh;
 #pragma unroll
@@ -321,11 +347,11 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
     }
 }
 
-template <class Visitor>
+template <bool TWO = false, class Visitor>
 __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
 {
     NoStop ns;
-    walk(T, r, stk, vis, __builtin_inff(), ns);
+    walk<TWO>(T, r, stk, vis, __builtin_inff(), ns);
 }
 
 // Record geometry of a coefficient layout (n1 density terms, n2 terms per SH
@@ -471,27 +497,36 @@ struct Shade {
     __device__ inline bool segment(int leaf, float t0, float t1)
     {
         const float delta = t1 - t0;
-        float sraw, h[3];
+        float h[3];
         if constexpr (MODE >= 16) {
+            // only the optical depth sigma_eff * delta stays live through the
+            // colour reads (the 64-VGPR budget of the snapshot render)
             constexpr int SDT = MODE - 16;
             float v[32];
+            float sraw;
             if constexpr (BUF) sraw = SnapEval<SDT>::sigma(srs, leaf, v);
             else sraw = SnapEval<SDT>::sigma(snap, leaf, v);
-            const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
-            if (!(sig * delta > 0.0f)) return false;
+            const float od = T.sigma_scale * fmaxf(sraw, 0.0f) * delta;
+            if (!(od > 0.0f)) return false;
             if constexpr (BUF) SnapEval<SDT>::colour(srs, leaf, Y, v, h);
             else SnapEval<SDT>::colour(snap, leaf, Y, v, h);
+            return composite(__expf(-od), h);
         } else {
             using E = LeafEval<MODE, N1, N2>;
             float k[E::kSigmaWords * E::W];
             float scale;
-            sraw = E::sigma(T, leaf, b, k, scale);
+            const float sraw = E::sigma(T, leaf, b, k, scale);
             const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
             if (!(sig * delta > 0.0f)) return false;   // transparent: contributes nothing
             E::colour(T, leaf, b, Y, k, scale, h);
+            return composite(__expf(-sig * delta), h);
         }
-        const float sig = T.sigma_scale * fmaxf(sraw, 0.0f);
-        const float e = __expf(-sig * delta);
+    }
+
+    // Front-to-back compositing of a segment of transmittance e and SH sums h;
+    // true once the ray's transmittance is below stop_T.
+    __device__ inline bool composite(float e, const float* h)
+    {
         const float w = Tr * (1.0f - e);
 #pragma unroll
         for (int c = 0; c < 3; ++c) C[c] = fmaf(w, sigmoidf_(h[c]), C[c]);

@@ -69,6 +69,14 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_la
     if (!(L.period > 0.0f) || !std::isfinite(L.period)) return fail(FPO_E_INVALID, "layout.period must be > 0");
     if (!(L.sigma_scale >= 0.0f) || !std::isfinite(L.sigma_scale))
         return fail(FPO_E_INVALID, "layout.sigma_scale must be finite and >= 0");
+    if (tree->grandchildren) {
+        // 32-bit byte offsets into the two-level table: 512 bytes per row
+        if (tree->n_grandchild_rows < 1 || tree->n_grandchild_rows > tree->n_nodes ||
+            tree->n_grandchild_rows > INT32_MAX / 512)
+            return fail(FPO_E_INVALID, "tree->n_grandchild_rows out of range");
+        if (reinterpret_cast<uintptr_t>(tree->grandchildren) & 7)
+            return fail(FPO_E_INVALID, "tree->grandchildren must be 8-byte aligned");
+    }
     if (need_coeffs) {
         if (!tree->coeffs) return fail(FPO_E_INVALID, "tree->coeffs is NULL");
         if (tree->dtype != FPO_F32 && tree->dtype != FPO_BF16 && tree->dtype != FPO_FP8_E4M3)

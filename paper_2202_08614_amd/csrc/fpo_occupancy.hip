@@ -122,6 +122,31 @@ __global__ __launch_bounds__(kBlock) void prune_nodes_kernel(PruneLaunch a)
     }
 }
 
+// Two-level tables: one thread per (time, node, child octant a) writes the
+// 8 entries (c, g_b), b < 8, of its 64-byte run: c = children[x][a] and g_b
+// the entries of c's row when c is an internal node (else 0).
+__global__ __launch_bounds__(kBlock) void grandchild_kernel(const int32_t* children, int64_t n_nodes, int32_t n_t,
+                                                            int64_t n_rows, int2* out)
+{
+    const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (id >= n_rows * 8 * n_t) return;
+    const int64_t per_t = n_rows * 8;
+    const int t = (int)(id / per_t);
+    const int64_t xa = id - (int64_t)t * per_t;             // x * 8 + a
+    const int32_t* tab = children + (int64_t)t * n_nodes * 8;
+    const int c = tab[xa];
+    int g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (c > 0 && c < n_nodes) {
+        const int4* row = reinterpret_cast<const int4*>(tab + (int64_t)c * 8);
+        const int4 r0 = row[0], r1 = row[1];
+        g[0] = r0.x; g[1] = r0.y; g[2] = r0.z; g[3] = r0.w;
+        g[4] = r1.x; g[5] = r1.y; g[6] = r1.z; g[7] = r1.w;
+    }
+    int4* o = reinterpret_cast<int4*>(out + ((int64_t)t * n_rows * 64 + xa * 8));
+#pragma unroll
+    for (int b = 0; b < 4; ++b) o[b] = make_int4(c, g[2 * b], c, g[2 * b + 1]);
+}
+
 struct OccLaunch {
     const int4* cells;         // [n_leaves] (depth, i, j, k), slot order
     const void* snap;
@@ -296,4 +321,22 @@ extern "C" fpo_status fpo_coarse_occupancy_at(const int32_t* leaf_cells, int64_t
         hipLaunchKernelGGL(dev::occupancy_mark_kernel<FPO_BF16>, dim3(grid), dim3(dev::kBlock), 0, s, a);
     hipLaunchKernelGGL(dev::occupancy_dilate_kernel, dim3(1), dim3(1024), 0, s, bits_out);
     return launch_status("fpo_coarse_occupancy_at");
+}
+
+extern "C" fpo_status fpo_grandchild_tables(const int32_t* children, int64_t n_nodes, int32_t n_t, int64_t n_rows,
+                                            int32_t* out, void* stream)
+{
+    ApiRange api_range_("fpo_grandchild_tables");
+    if (!children || !out) return fail(FPO_E_INVALID, "NULL device pointer");
+    if (n_nodes < 1 || n_nodes > INT32_MAX / 32) return fail(FPO_E_INVALID, "n_nodes out of range");
+    if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
+    if (n_rows < 1 || n_rows > n_nodes || n_rows > INT32_MAX / 512) return fail(FPO_E_INVALID, "n_rows out of range");
+    if (((uintptr_t)children & 15) || ((uintptr_t)out & 15))
+        return fail(FPO_E_INVALID, "children and out must be 16-byte aligned");
+    const int64_t threads = n_rows * 8 * (int64_t)n_t;
+    if (threads > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many rows");
+    hipLaunchKernelGGL(dev::grandchild_kernel, dim3((unsigned)((threads + dev::kBlock - 1) / dev::kBlock)),
+                       dim3(dev::kBlock), 0, static_cast<hipStream_t>(stream), children, n_nodes, n_t, n_rows,
+                       reinterpret_cast<int2*>(out));
+    return launch_status("fpo_grandchild_tables");
 }

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kBlock, BUF ? 8 : 1) void render_cam_kernel(CamLaun
     if (setup_ray(cam.frame[0], cam.frame[1], cam.frame[2], dx, dy, dz, r)) {
         sh9(r.d[0], r.d[1], r.d[2], sh.Y);
         if constexpr (!SKIP) {
-            walk(a.tree, r, s_stack + threadIdx.x, sh);
+            walk<(MODE >= 16)>(a.tree, r, s_stack + threadIdx.x, sh);
         } else {
             const float2 se = a.skip[pix];
             if (se.x < r.t_len) {
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock, BUF ? 8 : 1) void render_cam_kernel(CamLaun
                 for (int c = 0; c < 3; ++c) r.o[c] = fmaf(se.x, r.d[c], r.o[c]);
                 r.t_len -= se.x;
                 NoStop ns;
-                walk(a.tree, r, s_stack + threadIdx.x, sh, se.y - se.x, ns);
+                walk<(MODE >= 16)>(a.tree, r, s_stack + threadIdx.x, sh, se.y - se.x, ns);
             }
         }
     }

@@ -198,6 +198,89 @@ def test_prune_at_sigma_equals_prune_at(dev):
         assert 0.2 < kept < 0.95, kept
 
 
+def _grandchild_reference(children: np.ndarray, rows: int) -> np.ndarray:
+    """The two-level table from its definition: (c, children[c][b]) for
+    internal c, else (c, 0)."""
+    n = children.shape[0]
+    out = np.zeros((rows, 8, 8, 2), np.int32)
+    c = children[:rows]                                   # [rows][8]
+    out[..., 0] = c[:, :, None]
+    inner = (c > 0) & (c < n)
+    out[..., 1] = np.where(inner[:, :, None], children[np.where(inner, c, 0)], 0)
+    return out.reshape(rows, 64, 2)
+
+
+def test_grandchild_tables_match_definition(dev):
+    """fpo_grandchild_tables of the union table and of three pruned tables
+    equal the definition; the rows cover exactly the nodes with an internal
+    child (breadth-first numbering puts them first)."""
+    import torch
+    dijk = synth.blob_leaves(7, 40000)
+    k = synth.gaussian_coeffs(len(dijk), seed=21)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev)
+    children = tree.children.cpu().numpy()
+    depth = np.zeros(len(children), int)
+    for i in range(len(children)):
+        depth[children[i][children[i] > 0]] = depth[i] + 1
+    assert np.all(np.diff(depth) >= 0)
+    assert tree.upper() == int(np.nonzero((children > 0).any(1))[0][-1]) + 1 < len(children)
+    times = [3.0, 31.5, 47.25]
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    sigma = torch.empty((3, tree.leaf_stride), dtype=torch.float32, device=dev)
+    _lib.bake_times(tree, basis, _lib.FPO_F32, sigma_out=sigma)
+    pruned = _lib.prune_at_sigma(tree, sigma)
+    note("fpo_grandchild_tables union and 3 pruned tables")
+    g_union = _lib.grandchild_tables(tree)
+    g_pruned = _lib.grandchild_tables(tree, pruned)
+    g_all = _lib.grandchild_tables(tree, n_rows=tree.n_nodes)
+    torch.cuda.synchronize()
+    rows = tree.upper()
+    assert np.array_equal(g_union[0].cpu().numpy(), _grandchild_reference(children, rows))
+    assert np.array_equal(g_all[0].cpu().numpy(), _grandchild_reference(children, tree.n_nodes))
+    pr = pruned.cpu().numpy()
+    for t in range(3):
+        assert np.array_equal(g_pruned[t].cpu().numpy(), _grandchild_reference(pr[t], rows))
+
+
+@pytest.mark.parametrize("dtype", [_lib.FPO_F32, _lib.FPO_BF16])
+def test_renders_through_grandchild_tables_are_identical(dev, dtype):
+    """Snapshot renders (plain, noalloc, coarse skip) through a view carrying
+    a two-level table walk the same slots: the images equal those without it
+    bit for bit, for the union table and for a pruned table, with the table
+    over the upper nodes and over every node."""
+    import torch
+    dijk = synth.blob_leaves(7, 40000)
+    k = synth.gaussian_coeffs(len(dijk), seed=23)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev)
+    times = [12.5]
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    sigma = torch.empty((1, tree.leaf_stride), dtype=torch.float32, device=dev)
+    snap = _lib.bake_times(tree, basis, dtype, sigma_out=sigma)
+    pruned = _lib.prune_at_sigma(tree, sigma)
+    pt = _lib.tree_with_children(tree, pruned[0])
+    cams = [synth.ring_camera(0.4 + 0.9 * j, math.radians(8 + 9 * j), 1.5, 30.0, 96, 64, times[0]) for j in range(4)]
+    bits = torch.from_numpy(_lib.coarse_occupancy(dijk, 7).view(np.int32)).to(dev)
+    ws = _lib.skip_workspace(4, 64, 96, dev)
+    plain = _lib.make_opts(stop_T=1e-3, snapshot=snap[0], snapshot_dtype=dtype)
+    skip = _lib.make_opts(stop_T=1e-3, snapshot=snap[0], snapshot_dtype=dtype, flags=_lib.FPO_RENDER_SKIP_COARSE,
+                          coarse_bits=bits, workspace=ws)
+    for base in (tree, pt):
+        note(f"renders through grandchild tables dtype={dtype} pruned={base is pt}")
+        for rows in (None, tree.n_nodes):
+            g = _lib.grandchild_tables(tree, base.children, n_rows=rows)
+            gt = _lib.tree_with_children(base, base.children, g[0])
+            for opts in (plain, skip):
+                want, _ = _lib.render(base, cams, opts)
+                got, _ = _lib.render(gt, cams, opts)
+                torch.cuda.synchronize()
+                assert torch.equal(got, want)
+            want, _ = _lib.render_noalloc(base, cams, plain)
+            got, _ = _lib.render_noalloc(gt, cams, plain)
+            torch.cuda.synchronize()
+            assert torch.equal(got, want)
+            assert float(want.max()) > 0.05
+
+
 def test_c2_pruned_decode_sampled(oracle_lib, dev):
     """The pruned decode path at full size: the 2M-leaf scene, the step's 10
     times baked into F32 snapshots and pruned in one call each, 16 cameras of
@@ -219,6 +302,7 @@ def test_c2_pruned_decode_sampled(oracle_lib, dev):
     torch.cuda.synchronize()
     kept = (pruned != 0).sum(dim=(1, 2)).cpu().numpy() / float((tree.children != 0).sum())
     assert np.all(kept < 0.95), kept
+    gc = _lib.grandchild_tables(tree, pruned)
     ot = oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth)
     p = oracle_lib.make_params(stop_T=1e-3)
     rng = np.random.default_rng(10)
@@ -227,7 +311,9 @@ def test_c2_pruned_decode_sampled(oracle_lib, dev):
         note(f"c2 pruned render time index {j}")
         got, _ = _lib.render(_lib.tree_with_children(tree, pruned[j]), cams[j * per:(j + 1) * per], opts)
         plain, _ = _lib.render(tree, cams[j * per:(j + 1) * per], opts)
+        two, _ = _lib.render(_lib.tree_with_children(tree, pruned[j], gc[j]), cams[j * per:(j + 1) * per], opts)
         torch.cuda.synchronize()
+        assert torch.equal(two, got)
         diff = (got - plain).abs().amax(-1)
         assert float((diff > 0).float().mean()) <= 1e-3 and float(diff.max()) <= 2e-5
         m = 3000

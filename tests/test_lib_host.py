@@ -289,6 +289,33 @@ def test_prune_entries_validate_before_launching():
 
 
 @host_only
+def test_grandchild_tables_validate_before_launching():
+    """fpo_grandchild_tables and a tree view carrying a two-level table are
+    checked on the host (fake pointers: nothing is launched)."""
+    L = _lib.lib()
+    p = ctypes.c_void_p(64)
+    assert L.fpo_grandchild_tables(None, 10, 1, 4, p, None) == _lib.FPO_E_INVALID
+    assert L.fpo_grandchild_tables(p, 10, 0, 4, p, None) == _lib.FPO_E_INVALID        # n_t
+    assert L.fpo_grandchild_tables(p, 10, 1, 0, p, None) == _lib.FPO_E_INVALID        # no rows
+    assert L.fpo_grandchild_tables(p, 10, 1, 11, p, None) == _lib.FPO_E_INVALID       # rows > nodes
+    assert L.fpo_grandchild_tables(p, 10, 1, 4, ctypes.c_void_p(72), None) == _lib.FPO_E_INVALID
+    view = _lib.TreeView()
+    view.children = 16
+    view.n_nodes = 4
+    view.max_depth = 3
+    view.n_leaves = 10
+    view.leaf_stride = 10
+    view.layout = _lib.make_layout()
+    view.grandchildren = 64
+    sig = ctypes.c_void_p(64)
+    for rows, ptr in ((0, 64), (5, 64), (2, 68)):
+        view.n_grandchild_rows = rows
+        view.grandchildren = ptr
+        assert L.fpo_prune_at_sigma(ctypes.byref(view), sig, 10, 1, p, None) == _lib.FPO_E_INVALID
+        assert "grandchild" in L.fpo_last_error().decode()
+
+
+@host_only
 def test_other_layouts_are_limited_to_render_pack_and_bake():
     """Layouts (n1, n2) other than (31, 5) pass validation only where they are
     compiled; unknown layouts are rejected everywhere."""
