@@ -313,7 +313,7 @@ def per_frame_leg(dev, sc, tree, oracle_mod, n_frames: int = 60, reps: int = 3, 
     return res
 
 
-def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
+def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None, two_level: bool = True):
     """Fine-tune throughput on the 500k-leaf depth-8 scene: 8192-ray batches
     drawn uniformly over 24 cameras x 30 times at 800x800, L2 loss, Adam.
     With the oracle, also the oracle's forward + backward of the first batch
@@ -327,7 +327,7 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
     init = synth.perturb_coeffs(gt, 0.05, seed=synth.COEFF_SEED + 1)
     cams = synth.c4_cameras()
     ft = FineTuner.from_scene(dijk, gt, init, 8, cams, dev, stop_T=1e-3, lr=1e-2, batch=8192,
-                              seed=synth.RAY_SEED)
+                              seed=synth.RAY_SEED, two_level=two_level)
     torch.cuda.synchronize()
     log(f"fine-tune scene: {len(dijk)} leaves, {len(cams)} target images, ready in {time.time() - t0:.1f}s")
     loss = torch.zeros(1, device=dev)
@@ -348,7 +348,7 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
         res["ms_per_step_with_adam" if with_adam else "ms_per_step_fwd_bwd"] = round(ms, 4)
     # the same steps captured once in a HIP graph and replayed (batch copied in before each replay)
     ft_graph = FineTuner(ft.tree, ft.images, cams, stop_T=1e-3, lr=1e-2, batch=8192, seed=synth.RAY_SEED,
-                         graph=True)
+                         graph=True, two_level=two_level)
     for b in batches[:warmup]:
         ft_graph.step(*b[:3], loss, t_idx=b[3])
     torch.cuda.synchronize()
@@ -364,7 +364,7 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
     del ft_graph
     # the same steps with the backward walking every ray again (no segment records)
     ft_walk = FineTuner(ft.tree, ft.images, cams, stop_T=1e-3, lr=1e-2, batch=8192, seed=synth.RAY_SEED,
-                        record=False)
+                        record=False, two_level=two_level)
     for b in batches[:warmup]:
         ft_walk.step(*b[:3], loss, with_adam=False, t_idx=b[3])
     torch.cuda.synchronize()
@@ -380,7 +380,7 @@ def finetune_leg(dev, steps: int = 40, warmup: int = 5, oracle_mod=None):
     del ft_walk
     # lazy Adam: only records the batch reached are updated (a semantic change, reported apart)
     ft_touch = FineTuner(ft.tree, ft.images, cams, stop_T=1e-3, lr=1e-2, batch=8192, seed=synth.RAY_SEED,
-                         adam="touched")
+                         adam="touched", two_level=two_level)
     for b in batches[:warmup]:
         ft_touch.step(*b[:3], loss, t_idx=b[3])
     torch.cuda.synchronize()
@@ -949,7 +949,8 @@ def main():
     if args.only_finetune:
         import oracle
         print(json.dumps({"finetune": finetune_leg(dev, steps=args.ft_steps,
-                                                   oracle_mod=None if args.no_cpu else oracle)}), flush=True)
+                                                   oracle_mod=None if args.no_cpu else oracle,
+                                                   two_level=not args.no_grandchild)}), flush=True)
         return
     t0 = time.time()
     sc = synth.c2_scene()
@@ -1161,7 +1162,8 @@ def main():
     fus = None if args.no_fusion else fusion_leg(dev, sc, tree)
     per_frame = None if args.no_per_frame else per_frame_leg(dev, sc, tree, oracle)
     bake = None if args.no_bake else bake_leg(dev, sc, tree, oracle)
-    ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps, oracle_mod=oracle)
+    ft = None if args.no_finetune else finetune_leg(dev, steps=args.ft_steps, oracle_mod=oracle,
+                                                    two_level=not args.no_grandchild)
     prop = None if args.no_proposal else proposal_leg(dev, sc, tree, oracle)
     del tree
     torch.cuda.empty_cache()

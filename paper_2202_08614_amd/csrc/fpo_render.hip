@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kBlock, REC ? 8 : 1) void render_rays_wave_kernel(R
         float Y[FPO_N_SH];
         sh9(r.d[0], r.d[1], r.d[2], Y);
         sh.sl.init(lane, a.basis + (int64_t)ti * FPO_BASIS_STRIDE, Y);
-        walk(a.tree, r, s_stack + threadIdx.x, sh);
+        walk<true>(a.tree, r, s_stack + threadIdx.x, sh);
     }
     if (lane == 0) {
 #pragma unroll

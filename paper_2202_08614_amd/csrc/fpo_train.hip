@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void render_backward_wave_kernel(BackwardLa
         float Y[FPO_N_SH];
         sh9(r.d[0], r.d[1], r.d[2], Y);
         sh.sl.init(lane, a.basis + (int64_t)ti * FPO_BASIS_STRIDE, Y);
-        walk(a.tree, r, s_stack + threadIdx.x, sh);
+        walk<true>(a.tree, r, s_stack + threadIdx.x, sh);
     }
 }
 
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void render_backward_rec_kernel(BackwardLau
     sh9(r.d[0], r.d[1], r.d[2], Y);
     sh.sl.init(lane, a.basis + (int64_t)ti * FPO_BASIS_STRIDE, Y);
     if (cnt < 0) {
-        walk(a.tree, r, s_stack + threadIdx.x, sh);
+        walk<true>(a.tree, r, s_stack + threadIdx.x, sh);
         return;
     }
     const float4* rr = a.rec + r_id * a.rec_cap * 2;

@@ -26,11 +26,16 @@ from . import _lib
 class FineTuner:
     def __init__(self, tree: _lib.DeviceTree, images: torch.Tensor, cams: Sequence, stop_T: float = 1e-3,
                  lr: float = 1e-2, batch: int = 8192, seed: int = 2022, record: bool = True,
-                 record_cap: int = 128, graph: bool = False, adam: str = "dense"):
+                 record_cap: int = 128, graph: bool = False, adam: str = "dense", two_level: bool = True):
         dev = tree.children.device
         if adam not in ("dense", "touched"):
             raise ValueError("adam must be 'dense' or 'touched'")
         self.adam = adam
+        # two_level: the walks descend two levels per read through the tree's
+        # two-level table (built here once: the structure never changes while
+        # the coefficients are trained); the segments are the same
+        if two_level and tree.grandchildren is None and tree.upper() > 0:
+            tree = _lib.tree_with_children(tree, tree.children, _lib.grandchild_tables(tree)[0])
         self.tree = tree
         self.images = images
         self.n_img, self.H, self.W = int(images.shape[0]), int(images.shape[1]), int(images.shape[2])
@@ -71,14 +76,14 @@ class FineTuner:
     def from_scene(cls, leaf_dijk: np.ndarray, gt_coeffs: np.ndarray, init_coeffs: np.ndarray, max_depth: int,
                    cams: Sequence, dev, sigma_scale: float = 64.0, stop_T: float = 1e-3, lr: float = 1e-2,
                    batch: int = 8192, seed: int = 2022, record: bool = True, record_cap: int = 128,
-                   graph: bool = False, adam: str = "dense") -> "FineTuner":
+                   graph: bool = False, adam: str = "dense", two_level: bool = True) -> "FineTuner":
         """Targets are rendered from the ground-truth coefficients by fpo_render."""
         gt = _lib.DeviceTree.from_leaves(leaf_dijk, gt_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
         images, _ = _lib.render(gt, cams, _lib.make_opts(stop_T=stop_T))
         del gt
         tree = _lib.DeviceTree.from_leaves(leaf_dijk, init_coeffs, max_depth, device=dev, sigma_scale=sigma_scale)
         return cls(tree, images, cams, stop_T=stop_T, lr=lr, batch=batch, seed=seed, record=record,
-                   record_cap=record_cap, graph=graph, adam=adam)
+                   record_cap=record_cap, graph=graph, adam=adam, two_level=two_level)
 
     def sample(self):
         """A batch: image, row and column of each ray, and the time index of its image."""

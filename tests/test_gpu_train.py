@@ -119,6 +119,58 @@ def test_recorded_backward_matches_oracle_gradient(oracle_lib, dev, stop_T, cap)
     assert not bad.any(), (bad.sum(), np.abs(b - want).max())
 
 
+def test_two_level_table_gives_the_same_forward_and_backward(oracle_lib, dev):
+    """Forward (one ray per wave, with segment records; one ray per lane) and
+    backward (from the records; re-walking) through a view that carries the
+    two-level table walk the same segments: colours, transmittance and
+    records equal the plain view's bit for bit, gradients up to the order of
+    the atomic additions."""
+    import torch
+    n_rays = 4096
+    dijk = synth.blob_leaves(7, 30000)
+    coeffs = synth.gaussian_coeffs(len(dijk), seed=17)
+    tree = _lib.DeviceTree.from_leaves(dijk, coeffs, 7, device=dev, sigma_scale=16.0)
+    two = _lib.tree_with_children(tree, tree.children, _lib.grandchild_tables(tree)[0])
+    cams = [synth.ring_camera(0.5 + 1.7 * k, 0.2 - 0.15 * k, 1.5, 30.0, 64, 64, 0.0) for k in range(3)]
+    rng = np.random.default_rng(17)
+    ci = rng.integers(0, 3, n_rays)
+    o = np.zeros((n_rays, 3)); d = np.zeros((n_rays, 3))
+    for c in range(3):
+        sel = np.nonzero(ci == c)[0]
+        o[sel], d[sel] = oracle_lib.camera_rays(cams[c], rng.integers(0, 64, len(sel)), rng.integers(0, 64, len(sel)))
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    o_d, d_d = to(o.astype(np.float32)), to(d.astype(np.float32))
+    t_d = to(rng.integers(0, 3, n_rays).astype(np.int32))
+    g_d = to(rng.standard_normal((n_rays, 3)).astype(np.float32))
+    basis = to(_lib.time_basis([4.0, 22.5, 40.1]))
+    for n, flags in ((n_rays, _lib.FPO_RAYS_RECORD), (n_rays, 0), (40000, 0)):
+        note(f"two-level table forward/backward n={n} flags={flags}")
+        if n != n_rays:
+            idx = torch.from_numpy(rng.integers(0, n_rays, n)).to(dev)
+            oo, dd, tt, gg = o_d[idx].contiguous(), d_d[idx].contiguous(), t_d[idx].contiguous(), g_d[idx].contiguous()
+        else:
+            oo, dd, tt, gg = o_d, d_d, t_d, g_d
+        out = {}
+        for name, tr in (("plain", tree), ("two", two)):
+            ws = _lib.record_workspace(n, 128, dev) if flags else None
+            opts = _lib.make_opts(stop_T=1e-3, flags=flags, workspace=ws)
+            rgb, T = _lib.render_rays(tr, oo, dd, tt, basis, opts, want_T=True)
+            g = torch.zeros_like(tree.coeffs)
+            if n <= 32768:
+                _lib.render_backward(tr, oo, dd, tt, basis, rgb, gg, g, opts)
+            torch.cuda.synchronize()
+            out[name] = (rgb, T, g, None if ws is None else ws.clone())
+        a, b = out["plain"], out["two"]
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        assert float(a[1].min()) < 0.5
+        if a[3] is not None:
+            assert torch.equal(_lib.record_counts(a[3], n), _lib.record_counts(b[3], n))
+        if n <= 32768:
+            ga, gb = a[2].cpu().numpy(), b[2].cpu().numpy()
+            gmax = np.abs(ga).max()
+            assert gmax > 0 and np.all(np.abs(ga - gb) <= 1e-5 * np.abs(ga) + 1e-7 * gmax)
+
+
 def test_backward_matches_gpu_central_differences(oracle_lib, dev):
     """dL/dk on 64 coefficients against central differences (h = 1e-3) of
     the GPU forward, L = sum_r w_r . rgb_r accumulated in FP64."""
