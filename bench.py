@@ -885,16 +885,26 @@ def layouts_leg(dev, sc, tree, reps: int = 3):
                 _lib.bake_times(vt, basis[q:q + 1], _lib.FPO_F32, out=snap)
 
         f_ms, d_ms, i_ms = timed(fourier), timed(decode), timed(idft)
-        res[f"{n1}x{n2}"] = {"coeffs_per_leaf": nc, "record_bytes": 16 * _lib.layout_record_words(n1, n2),
-                             "store_GB_f32": round(L * nc * 4 / 1e9, 3),
-                             "fourier_ms_per_launch": round(f_ms, 3), "fourier_fps_1080p": round(per / (f_ms * 1e-3), 1),
-                             "decode_ms_per_launch": round(d_ms, 3), "decode_fps_1080p": round(per / (d_ms * 1e-3), 1),
-                             "idft_pass_ms": round(i_ms, 3)}
+        row = {"coeffs_per_leaf": nc, "record_bytes": 16 * _lib.layout_record_words(n1, n2),
+               "store_GB_f32": round(L * nc * 4 / 1e9, 3),
+               "fourier_ms_per_launch": round(f_ms, 3), "fourier_fps_1080p": round(per / (f_ms * 1e-3), 1),
+               "decode_ms_per_launch": round(d_ms, 3), "decode_fps_1080p": round(per / (d_ms * 1e-3), 1),
+               "idft_pass_ms": round(i_ms, 3)}
+        # quantised stores of the layout: codes (+ one F32 scale per leaf) and the Fourier-mode render from them
+        for dt, name in ((_lib.FPO_BF16, "bf16"), (_lib.FPO_FP8_E4M3, "fp8")):
+            qt = _lib.quantize(vt, dt)
+            q_ms = timed(lambda: [_lib.render(qt, cams[j * per:(j + 1) * per], opts_f, rgb=frames) for j in js])
+            row[f"store_GB_{name}"] = round(L * (nc * (2 if dt == _lib.FPO_BF16 else 1) + 4) / 1e9, 3)
+            row[f"fourier_{name}_ms_per_launch"] = round(q_ms, 3)
+            row[f"fourier_{name}_fps_1080p"] = round(per / (q_ms * 1e-3), 1)
+            del qt
+        res[f"{n1}x{n2}"] = row
         log(f"layout {n1}x{n2}: {res[f'{n1}x{n2}']}")
         del vt, recs
         torch.cuda.empty_cache()
     res["workload"] = ("2.0M-leaf depth-9 scene with random coefficients of each layout (std 1/(i+1)); 16 ring "
-                       "cameras x 1920x1080 per launch, time points 0 and 5 of the headline, T<1e-3; F32 store")
+                       "cameras x 1920x1080 per launch, time points 0 and 5 of the headline, T<1e-3; F32 store, "
+                       "and BF16 / FP8 stores quantised from it (Fourier-mode render)")
     return res
 
 
@@ -922,6 +932,7 @@ def main():
     ap.add_argument("--only-construct", action="store_true", help="run only the FPO-construction leg")
     ap.add_argument("--only-proposal", action="store_true", help="run only the learned-proposal leg")
     ap.add_argument("--only-bake", action="store_true", help="run only the bake leg")
+    ap.add_argument("--only-layouts", action="store_true", help="run only the Fourier-dimension (layouts) leg")
     ap.add_argument("--only-finetune", action="store_true", help="run only the fine-tune leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprof byte counters)")
@@ -972,6 +983,9 @@ def main():
         import oracle
         print(json.dumps({"bake": bake_leg(dev, sc, tree, None if args.no_cpu else oracle)}, default=float),
               flush=True)
+        return
+    if args.only_layouts:
+        print(json.dumps({"layouts": layouts_leg(dev, sc, tree)}), flush=True)
         return
     cams = sc.cameras
     n_t = 10

@@ -229,9 +229,10 @@ fpo_status fpo_camera_pack(const fpo_camera* cams, int32_t n_cams, float* table_
  *   dst    device [leaf_stride][R] 16-byte words (F32 records, R = 48 for the
  *          default layout); padding slots and slots >= n_leaves are written
  *          with zero.
- * Layouts other than (31, 5) are accepted by fpo_render (Fourier mode: F32
- * store, no skip; snapshot mode: any) and fpo_bake_times (F32 store and
- * output) only; every other call returns FPO_E_UNSUPPORTED for them. */
+ * Layouts other than (31, 5) are accepted by fpo_quantize, fpo_render
+ * (Fourier mode from F32, BF16 and FP8 stores without skipping; snapshot
+ * mode: any) and fpo_bake_times (every store and output) only; every other
+ * call returns FPO_E_UNSUPPORTED for them. */
 fpo_status fpo_pack_coeffs(const float* src, const int64_t* perm, int64_t n_leaves,
                            int64_t leaf_stride, const fpo_layout* layout, float* dst, void* stream);
 
@@ -364,16 +365,19 @@ fpo_status fpo_adam_step_touched(float* params, float* grad, float* m, float* v,
 /* ---------------------------------------------------------------------- */
 
 /* Quantise an F32 coefficient store (the paper states no precision; this is
- * the storage reading of this library).  Per leaf: scale = max |k| over its 166
- * coefficients for FPO_BF16, max |k| / 448 for FPO_FP8_E4M3 (OCP E4M3FN),
- * 1 for an all-zero leaf; code = round-to-nearest-even(k / scale) with the
- * quotient formed in FP32 (IEEE division), FP8 saturating at +-448.
- *   coeffs    device F32 leaf records ([leaf_stride][48] words).
- *   q_out     device leaf records of `dtype` ([leaf_stride][24] or [16] words);
- *             slots q >= 166 and leaves >= n_leaves are zero.
+ * the storage reading of this library).  Per leaf: scale = max |k| over its
+ * n1 + 27 n2 coefficients for FPO_BF16, max |k| / 448 for FPO_FP8_E4M3 (OCP
+ * E4M3FN), 1 for an all-zero leaf; code = round-to-nearest-even(k / scale)
+ * with the quotient formed in FP32 (IEEE division), FP8 saturating at +-448.
+ *   coeffs    device F32 leaf records of the layout ([leaf_stride][48] words
+ *             for (31, 5); see fpo_pack_coeffs).
+ *   layout    host, or NULL for (31, 5); any compiled (n1, n2).
+ *   q_out     device leaf records of `dtype` for the layout ([leaf_stride][24]
+ *             or [16] words for (31, 5)); code slots past the coefficients
+ *             and leaves >= n_leaves are zero.
  *   scale_out device [leaf_stride] F32 (1 for leaves >= n_leaves). */
-fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride, fpo_dtype dtype,
-                        void* q_out, float* scale_out, void* stream);
+fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride, const fpo_layout* layout,
+                        fpo_dtype dtype, void* q_out, float* scale_out, void* stream);
 
 /* Evaluate Eq. 7 and Eq. 9 at n_t times for every leaf (a time bake), with
  * matrix-core (MFMA) contractions [times x K] x [K x leaves] in FP32 from 4

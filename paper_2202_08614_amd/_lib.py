@@ -108,7 +108,7 @@ _SIGS = {
                           ctypes.c_float, _P, _P],
     "fpo_adam_step_touched": [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, _I32, _P, _P],
-    "fpo_quantize": [_P, _I64, _I64, ctypes.c_int, _P, _P, _P],
+    "fpo_quantize": [_P, _I64, _I64, ctypes.POINTER(Layout), ctypes.c_int, _P, _P, _P],
     "fpo_bake_times": [ctypes.POINTER(TreeView), _P, _I32, ctypes.c_int, _P, _P, _P],
     "fpo_coarse_occupancy": [_P, _I64, _I32, _P],
     "fpo_ray_labels": [ctypes.POINTER(TreeView), _P, _P, _P, _P, _P, _I32, _I64,
@@ -181,9 +181,11 @@ def make_layout(period: float = 60.0, sigma_scale: float = 64.0, n_sigma: int = 
     return Layout(int(n_sigma), int(n_sh_fourier), SH_DEGREE, float(period), float(sigma_scale))
 
 
-def layout_record_words(n_sigma: int, n_sh_fourier: int) -> int:
-    """16-byte words of an F32 record for the layout (n1, n2)."""
-    return ((n_sigma + 27 * n_sh_fourier + 3) // 4 + 7) // 8 * 8
+def layout_record_words(n_sigma: int, n_sh_fourier: int, dtype: int = FPO_F32) -> int:
+    """16-byte words of a record of `dtype` for the layout (n1, n2): whole
+    128-byte lines."""
+    per_word = {FPO_F32: 4, FPO_BF16: 8, FPO_FP8_E4M3: 16}[dtype]
+    return ((n_sigma + 27 * n_sh_fourier + per_word - 1) // per_word + 7) // 8 * 8
 
 
 def camera_struct(cams) -> ctypes.Array:
@@ -491,10 +493,12 @@ def quantize(tree: DeviceTree, dtype: int) -> DeviceTree:
     if tree.dtype != FPO_F32:
         raise ValueError("quantize needs an F32 tree")
     dev = tree.coeffs.device
-    q = torch.zeros((tree.leaf_stride, record_words(dtype), 4), dtype=torch.int32, device=dev)
+    lay = tree.layout
+    q = torch.zeros((tree.leaf_stride, layout_record_words(lay.n_sigma, lay.n_sh_fourier, dtype), 4),
+                    dtype=torch.int32, device=dev)
     scale = torch.empty((tree.leaf_stride,), dtype=torch.float32, device=dev)
-    _check(lib().fpo_quantize(_t_ptr(tree.coeffs), tree.n_leaves, tree.leaf_stride, int(dtype), _t_ptr(q),
-                              _t_ptr(scale), _stream()))
+    _check(lib().fpo_quantize(_t_ptr(tree.coeffs), tree.n_leaves, tree.leaf_stride, ctypes.byref(lay), int(dtype),
+                              _t_ptr(q), _t_ptr(scale), _stream()))
     return tree.with_store(q, scale, dtype)
 
 

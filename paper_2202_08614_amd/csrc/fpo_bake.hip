@@ -62,47 +62,54 @@ __device__ inline uint32_t f32_to_e4m3_rne(float y)
 }
 
 // One thread per leaf slot: scale = max|k| (BF16) or max|k| / 448 (FP8), 1 for
-// an all-zero leaf; code = RNE(k / scale).  Reads the F32 records, writes the
-// quantised records and the scale.
-template <int DT>
+// an all-zero leaf; code = RNE(k / scale).  Reads the F32 records of the
+// layout (n1, n2) twice (the maximum, then the codes word by word, so that
+// even 328 coefficients never sit in registers), writes the quantised records
+// and the scale.
+template <int DT, int N1, int N2>
 __global__ __launch_bounds__(kBlock) void quantize_kernel(const float4* src, int64_t n_leaves, int64_t stride,
                                                           uint4* dst, float* scale)
 {
+    using RS = Rec<FPO_F32, N1, N2>;
+    using RQ = Rec<DT, N1, N2>;
+    constexpr int kCoeff = RS::kCoeff;
+    constexpr int W = Pack<DT>::W;                        // 8 or 16 codes per word
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (l >= stride) return;
-    constexpr int kSrcR = Pack<FPO_F32>::R;
-    constexpr int W = Pack<DT>::W;                        // 8 or 16 codes per word
-    constexpr int R = Pack<DT>::R;
-    uint4* out = dst + l * R;
+    uint4* out = dst + l * RQ::R;
     if (l >= n_leaves) {
-        for (int g = 0; g < R; ++g) out[g] = make_uint4(0, 0, 0, 0);
+        for (int g = 0; g < RQ::R; ++g) out[g] = make_uint4(0, 0, 0, 0);
         scale[l] = 1.0f;
         return;
     }
-    const float4* in = src + l * kSrcR;
-    float k[(FPO_N_COEFF + 3) / 4 * 4];
+    const float4* in = src + l * RS::R;
     float mx = 0.0f;
-#pragma unroll
-    for (int g = 0; g < (FPO_N_COEFF + 3) / 4; ++g) {
+#pragma unroll 4
+    for (int g = 0; g < (kCoeff + 3) / 4; ++g) {
         const float4 w = in[g];
-        k[4 * g] = w.x; k[4 * g + 1] = w.y; k[4 * g + 2] = w.z; k[4 * g + 3] = w.w;
         mx = fmaxf(mx, fmaxf(fmaxf(fabsf(w.x), fabsf(w.y)), fmaxf(fabsf(w.z), fabsf(w.w))));
     }
     float s = (DT == FPO_BF16) ? mx : mx / 448.0f;
     if (mx == 0.0f) s = 1.0f;
     scale[l] = s;
-#pragma unroll
-    for (int g = 0; g < R; ++g) {
+    for (int g = 0; g < RQ::R; ++g) {
         uint32_t v[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int e = 0; e < W; ++e) {
-            const int q = g * W + e;
-            if (q >= FPO_N_COEFF) continue;
-            const float y = k[q] / s;
-            if (DT == FPO_BF16)
-                v[e >> 1] |= f32_to_bf16_rne(y) << (16 * (e & 1));
-            else
-                v[e >> 2] |= f32_to_e4m3_rne(y) << (8 * (e & 3));
+        for (int e4 = 0; e4 < W / 4; ++e4) {
+            const int q0 = g * W + 4 * e4;
+            if (q0 >= kCoeff) break;
+            const float4 w = in[q0 / 4];
+            const float x[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = 4 * e4 + u;
+                if (q0 + u >= kCoeff) continue;
+                const float y = x[u] / s;
+                if (DT == FPO_BF16)
+                    v[e >> 1] |= f32_to_bf16_rne(y) << (16 * (e & 1));
+                else
+                    v[e >> 2] |= f32_to_e4m3_rne(y) << (8 * (e & 3));
+            }
         }
         out[g] = make_uint4(v[0], v[1], v[2], v[3]);
     }
@@ -441,20 +448,25 @@ __global__ __launch_bounds__(kBlock) void eval_times_f32_kernel(TreeDev tree, co
     }
 }
 
-// Per-time evaluation for the other coefficient layouts (F32 store, n1 density
-// and n2 SH Fourier terms): the record is streamed word by word and every
-// coefficient q goes to its one output (sigma for q < n1, else z_m with
-// m = (q - n1) / n2 and basis index (q - n1) % n2), so no layout needs its
-// whole record in registers.
-template <int N1, int N2>
+// Per-time evaluation for the other coefficient layouts (n1 density and n2 SH
+// Fourier terms; F32, BF16 or FP8 store), one thread per leaf: word by word,
+// every coefficient q goes to its one output (sigma for q < n1, else z_m with
+// m = (q - n1) / n2 and basis index (q - n1) % n2), so every layout shares one
+// loop without index tables; quantised stores scale the sums by the leaf's
+// scale, as the default layout's kernels do.  (The compiler issues a record's
+// loads together: the widest F32 layouts run at one wave per SIMD, and still
+// stream at 5 TB/s.)
+template <int DT, int N1, int N2, int OUT_BF16>
 __global__ __launch_bounds__(kBlock) void eval_times_layout_kernel(TreeDev tree, const float* basis, int32_t n_t,
-                                                                   int64_t n_leaves, float* out, float* sigma)
+                                                                   int64_t n_leaves, void* out, float* sigma)
 {
-    using RC = Rec<FPO_F32, N1, N2>;
-    constexpr int kWords = (RC::kCoeff + 3) / 4;
+    using RC = Rec<DT, N1, N2>;
+    constexpr int W = Pack<DT>::W;
+    constexpr int kWords = (RC::kCoeff + W - 1) / W;
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (l >= n_leaves) return;
     const uint4* rec = tree.recs + l * RC::R;
+    const float sc = (DT == FPO_F32) ? 1.0f : tree.scale[l];
     for (int t = 0; t < n_t; ++t) {
         const float* b = basis + (int64_t)t * FPO_BASIS_STRIDE;
         float v[32];
@@ -462,19 +474,32 @@ __global__ __launch_bounds__(kBlock) void eval_times_layout_kernel(TreeDev tree,
         for (int e = 0; e < 32; ++e) v[e] = 0.0f;
 #pragma unroll
         for (int g = 0; g < kWords; ++g) {
-            float k[4];
-            Pack<FPO_F32>::unpack(rec[g], k);
+            float k[W];
+            Pack<DT>::unpack(rec[g], k);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int q = 4 * g + e;
+            for (int e = 0; e < W; ++e) {
+                const int q = W * g + e;
                 if (q < N1) v[0] = fmaf(k[e], b[q], v[0]);
                 else if (q < RC::kCoeff) v[1 + (q - N1) / N2] = fmaf(k[e], b[(q - N1) % N2], v[1 + (q - N1) / N2]);
             }
         }
-        if (sigma) sigma[(int64_t)t * tree.stride + l] = v[0];
-        float4* o = reinterpret_cast<float4*>(out) + ((int64_t)t * tree.stride + l) * 8;
+        if constexpr (DT != FPO_F32) {
 #pragma unroll
-        for (int w = 0; w < 8; ++w) o[w] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+            for (int e = 0; e < FPO_N_BAKED; ++e) v[e] *= sc;
+        }
+        const int64_t r = (int64_t)t * tree.stride + l;
+        if (sigma) sigma[r] = stored_sigma<OUT_BF16>(v[0]);
+        if constexpr (OUT_BF16) {
+            uint4* o = static_cast<uint4*>(out) + r * 4;
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                o[w] = make_uint4(pack_bf16x2(v[8 * w], v[8 * w + 1]), pack_bf16x2(v[8 * w + 2], v[8 * w + 3]),
+                                  pack_bf16x2(v[8 * w + 4], v[8 * w + 5]), pack_bf16x2(v[8 * w + 6], v[8 * w + 7]));
+        } else {
+            float4* o = static_cast<float4*>(out) + r * 8;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) o[w] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+        }
     }
 }
 
@@ -487,24 +512,33 @@ using namespace fpo;
 // the streaming FMA kernel is used; from here on the MFMA tiles pay off.
 static constexpr int32_t kMfmaMinTimes = 4;
 
-extern "C" fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride, fpo_dtype dtype,
-                                   void* q_out, float* scale_out, void* stream)
+extern "C" fpo_status fpo_quantize(const float* coeffs, int64_t n_leaves, int64_t leaf_stride,
+                                   const fpo_layout* layout, fpo_dtype dtype, void* q_out, float* scale_out,
+                                   void* stream)
 {
     ApiRange api_range_("fpo_quantize");
     if (!coeffs || !q_out || !scale_out) return fail(FPO_E_INVALID, "NULL device pointer");
     if (dtype != FPO_BF16 && dtype != FPO_FP8_E4M3) return fail(FPO_E_INVALID, "dtype must be BF16 or FP8_E4M3");
     if (n_leaves < 1 || leaf_stride < n_leaves) return fail(FPO_E_INVALID, "bad n_leaves / leaf_stride");
     if (leaf_stride > (int64_t)INT32_MAX * dev::kBlock) return fail(FPO_E_INVALID, "too many leaves");
+    const int n1 = layout ? layout->n_sigma : FPO_N_SIGMA;
+    const int n2 = layout ? layout->n_sh_fourier : FPO_N_SH_FOURIER;
     const int64_t grid = (leaf_stride + dev::kBlock - 1) / dev::kBlock;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (dtype == FPO_BF16)
-        hipLaunchKernelGGL(dev::quantize_kernel<FPO_BF16>, dim3((unsigned)grid), dim3(dev::kBlock), 0, s,
-                           reinterpret_cast<const float4*>(coeffs), n_leaves, leaf_stride,
-                           static_cast<uint4*>(q_out), scale_out);
-    else
-        hipLaunchKernelGGL(dev::quantize_kernel<FPO_FP8_E4M3>, dim3((unsigned)grid), dim3(dev::kBlock), 0, s,
-                           reinterpret_cast<const float4*>(coeffs), n_leaves, leaf_stride,
-                           static_cast<uint4*>(q_out), scale_out);
+    const float4* src = reinterpret_cast<const float4*>(coeffs);
+    uint4* dst = static_cast<uint4*>(q_out);
+    const bool bf = dtype == FPO_BF16;
+    switch (n1 * 100 + n2) {
+#define FPO_Q(A, B) case A * 100 + B:                                                                           \
+        if (bf) hipLaunchKernelGGL((dev::quantize_kernel<FPO_BF16, A, B>), dim3((unsigned)grid), dim3(dev::kBlock), \
+                                   0, s, src, n_leaves, leaf_stride, dst, scale_out);                          \
+        else hipLaunchKernelGGL((dev::quantize_kernel<FPO_FP8_E4M3, A, B>), dim3((unsigned)grid),              \
+                                dim3(dev::kBlock), 0, s, src, n_leaves, leaf_stride, dst, scale_out);          \
+        break
+        FPO_Q(31, 5); FPO_Q(11, 5); FPO_Q(21, 5); FPO_Q(11, 11); FPO_Q(21, 11); FPO_Q(31, 11);
+#undef FPO_Q
+        default: return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
+    }
     return launch_status("fpo_quantize");
 }
 
@@ -518,17 +552,20 @@ extern "C" fpo_status fpo_bake_times(const fpo_tree_view* tree, const float* bas
     if (n_t < 1) return fail(FPO_E_INVALID, "n_t must be >= 1");
     if (out_dtype != FPO_F32 && out_dtype != FPO_BF16) return fail(FPO_E_INVALID, "out_dtype must be F32 or BF16");
     if (!default_layout(tree->layout)) {
-        if (tree->dtype != FPO_F32 || out_dtype != FPO_F32)
-            return fail(FPO_E_UNSUPPORTED, "layouts other than (31, 5) bake F32 stores into F32 snapshots only");
         const dev::TreeDev td = dev::tree_dev(tree);
         const int64_t g1 = (tree->n_leaves + dev::kBlock - 1) / dev::kBlock;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        float* o = static_cast<float*>(out);
-        switch (tree->layout.n_sigma * 100 + tree->layout.n_sh_fourier) {
-#define FPO_EVL(A, B) case A * 100 + B: \
-            hipLaunchKernelGGL((dev::eval_times_layout_kernel<A, B>), dim3((unsigned)g1), dim3(dev::kBlock), 0, s, td, basis, n_t, tree->n_leaves, o, sigma_out); break
+        const int bfo = out_dtype == FPO_BF16 ? 1 : 0;
+        const int key = (tree->layout.n_sigma * 100 + tree->layout.n_sh_fourier) * 100 + (int)tree->dtype * 10 + bfo;
+        switch (key) {
+#define FPO_EVL1(A, B, DT, BF) case (A * 100 + B) * 100 + DT * 10 + BF:                                         \
+            hipLaunchKernelGGL((dev::eval_times_layout_kernel<DT, A, B, BF>), dim3((unsigned)g1), dim3(dev::kBlock), \
+                               0, s, td, basis, n_t, tree->n_leaves, out, sigma_out); break
+#define FPO_EVL(A, B) FPO_EVL1(A, B, 0, 0); FPO_EVL1(A, B, 0, 1); FPO_EVL1(A, B, 1, 0); FPO_EVL1(A, B, 1, 1); \
+            FPO_EVL1(A, B, 2, 0); FPO_EVL1(A, B, 2, 1)
             FPO_EVL(11, 5); FPO_EVL(21, 5); FPO_EVL(11, 11); FPO_EVL(21, 11); FPO_EVL(31, 11);
 #undef FPO_EVL
+#undef FPO_EVL1
             default: return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
         }
         return launch_status("fpo_bake_times");

@@ -444,6 +444,20 @@ static void launch_cam(const dev::CamLaunch& a, int grid, int skip, hipStream_t 
                            dim3(dev::kBlock), 0, s, a);
 }
 
+// Fourier-mode render of another coefficient layout (n1, n2) = key / 100,
+// key % 100 from a store of DT; false if the layout is not compiled.
+template <int DT>
+static bool launch_layout(const dev::CamLaunch& a, int key, int grid, hipStream_t s)
+{
+    switch (key) {
+#define FPO_LAY(A, B) case A * 100 + B: \
+        hipLaunchKernelGGL((dev::render_cam_kernel<DT, false, A, B>), dim3(grid), dim3(dev::kBlock), 0, s, a); return true
+        FPO_LAY(11, 5); FPO_LAY(21, 5); FPO_LAY(11, 11); FPO_LAY(21, 11); FPO_LAY(31, 11);
+#undef FPO_LAY
+        default: return false;
+    }
+}
+
 // The body of fpo_render: cameras go out in launches of at most
 // cams_per_launch (<= 16); the skip modes' scratch (opts->workspace) holds
 // one launch's pixels and is reused by every launch of the call.
@@ -456,8 +470,8 @@ static fpo_status render_impl(const fpo_tree_view* tree, const fpo_camera* cams,
     if ((st = check_opts(opts, tree, true)) != FPO_OK) return st;
     // the snapshot render does not read coefficients, so any compiled layout goes
     const bool variant = !default_layout(tree->layout) && !opts->snapshot;
-    if (variant && (tree->dtype != FPO_F32 || opts->flags != 0))
-        return fail(FPO_E_UNSUPPORTED, "layouts other than (31, 5) render from F32 stores without skipping only");
+    if (variant && opts->flags != 0)
+        return fail(FPO_E_UNSUPPORTED, "layouts other than (31, 5) render without skipping only");
     if (!cams || n_cams < 1) return fail(FPO_E_INVALID, "cams is NULL or n_cams < 1");
     if (!rgb_out) return fail(FPO_E_INVALID, "rgb_out is NULL");
     const int W = cams[0].width, H = cams[0].height;
@@ -537,14 +551,13 @@ static fpo_status render_impl(const fpo_tree_view* tree, const fpo_camera* cams,
         }
         if (variant) {
             const int key = tree->layout.n_sigma * 100 + tree->layout.n_sh_fourier;
-            switch (key) {
-                case 1105: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 11, 5>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
-                case 2105: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 21, 5>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
-                case 1111: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 11, 11>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
-                case 2111: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 21, 11>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
-                case 3111: hipLaunchKernelGGL((dev::render_cam_kernel<FPO_F32, false, 31, 11>), dim3(grid), dim3(dev::kBlock), 0, s, a); break;
-                default: return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
+            bool ok = false;
+            switch (tree->dtype) {
+                case FPO_F32: ok = launch_layout<FPO_F32>(a, key, grid, s); break;
+                case FPO_BF16: ok = launch_layout<FPO_BF16>(a, key, grid, s); break;
+                default: ok = launch_layout<FPO_FP8_E4M3>(a, key, grid, s); break;
             }
+            if (!ok) return fail(FPO_E_UNSUPPORTED, "layout (n1, n2) not compiled");
             if ((st = launch_status("fpo_render")) != FPO_OK) return st;
             continue;
         }

@@ -60,3 +60,81 @@ def test_layout_idft_pass_matches_oracle(oracle_lib, dev, n1, n2):
     mag[:, :, 1:] = np.einsum("ti,lmi->tlm", np.abs(B[:, :n2]), kz)
     assert np.all(np.abs(got - want) <= (n1 + 4) * 2.0 ** -24 * mag + 1e-7)
     assert np.all(out.cpu().numpy()[:, :, 28:] == 0.0)
+
+
+QUANT = [(_lib.FPO_BF16, "bf16"), (_lib.FPO_FP8_E4M3, "fp8")]
+
+
+def _layout_codes(q: np.ndarray, dtype: int, perm: np.ndarray, n: int, n_coeff: int) -> np.ndarray:
+    """Quantised leaf records [stride][R][4] int32 -> codes [L][n_coeff] in caller order."""
+    per = np.ascontiguousarray(q).view(np.uint8).reshape(q.shape[0], -1)
+    codes = (per.view(np.uint16) if dtype == _lib.FPO_BF16 else per)[:n, :n_coeff]
+    out = np.zeros_like(codes)
+    out[perm] = codes
+    return out
+
+
+@pytest.mark.parametrize("dtype,kind", QUANT)
+@pytest.mark.parametrize("n1,n2", [(11, 5), (21, 11), (31, 11)])
+def test_layout_quantised_store(oracle_lib, dev, n1, n2, dtype, kind):
+    """A quantised store of another layout: codes and scales bit-exact against
+    the reference codec; the Fourier-mode render against the oracle on the
+    dequantised coefficients (kernel error, 1e-4); the per-time pass into F32
+    and BF16 snapshots against the oracle's bake of the dequantised
+    coefficients, the density plane equal to the records' value 0."""
+    import torch
+    from oracle import codec
+    sc = synth.c1_scene()
+    n_coeff = n1 + 27 * n2
+    k = synth.gaussian_coeffs(sc.n_leaves, seed=n1 * 10 + n2, n_sigma=n1, n_sh_fourier=n2)
+    k[0] = 0.0                                               # an all-zero leaf: scale 1
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, k, 6, device=dev, leaf_stride=sc.n_leaves + 3,
+                                       n_sigma=n1, n_sh_fourier=n2)
+    note(f"layout ({n1}, {n2}) fpo_quantize {kind}")
+    qt = _lib.quantize(tree, dtype)
+    torch.cuda.synchronize()
+    assert qt.coeffs.shape[1] == _lib.layout_record_words(n1, n2, dtype)
+    want_codes, want_scale = codec.quantize(k, kind)
+    got_scale = np.zeros(sc.n_leaves, np.float32)
+    got_scale[tree.perm] = qt.scale.cpu().numpy()[:sc.n_leaves]
+    assert np.array_equal(got_scale.view(np.uint32), want_scale.view(np.uint32))
+    got = _layout_codes(qt.coeffs.cpu().numpy(), dtype, tree.perm, sc.n_leaves, n_coeff)
+    assert np.array_equal(got, want_codes)
+    rest = np.ascontiguousarray(qt.coeffs.cpu().numpy()).view(np.uint8).reshape(qt.coeffs.shape[0], -1)
+    width = 2 if dtype == _lib.FPO_BF16 else 1
+    assert not rest[:, n_coeff * width:].any() and not rest[sc.n_leaves:].any()
+    k_eff = codec.dequantize(want_codes, want_scale, kind)
+    # Fourier-mode render of the quantised store
+    cam = synth.ring_camera(0.6, 0.25, 1.5, 45.0, 40, 32, 23.9)
+    note(f"layout ({n1}, {n2}) render {kind}")
+    rgb, _ = _lib.render(qt, [cam], _lib.make_opts(stop_T=1e-3))
+    torch.cuda.synchronize()
+    o, d = oracle_lib.camera_rays(cam)
+    ot = oracle_lib.OracleTree(sc.leaf_dijk, 6)
+    p = oracle_lib.make_params(n_sigma=n1, n_sh_fourier=n2, stop_T=1e-3)
+    ref = conditioned_reference(oracle_lib, ot, k_eff, p, [cam.time], o, d, np.zeros(len(o), np.int32))
+    assert (ref["T"][:, 0] < 0.9).sum() > 100
+    check_parity(rgb[0].cpu().numpy().reshape(-1, 3), ref, 1e-4)
+    # per-time pass into F32 and BF16 snapshots, with the density plane
+    times = [5.1, 44.2]
+    basis = torch.from_numpy(_lib.time_basis(times, _lib.make_layout(n_sigma=max(n1, n2)))).to(dev)
+    pb = oracle_lib.make_params(n_sigma=n1, n_sh_fourier=n2)
+    want = oracle_lib.bake(k_eff, pb, times)[:, :, tree.perm].transpose(0, 2, 1)      # [n_t][slot][28]
+    B = np.stack([oracle_lib.basis(t, 60.0, max(n1, n2)) for t in times])
+    ka = np.abs(k_eff[tree.perm])
+    mag = np.zeros_like(want)
+    mag[:, :, 0] = np.abs(B[:, :n1]) @ ka[:, :n1].T
+    mag[:, :, 1:] = np.einsum("ti,lmi->tlm", np.abs(B[:, :n2]), ka[:, n1:].reshape(-1, 27, n2))
+    for out_dtype in (_lib.FPO_F32, _lib.FPO_BF16):
+        sigma = torch.empty((2, tree.leaf_stride), dtype=torch.float32, device=dev)
+        note(f"layout ({n1}, {n2}) fpo_bake_times {kind} store, out {out_dtype}")
+        out = _lib.bake_times(qt, basis, out_dtype, sigma_out=sigma)
+        torch.cuda.synchronize()
+        got = out.float().cpu().numpy()[:, :sc.n_leaves, :28]
+        # FP32 sums of n terms, then (quantised stores) one product with the scale; BF16 output: one more rounding
+        bound = (n1 + 6) * 2.0 ** -24 * mag + 1e-7
+        if out_dtype == _lib.FPO_BF16:
+            bound = bound + 2.0 ** -8 * np.abs(want)
+        assert np.all(np.abs(got - want) <= bound), np.abs(got - want).max()
+        assert np.array_equal(sigma.cpu().numpy()[:, :sc.n_leaves].view(np.uint32),
+                              out[:, :sc.n_leaves, 0].float().cpu().numpy().view(np.uint32))

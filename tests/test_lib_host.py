@@ -318,7 +318,9 @@ def test_grandchild_tables_validate_before_launching():
 @host_only
 def test_other_layouts_are_limited_to_render_pack_and_bake():
     """Layouts (n1, n2) other than (31, 5) pass validation only where they are
-    compiled; unknown layouts are rejected everywhere."""
+    compiled (packing, quantisation, the Fourier-mode render without skipping,
+    the bake); the fine-tune calls and skipping reject them, and unknown
+    layouts are rejected everywhere."""
     L = _lib.lib()
     view = _lib.TreeView()
     view.children = 16
@@ -330,14 +332,12 @@ def test_other_layouts_are_limited_to_render_pack_and_bake():
     view.layout = _lib.make_layout(n_sigma=21, n_sh_fourier=11)
     opts = _lib.make_opts()
     p = ctypes.c_void_p(64)
-    # render_rays, backward and bake with a BF16 output reject the layout
+    # render_rays and the backward reject the layout
     st = L.fpo_render_rays(ctypes.byref(view), p, p, p, p, 1, 1, ctypes.byref(opts), p, None, None)
     assert st == _lib.FPO_E_UNSUPPORTED
     st = L.fpo_render_backward(ctypes.byref(view), p, p, p, p, 1, 1, ctypes.byref(opts), p, p, p, None)
     assert st == _lib.FPO_E_UNSUPPORTED
-    st = L.fpo_bake_times(ctypes.byref(view), p, 1, _lib.FPO_BF16, p, None, None)
-    assert st == _lib.FPO_E_UNSUPPORTED
-    # a skipping render or a quantised store with the layout
+    # so does a skipping render, also from a quantised store
     o2 = _lib.make_opts(flags=_lib.FPO_RENDER_SKIP_COARSE)
     o2.coarse_bits = 64
     o2.workspace = 64
@@ -346,7 +346,10 @@ def test_other_layouts_are_limited_to_render_pack_and_bake():
     assert L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(o2), p, None, None) == _lib.FPO_E_UNSUPPORTED
     view.dtype = _lib.FPO_BF16
     view.leaf_scale = 64
-    assert L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(opts), p, None, None) == _lib.FPO_E_UNSUPPORTED
+    assert L.fpo_render(ctypes.byref(view), cams, 1, ctypes.byref(o2), p, None, None) == _lib.FPO_E_UNSUPPORTED
+    # quantisation of an uncompiled layout
+    bad = _lib.make_layout(n_sigma=15, n_sh_fourier=5)
+    assert L.fpo_quantize(p, 1, 1, ctypes.byref(bad), _lib.FPO_BF16, p, p, None) == _lib.FPO_E_UNSUPPORTED
     # a layout that is not compiled at all
     view.dtype = _lib.FPO_F32
     view.layout = _lib.make_layout(n_sigma=15, n_sh_fourier=5)
