@@ -141,7 +141,7 @@ def test_render_through_pruned_tables(oracle_lib, dev, dtype):
 # layout kernel
 SIGMA_PLANE_CASES = [(_lib.FPO_F32, 1), (_lib.FPO_F32, 3), (_lib.FPO_F32, 10), (_lib.FPO_F32, 21),
                      (_lib.FPO_BF16, 2), (_lib.FPO_BF16, 5), (_lib.FPO_FP8_E4M3, 2), (_lib.FPO_FP8_E4M3, 17),
-                     ("layout_21_11", 2)]
+                     ("layout_21_11", 2), ("layout_11_5_fp8", 3)]
 
 
 @pytest.mark.parametrize("store,n_t", SIGMA_PLANE_CASES)
@@ -150,14 +150,17 @@ def test_bake_sigma_plane_is_record_value(dev, store, n_t, out_dtype):
     """fpo_bake_times sigma_out holds value 0 of every record it writes, as
     FP32, bit for bit; slots past n_leaves are left alone."""
     import torch
-    if store == "layout_21_11" and out_dtype != _lib.FPO_F32:
-        pytest.skip("other layouts bake into F32 snapshots only")
     dijk = synth.random_tree_leaves(13, 6, p_split=0.6)
     n = len(dijk)
     if store == "layout_21_11":
         k = synth.gaussian_coeffs(n, seed=13, n_sigma=21, n_sh_fourier=11)
         tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=n + 7, n_sigma=21, n_sh_fourier=11)
         layout = _lib.make_layout(n_sigma=21)
+    elif store == "layout_11_5_fp8":
+        k = synth.gaussian_coeffs(n, seed=13, n_sigma=11)
+        tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=n + 7, n_sigma=11)
+        tree = _lib.quantize(tree, _lib.FPO_FP8_E4M3)
+        layout = _lib.make_layout(n_sigma=11)
     else:
         k = synth.gaussian_coeffs(n, seed=13)
         tree = _lib.DeviceTree.from_leaves(dijk, k, 6, device=dev, leaf_stride=n + 7)

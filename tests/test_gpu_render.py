@@ -235,6 +235,40 @@ def test_render_is_deterministic(c1, dev):
     assert torch.equal(a, b)
 
 
+def test_renders_in_flight_on_two_streams_equal_sequential_ones(c1, dev):
+    """fpo_render keeps no state between calls on the device: launches that
+    run at the same time on two streams (Fourier and snapshot mode, each
+    call 16 cameras) give the images of the same calls made one after the
+    other, bit for bit."""
+    import torch
+    sc, tree = c1
+    times = [1.0 + 7.5 * j for j in range(6)]
+    basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    snaps = _lib.bake_times(tree, basis, _lib.FPO_F32)
+    calls = []
+    for j, t in enumerate(times):
+        cams = [synth.ring_camera(0.39 * k + 0.1 * j, 0.2, 1.5, 45.0, 320, 240, t) for k in range(16)]
+        snap = j % 2 == 1
+        opts = _lib.make_opts(stop_T=1e-3, snapshot=snaps[j] if snap else None, snapshot_dtype=_lib.FPO_F32)
+        calls.append((cams, opts))
+    note("two streams: 6 calls x 16 cameras 320x240, alternating Fourier / snapshot mode")
+    seq = [_lib.render(tree, cams, o)[0] for cams, o in calls]
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    out = [torch.full_like(x, float("nan")) for x in seq]
+    for rep in range(3):
+        side.wait_stream(main)
+        for j, (cams, o) in enumerate(calls):
+            with torch.cuda.stream(main if j % 2 == 0 else side):
+                _lib.render(tree, cams, o, rgb=out[j])
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        for j in range(len(calls)):
+            assert torch.equal(out[j], seq[j]), (rep, j)
+            out[j].fill_(float("nan"))
+
+
 @pytest.fixture(scope="module")
 def c2(dev):
     sc = synth.c2_scene()
