@@ -1176,12 +1176,12 @@ def main():
         flop_ray = FLOP_PER_RAY + FLOP_SIGMA * (seg - opq).mean() + FLOP_OPAQUE * opq.mean()
         gather_ray = BYTES_SIGMA_WORDS * (seg - opq).mean() + BYTES_LEAF * opq.mean()
         kernel = "render_cam_kernel<F32> (per-sample IDFT)"
-        kernel_key = "render_cam_kernel<0, false, 31, 5, false>"
+        kernel_key = "render_cam_kernel<0, false, 31, 5, false, 1>"
     else:
         flop_ray = FLOP_PER_RAY + FLOP_SNAP_SIGMA * (seg - opq).mean() + FLOP_SNAP_OPAQUE * opq.mean()
         gather_ray = 16 * (seg - opq).mean() + 128 * opq.mean()
         kernel = "render_cam_kernel<snapshot F32> (after the bake of the step's 10 time points)"
-        kernel_key = "render_cam_kernel<16, false, 31, 5, true>"
+        kernel_key = "render_cam_kernel<16, false, 31, 5, true, 4>"
         if best == "decode_pruned":
             kernel = ("render_cam_kernel<snapshot F32> through the per-time pruned child tables (after the bake "
                       "and pruning of the step's 10 time points)")

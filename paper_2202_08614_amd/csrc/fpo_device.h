@@ -217,7 +217,7 @@ struct NoStop {
 
 // TWO: descend through the two-level table where the tree has one (the
 // snapshot camera renders; elsewhere the extra registers cost occupancy).
-template <bool TWO = false, class Visitor, class Stop>
+template <bool TWO = false, int STRIDE = kBlock, class Visitor, class Stop>
 __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis, float t_end, Stop& stop)
 {
     // The child table is read through a buffer resource: 32-bit byte offsets
@@ -278,7 +278,7 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
                     q[a] = (int)__builtin_amdgcn_fmed3f(fmaf(tg, fabsf(r.d[a]), xf[a]), pos[a], pos[a] + top);
             }
             do {
-                stk[csh * kBlock] = no;    // the node and the child the ray is in
+                stk[csh * STRIDE] = no;    // the node and the child the ray is in
                 csh -= 1;
                 const int bits = (__builtin_amdgcn_ubfe(q[0], csh, 1) | (__builtin_amdgcn_ubfe(q[1], csh, 1) << 1) |
                                   (__builtin_amdgcn_ubfe(q[2], csh, 1) << 2)) ^ mirror;
@@ -291,7 +291,7 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
                     no = (ch << 3) | bits;
                     ch = e[0];
                     if (ch > 0 && ch < T.n_nodes) {
-                        stk[csh * kBlock] = no;
+                        stk[csh * STRIDE] = no;
                         csh -= 1;
                         no = (ch << 3) | b2;
                         ch = e[1];
@@ -329,7 +329,7 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
             if (h > csh) {
                 // pop to the deepest node that contains the new slot (stacked under the slot size h)
                 csh = h;
-                no = stk[h * kBlock] ^ (1 << ax);
+                no = stk[h * STRIDE] ^ (1 << ax);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) pos[a] = __builtin_ldexpf(floorf(__builtin_ldexpf(pos[a], -h)), h);
             } else {
@@ -347,11 +347,11 @@ __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& v
     }
 }
 
-template <bool TWO = false, class Visitor>
+template <bool TWO = false, int STRIDE = kBlock, class Visitor>
 __device__ inline void walk(const TreeDev& T, const Ray& r, int* stk, Visitor& vis)
 {
     NoStop ns;
-    walk<TWO>(T, r, stk, vis, __builtin_inff(), ns);
+    walk<TWO, STRIDE>(T, r, stk, vis, __builtin_inff(), ns);
 }
 
 // Record geometry of a coefficient layout (n1 density terms, n2 terms per SH
