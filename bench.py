@@ -168,20 +168,37 @@ def bake_leg(dev, sc, tree, oracle_mod, n_t: int = 64, reps: int = 5):
              "bake_hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
              "bake_TFLOPs": round(flops / (ms * 1e-3) / 1e12, 2),
              "bake_mfma_frac": round(flops / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4)}
-        opts = _lib.make_opts(stop_T=1e-3, snapshot=snaps, snapshot_dtype=_lib.FPO_BF16,
-                              snapshot_cam_stride=tree.leaf_stride)
+        # the 64 views as calls of 16 (view k from snapshot k), alternating between the launch stream
+        # and a second one (two launches in flight), and on the launch stream alone
+        per = 16
+        opts_q = [_lib.make_opts(stop_T=1e-3, snapshot=snaps[q], snapshot_dtype=_lib.FPO_BF16,
+                                 snapshot_cam_stride=tree.leaf_stride) for q in range(0, n_t, per)]
         frames = torch.empty((n_t, 800, 800, 3), dtype=torch.float32, device=dev)
-        _lib.render(tree, cams, opts, rgb=frames)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            _lib.render(tree, cams, opts, rgb=frames)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        rms = e0.elapsed_time(e1) / reps
-        r["snapshot_render_ms_64x800x800"] = round(rms, 4)
-        r["snapshot_render_Mrays_s"] = round(n_t * 800 * 800 / (rms * 1e-3) / 1e6, 1)
+        side = torch.cuda.Stream()
+
+        def render_views(n_streams):
+            streams = [stream, side][:n_streams]
+            for st in streams[1:]:
+                st.wait_stream(stream)
+            for i, q in enumerate(range(0, n_t, per)):
+                with torch.cuda.stream(streams[i % n_streams]):
+                    _lib.render(tree, cams[q:q + per], opts_q[i], rgb=frames[q:q + per])
+            for st in streams[1:]:
+                stream.wait_stream(st)
+
+        for n_streams in (1, 2):
+            render_views(n_streams)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                render_views(n_streams)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rms = e0.elapsed_time(e1) / reps
+            key = "" if n_streams == 2 else "_one_stream"
+            r["snapshot_render_ms_64x800x800" + key] = round(rms, 4)
+            r["snapshot_render_Mrays_s" + key] = round(n_t * 800 * 800 / (rms * 1e-3) / 1e6, 1)
         if sample is not None:
             ci, py, px, o, d, ot, p, full = sample
             got = frames[torch.from_numpy(ci).to(dev), torch.from_numpy(py).to(dev),
