@@ -126,6 +126,13 @@ typedef struct {
                                      read from the nodes it covers.  8-byte aligned. */
     int64_t n_grandchild_rows;    /* rows of grandchildren: nodes 0 .. n - 1 (1 .. min(n_nodes, 2^22 - 1));
                                      ignored when grandchildren is NULL */
+    const int64_t* level_offsets; /* host [max_depth + 1], or NULL: the nodes of depth L are rows
+                                     level_offsets[L] .. level_offsets[L + 1] - 1, as fpo_build_tree
+                                     numbers them (0 first, n_nodes last, non-decreasing).  The
+                                     pruning calls then clear empty subtrees one level per pass,
+                                     bottom up, instead of passing over every row max_depth - 1
+                                     times; with offsets that do not match the table the pruning
+                                     may leave some empty subtrees in place (renders still equal) */
 } fpo_tree_view;
 
 /* Pinhole camera: ray through pixel centre (u + 0.5, v + 0.5), row 0 at the

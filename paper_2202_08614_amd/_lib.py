@@ -52,7 +52,8 @@ class TreeView(ctypes.Structure):
                 ("max_depth", ctypes.c_int32), ("coeffs", ctypes.c_void_p),
                 ("leaf_scale", ctypes.c_void_p), ("dtype", ctypes.c_int),
                 ("n_leaves", ctypes.c_int64), ("leaf_stride", ctypes.c_int64),
-                ("layout", Layout), ("grandchildren", ctypes.c_void_p), ("n_grandchild_rows", ctypes.c_int64)]
+                ("layout", Layout), ("grandchildren", ctypes.c_void_p), ("n_grandchild_rows", ctypes.c_int64),
+                ("level_offsets", ctypes.c_void_p)]
 
 
 class CameraC(ctypes.Structure):
@@ -280,8 +281,10 @@ class DeviceTree:
 
     def __init__(self, children, n_nodes: int, max_depth: int, coeffs, scale, dtype: int,
                  n_leaves: int, leaf_stride: int, perm: np.ndarray, layout: Layout,
-                 n_upper: Optional[int] = None, grandchildren=None):
+                 n_upper: Optional[int] = None, grandchildren=None, levels: Optional[np.ndarray] = None):
         self.children = children
+        # host int64 [max_depth + 1]: first node of each depth (fpo_build_tree's numbering), or None
+        self.levels = None if levels is None else np.ascontiguousarray(levels, dtype=np.int64)
         # nodes that have an internal child (numbered first, breadth first); None: not known yet
         self.n_upper = n_upper
         # two-level table of `children` (fpo_grandchild_tables), or None
@@ -313,12 +316,13 @@ class DeviceTree:
         pack_coeffs(src, perm_d, n, stride, recs, layout)
         del src
         return cls(torch.from_numpy(children).to(device), children.shape[0], max_depth, recs, None,
-                   FPO_F32, n, stride, perm, layout, n_upper=upper_rows(children))
+                   FPO_F32, n, stride, perm, layout, n_upper=upper_rows(children),
+                   levels=level_offsets(children, max_depth))
 
     def with_store(self, coeffs, scale, dtype: int) -> "DeviceTree":
         return DeviceTree(self.children, self.n_nodes, self.max_depth, coeffs, scale, dtype,
                           self.n_leaves, self.leaf_stride, self.perm, self.layout, self.n_upper,
-                          self.grandchildren)
+                          self.grandchildren, self.levels)
 
     def upper(self) -> int:
         """Nodes with an internal child (computed from the child table once)."""
@@ -340,7 +344,31 @@ class DeviceTree:
         if self.grandchildren is not None:
             v.grandchildren = self.grandchildren.data_ptr()
             v.n_grandchild_rows = int(self.grandchildren.shape[-3])
+        if self.levels is not None:
+            v.level_offsets = self.levels.ctypes.data
         return v
+
+
+def level_offsets(children: np.ndarray, max_depth: int) -> Optional[np.ndarray]:
+    """First node of each depth, [max_depth + 1] int64 ending at n_nodes, for a
+    child table numbered level by level (fpo_build_tree's order: the internal
+    children of depth-L nodes are exactly the next rows, each once); None if
+    the table is not numbered so."""
+    ch = np.asarray(children)
+    n = int(ch.shape[0])
+    off = np.zeros(max_depth + 1, dtype=np.int64)
+    lo, hi = 0, min(n, 1)                 # depth 0: the root
+    for L in range(max_depth):
+        off[L] = lo
+        kids = ch[lo:hi]
+        kids = kids[kids > 0].astype(np.int64)
+        if kids.size and (kids.min() != hi or kids.max() != hi + kids.size - 1 or np.unique(kids).size != kids.size):
+            return None
+        lo, hi = hi, hi + kids.size
+    if lo != hi or hi != n:               # no internal node at depth max_depth; every row reached
+        return None
+    off[max_depth] = n
+    return off
 
 
 def upper_rows(children: np.ndarray) -> int:
@@ -738,7 +766,7 @@ def tree_with_children(tree: DeviceTree, children, grandchildren=None) -> "Devic
     if grandchildren is not None and (grandchildren.dim() != 3 or tuple(grandchildren.shape[1:]) != (64, 2)):
         raise ValueError("grandchildren must be [rows][64][2]")
     return DeviceTree(children, tree.n_nodes, tree.max_depth, tree.coeffs, tree.scale, tree.dtype, tree.n_leaves,
-                      tree.leaf_stride, tree.perm, tree.layout, tree.n_upper, grandchildren)
+                      tree.leaf_stride, tree.perm, tree.layout, tree.n_upper, grandchildren, tree.levels)
 
 
 def grandchild_tables(tree: DeviceTree, children=None, n_rows: Optional[int] = None, out=None):

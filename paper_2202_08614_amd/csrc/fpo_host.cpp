@@ -77,6 +77,13 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_la
         if (reinterpret_cast<uintptr_t>(tree->grandchildren) & 7)
             return fail(FPO_E_INVALID, "tree->grandchildren must be 8-byte aligned");
     }
+    if (tree->level_offsets) {
+        const int64_t* lo = tree->level_offsets;
+        if (lo[0] != 0 || lo[tree->max_depth] != tree->n_nodes)
+            return fail(FPO_E_INVALID, "tree->level_offsets must start at 0 and end at n_nodes");
+        for (int L = 0; L < tree->max_depth; ++L)
+            if (lo[L + 1] < lo[L]) return fail(FPO_E_INVALID, "tree->level_offsets must not decrease");
+    }
     if (need_coeffs) {
         if (!tree->coeffs) return fail(FPO_E_INVALID, "tree->coeffs is NULL");
         if (tree->dtype != FPO_F32 && tree->dtype != FPO_BF16 && tree->dtype != FPO_FP8_E4M3)

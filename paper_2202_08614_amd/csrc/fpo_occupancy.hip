@@ -60,6 +60,7 @@ struct PruneLaunch {
     int32_t n_t;
     int32_t n_leaves;
     float sigma_scale;
+    int64_t lo, cnt;           // node passes: rows lo .. lo + cnt - 1 of each time
 };
 
 // First pass: one thread per (time, node) row; leaves are kept iff opaque at t,
@@ -93,15 +94,16 @@ __global__ __launch_bounds__(kBlock) void prune_leaves_kernel(PruneLaunch a)
     o[1] = make_int4(e[4], e[5], e[6], e[7]);
 }
 
-// Later passes: clear internal children whose row at this time is empty.
+// Later passes: clear internal children whose row at this time is empty,
+// for rows a.lo .. a.lo + a.cnt - 1 (every row, or one level of the tree).
 // Rows are read and written as two 16-byte words (a row another thread clears
 // in the same pass may be read old or new; either is safe, see above).
 __global__ __launch_bounds__(kBlock) void prune_nodes_kernel(PruneLaunch a)
 {
     const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (id >= a.n_nodes * a.n_t) return;
-    const int t = (int)(id / a.n_nodes);
-    const int64_t node = id - (int64_t)t * a.n_nodes;
+    if (id >= a.cnt * a.n_t) return;
+    const int t = (int)(id / a.cnt);
+    const int64_t node = a.lo + (id - (int64_t)t * a.cnt);
     int4* base = reinterpret_cast<int4*>(a.out + (int64_t)t * a.n_nodes * 8);
     const int4 r0 = base[2 * node], r1 = base[2 * node + 1];
     int e[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
@@ -267,6 +269,22 @@ fpo_status prune_impl(const fpo_tree_view* tree, const void* src, int kind, int6
     else
         hipLaunchKernelGGL(dev::prune_leaves_kernel<dev::kSigmaPlane>, dim3(grid), dim3(dev::kBlock), 0, s, a);
     if ((st = launch_status(name)) != FPO_OK) return st;
+    if (tree->level_offsets) {
+        // one pass per level, bottom up: the nodes of depth L clear their children
+        // (depth L + 1), whose rows the pass before has settled; the deepest
+        // nodes have leaf children only
+        for (int L = tree->max_depth - 2; L >= 0; --L) {
+            a.lo = tree->level_offsets[L];
+            a.cnt = tree->level_offsets[L + 1] - a.lo;
+            if (a.cnt == 0) continue;
+            const unsigned g = (unsigned)((a.cnt * n_t + dev::kBlock - 1) / dev::kBlock);
+            hipLaunchKernelGGL(dev::prune_nodes_kernel, dim3(g), dim3(dev::kBlock), 0, s, a);
+            if ((st = launch_status(name)) != FPO_OK) return st;
+        }
+        return FPO_OK;
+    }
+    a.lo = 0;
+    a.cnt = tree->n_nodes;
     for (int pass = 1; pass < tree->max_depth; ++pass) {
         hipLaunchKernelGGL(dev::prune_nodes_kernel, dim3(grid), dim3(dev::kBlock), 0, s, a);
         if ((st = launch_status(name)) != FPO_OK) return st;

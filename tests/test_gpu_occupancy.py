@@ -8,6 +8,8 @@ and the ReLU by a plain recursion; renders through the pruned tables are
 checked against the oracle and against the unpruned render."""
 import math
 
+import copy
+
 import numpy as np
 import pytest
 
@@ -182,21 +184,28 @@ def test_bake_sigma_plane_is_record_value(dev, store, n_t, out_dtype):
 
 def test_prune_at_sigma_equals_prune_at(dev):
     """Tables pruned from the density plane equal those pruned from the
-    records (F32 and BF16 snapshots, 12 times of a depth-7 blob scene)."""
+    records (F32 and BF16 snapshots, 12 times of a depth-7 blob scene), and
+    one node pass per tree level (the tree's level offsets) gives the tables
+    of max_depth - 1 passes over every row."""
     import torch
     dijk = synth.blob_leaves(7, 40000)
     k = synth.gaussian_coeffs(len(dijk), seed=5)
     tree = _lib.DeviceTree.from_leaves(dijk, k, 7, device=dev, leaf_stride=len(dijk) + 9)
     times = [2.5 * i + 0.1 for i in range(12)]
     basis = torch.from_numpy(_lib.time_basis(times)).to(dev)
+    flat = copy.copy(tree)
+    flat.levels = None          # node passes over every row instead of one level per pass
+    assert tree.levels is not None
     for dt in (_lib.FPO_F32, _lib.FPO_BF16):
         sigma = torch.empty((len(times), tree.leaf_stride), dtype=torch.float32, device=dev)
         note(f"fpo_prune_at_sigma against fpo_prune_at dtype={dt}")
         snaps = _lib.bake_times(tree, basis, dt, sigma_out=sigma)
         a = _lib.prune_at(tree, snaps, dt)
         b = _lib.prune_at_sigma(tree, sigma)
+        c = _lib.prune_at_sigma(flat, sigma)
+        d = _lib.prune_at(flat, snaps, dt)
         torch.cuda.synchronize()
-        assert torch.equal(a, b)
+        assert torch.equal(a, b) and torch.equal(b, c) and torch.equal(c, d)
         kept = (a != 0).sum().item() / (len(times) * (tree.children != 0).sum().item())
         assert 0.2 < kept < 0.95, kept
 

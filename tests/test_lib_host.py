@@ -286,6 +286,36 @@ def test_prune_entries_validate_before_launching():
     assert L.fpo_prune_at(tv, p, _lib.FPO_FP8_E4M3, 10, 1, p, None) == _lib.FPO_E_INVALID      # record dtype
     assert L.fpo_prune_at(tv, p, _lib.FPO_F32, 9, 2, p, None) == _lib.FPO_E_INVALID
     assert "stride" in L.fpo_last_error().decode()
+    # level offsets: from 0 to n_nodes, never decreasing
+    for bad in ([1, 1, 2, 4], [0, 1, 2, 3], [0, 2, 1, 4]):
+        lv = np.array(bad, dtype=np.int64)
+        view.level_offsets = lv.ctypes.data
+        assert L.fpo_prune_at_sigma(tv, p, 10, 1, p, None) == _lib.FPO_E_INVALID, bad
+        assert "level_offsets" in L.fpo_last_error().decode()
+    view.level_offsets = None
+
+
+def test_level_offsets_of_built_trees():
+    """The first node of each depth, from the child table of fpo_build_tree:
+    every internal child of a depth-L node lies in depth L + 1's rows; the
+    offsets run from 0 to n_nodes."""
+    for depth, dijk in ((6, synth.random_tree_leaves(13, 6, p_split=0.6)), (5, synth.shell_leaves(5, 0.33, 0.09)),
+                        (7, synth.blob_leaves(7, 40000))):
+        ch, _ = _lib.build_tree(dijk, depth)
+        off = _lib.level_offsets(ch, depth)
+        assert off is not None and off[0] == 0 and off[-1] == ch.shape[0] and (np.diff(off) >= 0).all()
+        assert off[1] == 1                                   # the root alone at depth 0
+        for L in range(depth - 1):
+            kids = ch[off[L]:off[L + 1]]
+            kids = kids[kids > 0]
+            assert ((kids >= off[L + 1]) & (kids < off[L + 2])).all()
+        assert not (ch[off[depth - 1]:] > 0).any()           # the deepest internal nodes hold leaves only
+        # a child pointing back up a level is no level numbering
+        bad = ch.copy()
+        r = int(np.nonzero((bad[off[1]:off[2]] > 0).any(axis=1))[0][0]) + int(off[1])
+        c = int(np.nonzero(bad[r] > 0)[0][0])
+        bad[r, c] = 1 if r != 1 else 2
+        assert _lib.level_offsets(bad, depth) is None
 
 
 @host_only
