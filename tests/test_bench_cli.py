@@ -24,3 +24,13 @@ def test_help_lists_the_contract_flags():
     assert r.returncode == 0
     for flag in ("--gpus", "--steps", "--warmup"):
         assert flag in r.stdout
+
+
+def test_render_streams_take_one_or_two():
+    """--render-streams: the step's render launches in flight at once (1 or 2);
+    anything else is refused by the parser before the GPU is touched."""
+    r = _bench("--help")
+    assert "--render-streams" in r.stdout
+    for bad in ("0", "3"):
+        r = _bench("--render-streams", bad, "--steps", "1")
+        assert r.returncode == 2 and "--render-streams" in r.stderr and r.stdout == ""
