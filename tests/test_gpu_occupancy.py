@@ -90,6 +90,32 @@ def test_prune_and_occupancy_at_match_definitions(oracle_lib, dev, dtype):
         assert np.array_equal(bits[t], want_bits), int(np.unpackbits((bits[t] ^ want_bits).view(np.uint8)).sum())
 
 
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_prune_level_passes_on_shallow_trees(oracle_lib, dev, depth):
+    """Trees of depth 1 to 3 (no node pass at depth 1, one or two level
+    passes above it): the tables pruned one level per pass and by passes over
+    every row both equal the bottom-up definition."""
+    import torch
+    dijk = synth.random_tree_leaves(40 + depth, depth, p_split=0.7)
+    k = synth.gaussian_coeffs(len(dijk), seed=40 + depth)
+    tree = _lib.DeviceTree.from_leaves(dijk, k, depth, device=dev, leaf_stride=len(dijk) + 3)
+    assert tree.levels is not None and len(tree.levels) == depth + 1
+    flat = copy.copy(tree)
+    flat.levels = None
+    times = [3.0, 31.0, 47.5]
+    snaps, vals = _oracle_snapshots(oracle_lib, k, times, tree.perm, tree.leaf_stride, _lib.FPO_F32)
+    snaps = snaps.to(dev)
+    children = tree.children.cpu().numpy()
+    for tr in (tree, flat):
+        note(f"fpo_prune_at depth={depth} level passes={tr.levels is not None}")
+        got = _lib.prune_at(tr, snaps, _lib.FPO_F32)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        for t in range(len(times)):
+            want = _expected_pruned(children, (vals[t, 0] > 0.0)[tree.perm])
+            assert np.array_equal(got[t], want), (depth, t, int((got[t] != want).sum()))
+
+
 @pytest.mark.parametrize("dtype", [_lib.FPO_F32, _lib.FPO_BF16])
 def test_render_through_pruned_tables(oracle_lib, dev, dtype):
     """Snapshot renders through the pruned table of their time equal the
