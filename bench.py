@@ -872,7 +872,7 @@ def layouts_leg(dev, sc, tree, reps: int = 3):
         _lib.pack_coeffs(src, perm_d, L, tree.leaf_stride, recs, layout)
         del src
         vt = _lib.DeviceTree(tree.children, tree.n_nodes, tree.max_depth, recs, None, _lib.FPO_F32, L,
-                             tree.leaf_stride, tree.perm, layout)
+                             tree.leaf_stride, tree.perm, layout, bounds=tree.bounds)
         basis = torch.from_numpy(_lib.time_basis([cams[j * per].time for j in js], layout)).to(dev)
         opts_f = _lib.make_opts(stop_T=sc.stop_T)
         opts_s = _lib.make_opts(stop_T=sc.stop_T, snapshot=snap, snapshot_dtype=_lib.FPO_F32)
@@ -1250,6 +1250,7 @@ def main():
                                   "decode_pruned": n_t + 1 + sc.max_depth + (1 if two else 0)}[best],
             "two_level_tables": two and best != "fourier",
             "render_streams": args.render_streams,
+            "rays_clipped_to_leaf_bounds": tree.bounds is not None,
         },
         "fps_1080p": round(fps, 2),
         "render_path": best,

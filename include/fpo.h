@@ -133,6 +133,17 @@ typedef struct {
                                      bottom up, instead of passing over every row max_depth - 1
                                      times; with offsets that do not match the table the pruning
                                      may leave some empty subtrees in place (renders still equal) */
+    const int32_t* bounds;        /* host [6] int32, or NULL (the unit cube): a box on the finest
+                                     lattice (2^max_depth cells per axis) that holds every leaf,
+                                     [bounds[0], bounds[3]) x [bounds[1], bounds[4]) x [bounds[2],
+                                     bounds[5]), e.g. from fpo_leaf_bounds; 0 <= lo < hi <= 2^max_depth
+                                     per axis.  fpo_render and fpo_render_noalloc without skip flags
+                                     clip each camera ray to this box instead of the unit cube: a ray
+                                     that misses it ends at once, the others start their walk on its
+                                     face.  Outside the leaves there is nothing to composite (Eq. 2),
+                                     so the image is the same up to FP32 rounding of the entry point;
+                                     a box that cuts a leaf drops the part of it outside.  The other
+                                     calls ignore it */
 } fpo_tree_view;
 
 /* Pinhole camera: ray through pixel centre (u + 0.5, v + 0.5), row 0 at the
@@ -209,6 +220,16 @@ typedef struct {
 fpo_status fpo_build_tree(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
                           int32_t* children_out, int64_t cap_nodes, int64_t* n_nodes_out,
                           int64_t* perm_out);
+
+/* The smallest box on the finest lattice (2^max_depth cells per axis) that
+ * holds every leaf of the octree (Sec. 3: the leaves are the only cells with
+ * content), for fpo_tree_view.bounds.
+ *   leaf_dijk   host [n_leaves][4] int32 (depth, i, j, k), as for fpo_build_tree.
+ *   bounds_out  host [6] int32: lo x, y, z, then hi x, y, z (half-open).
+ * FPO_E_INVALID: NULL pointers, n_leaves < 1, max_depth outside 1..10, a depth
+ * outside 1..max_depth or a coordinate outside [0, 2^depth).  Overlaps are
+ * not checked (fpo_build_tree does).  Runs on the calling thread; no device work. */
+fpo_status fpo_leaf_bounds(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth, int32_t* bounds_out);
 
 /* Real Fourier basis of Eq. 8 evaluated in FP64 on the host and rounded to
  * FP32: basis_out[r * 32 + i] = IDFT_i(times[r]) for i < n_sigma, 0 for the

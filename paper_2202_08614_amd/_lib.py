@@ -53,7 +53,7 @@ class TreeView(ctypes.Structure):
                 ("leaf_scale", ctypes.c_void_p), ("dtype", ctypes.c_int),
                 ("n_leaves", ctypes.c_int64), ("leaf_stride", ctypes.c_int64),
                 ("layout", Layout), ("grandchildren", ctypes.c_void_p), ("n_grandchild_rows", ctypes.c_int64),
-                ("level_offsets", ctypes.c_void_p)]
+                ("level_offsets", ctypes.c_void_p), ("bounds", ctypes.c_void_p)]
 
 
 class CameraC(ctypes.Structure):
@@ -89,6 +89,7 @@ _lib = None
 # name -> argtypes; every function returns fpo_status (int)
 _SIGS = {
     "fpo_build_tree": [_P, _I64, _I32, _P, _I64, _P, _P],
+    "fpo_leaf_bounds": [_P, _I64, _I32, _P],
     "fpo_time_basis": [_P, _I32, ctypes.POINTER(Layout), _P],
     "fpo_camera_pack": [ctypes.POINTER(CameraC), _I32, _P],
     "fpo_pack_coeffs": [_P, _P, _I64, _I64, ctypes.POINTER(Layout), _P, _P],
@@ -256,6 +257,14 @@ def build_tree(leaf_dijk: np.ndarray, max_depth: int):
     return children, perm
 
 
+def leaf_bounds(leaf_dijk: np.ndarray, max_depth: int) -> np.ndarray:
+    """fpo_leaf_bounds -> int32 [6]: lo x, y, z, hi x, y, z on the finest lattice."""
+    dijk = np.ascontiguousarray(leaf_dijk, dtype=np.int32)
+    out = np.zeros(6, dtype=np.int32)
+    _check(lib().fpo_leaf_bounds(_np_ptr(dijk), dijk.shape[0], int(max_depth), _np_ptr(out)))
+    return out
+
+
 def time_basis(times: Sequence[float], layout: Optional[Layout] = None) -> np.ndarray:
     layout = layout or make_layout()
     t = np.ascontiguousarray(times, dtype=np.float64)
@@ -281,8 +290,11 @@ class DeviceTree:
 
     def __init__(self, children, n_nodes: int, max_depth: int, coeffs, scale, dtype: int,
                  n_leaves: int, leaf_stride: int, perm: np.ndarray, layout: Layout,
-                 n_upper: Optional[int] = None, grandchildren=None, levels: Optional[np.ndarray] = None):
+                 n_upper: Optional[int] = None, grandchildren=None, levels: Optional[np.ndarray] = None,
+                 bounds: Optional[np.ndarray] = None):
         self.children = children
+        # host int32 [6]: lattice box holding every leaf (fpo_leaf_bounds), or None (the unit cube)
+        self.bounds = None if bounds is None else np.ascontiguousarray(bounds, dtype=np.int32)
         # host int64 [max_depth + 1]: first node of each depth (fpo_build_tree's numbering), or None
         self.levels = None if levels is None else np.ascontiguousarray(levels, dtype=np.int64)
         # nodes that have an internal child (numbered first, breadth first); None: not known yet
@@ -303,7 +315,9 @@ class DeviceTree:
     def from_leaves(cls, leaf_dijk: np.ndarray, coeffs: np.ndarray, max_depth: int,
                     device="cuda", period: float = 60.0, sigma_scale: float = 64.0,
                     leaf_stride: Optional[int] = None, n_sigma: int = N_SIGMA,
-                    n_sh_fourier: int = N_SH_FOURIER) -> "DeviceTree":
+                    n_sh_fourier: int = N_SH_FOURIER, clip: bool = True) -> "DeviceTree":
+        """clip: camera renders start each ray on the leaves' bounds
+        (fpo_leaf_bounds) instead of the unit cube."""
         import torch
         children, perm = build_tree(leaf_dijk, max_depth)
         n = int(leaf_dijk.shape[0])
@@ -317,12 +331,13 @@ class DeviceTree:
         del src
         return cls(torch.from_numpy(children).to(device), children.shape[0], max_depth, recs, None,
                    FPO_F32, n, stride, perm, layout, n_upper=upper_rows(children),
-                   levels=level_offsets(children, max_depth))
+                   levels=level_offsets(children, max_depth),
+                   bounds=leaf_bounds(leaf_dijk, max_depth) if clip else None)
 
     def with_store(self, coeffs, scale, dtype: int) -> "DeviceTree":
         return DeviceTree(self.children, self.n_nodes, self.max_depth, coeffs, scale, dtype,
                           self.n_leaves, self.leaf_stride, self.perm, self.layout, self.n_upper,
-                          self.grandchildren, self.levels)
+                          self.grandchildren, self.levels, self.bounds)
 
     def upper(self) -> int:
         """Nodes with an internal child (computed from the child table once)."""
@@ -346,6 +361,8 @@ class DeviceTree:
             v.n_grandchild_rows = int(self.grandchildren.shape[-3])
         if self.levels is not None:
             v.level_offsets = self.levels.ctypes.data
+        if self.bounds is not None:
+            v.bounds = self.bounds.ctypes.data
         return v
 
 
@@ -766,7 +783,8 @@ def tree_with_children(tree: DeviceTree, children, grandchildren=None) -> "Devic
     if grandchildren is not None and (grandchildren.dim() != 3 or tuple(grandchildren.shape[1:]) != (64, 2)):
         raise ValueError("grandchildren must be [rows][64][2]")
     return DeviceTree(children, tree.n_nodes, tree.max_depth, tree.coeffs, tree.scale, tree.dtype, tree.n_leaves,
-                      tree.leaf_stride, tree.perm, tree.layout, tree.n_upper, grandchildren, tree.levels)
+                      tree.leaf_stride, tree.perm, tree.layout, tree.n_upper, grandchildren, tree.levels,
+                      tree.bounds)
 
 
 def grandchild_tables(tree: DeviceTree, children=None, n_rows: Optional[int] = None, out=None):

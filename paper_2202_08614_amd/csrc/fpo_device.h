@@ -30,6 +30,7 @@ struct TreeDev {
     float sigma_scale;
     const int2* gc;         // two-level table [n_gc][64] (children, grandchild), or null
     int32_t n_gc;           // rows of gc (0 without one)
+    float box_lo[3], box_hi[3];   // the leaves' bounds in cube units (default: the unit cube)
 };
 
 // Host helper: the kernel-side view of a validated fpo_tree_view.
@@ -46,6 +47,12 @@ inline TreeDev tree_dev(const fpo_tree_view* t)
     d.n_leaves = (int32_t)t->n_leaves;
     d.max_depth = t->max_depth;
     d.sigma_scale = t->layout.sigma_scale;
+    // lattice bounds / 2^max_depth: exact in FP32
+    const float cell = 1.0f / (float)(1 << t->max_depth);
+    for (int a = 0; a < 3; ++a) {
+        d.box_lo[a] = t->bounds ? (float)t->bounds[a] * cell : 0.0f;
+        d.box_hi[a] = t->bounds ? (float)t->bounds[3 + a] * cell : 1.0f;
+    }
     return d;
 }
 
@@ -139,7 +146,10 @@ struct Ray {
     float t_len;    // length inside the cube
 };
 
-__host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx, float dy, float dz, Ray& r)
+// Clip the ray to the box [lo, hi] (cube units) instead of the unit cube:
+// the entry point is then on the box's face and t_len the chord inside it.
+__host__ __device__ inline bool setup_ray_in(const float* lo_b, const float* hi_b, float ox, float oy, float oz,
+                                             float dx, float dy, float dz, Ray& r)
 {
     const float n2 = dx * dx + dy * dy + dz * dz;
     if (!(n2 > 0.0f)) return false;
@@ -152,13 +162,13 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
         r.d[a] = d[a];
         if (d[a] == 0.0f) {
             r.inv[a] = 0.0f;
-            if (o[a] < 0.0f || o[a] > 1.0f) return false;
+            if (o[a] < lo_b[a] || o[a] > hi_b[a]) return false;
             continue;
         }
         const float inv = 1.0f / d[a];
         r.inv[a] = inv;
-        float t1 = (0.0f - o[a]) * inv;
-        float t2 = (1.0f - o[a]) * inv;
+        float t1 = (lo_b[a] - o[a]) * inv;
+        float t2 = (hi_b[a] - o[a]) * inv;
         if (t1 > t2) { const float s = t1; t1 = t2; t2 = s; }
         lo = fmaxf(lo, t1);
         hi = fminf(hi, t2);
@@ -169,6 +179,12 @@ __host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx
 #pragma unroll
     for (int a = 0; a < 3; ++a) r.o[a] = fmaf(lo, d[a], o[a]);
     return true;
+}
+
+__host__ __device__ inline bool setup_ray(float ox, float oy, float oz, float dx, float dy, float dz, Ray& r)
+{
+    const float lo_b[3] = {0.0f, 0.0f, 0.0f}, hi_b[3] = {1.0f, 1.0f, 1.0f};
+    return setup_ray_in(lo_b, hi_b, ox, oy, oz, dx, dy, dz, r);
 }
 
 // --------------------------------------------------------------------------

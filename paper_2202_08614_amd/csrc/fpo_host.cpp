@@ -84,6 +84,12 @@ fpo_status check_tree(const fpo_tree_view* tree, bool need_coeffs, bool allow_la
         for (int L = 0; L < tree->max_depth; ++L)
             if (lo[L + 1] < lo[L]) return fail(FPO_E_INVALID, "tree->level_offsets must not decrease");
     }
+    if (tree->bounds) {
+        const int32_t G = int32_t(1) << tree->max_depth;
+        for (int a = 0; a < 3; ++a)
+            if (tree->bounds[a] < 0 || tree->bounds[a] >= tree->bounds[3 + a] || tree->bounds[3 + a] > G)
+                return fail(FPO_E_INVALID, "tree->bounds must hold 0 <= lo < hi <= 2^max_depth on every axis");
+    }
     if (need_coeffs) {
         if (!tree->coeffs) return fail(FPO_E_INVALID, "tree->coeffs is NULL");
         if (tree->dtype != FPO_F32 && tree->dtype != FPO_BF16 && tree->dtype != FPO_FP8_E4M3)
@@ -201,6 +207,33 @@ static uint64_t spread3(uint64_t v)
 using namespace fpo;
 
 extern "C" const char* fpo_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" fpo_status fpo_leaf_bounds(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
+                                      int32_t* bounds_out)
+{
+    ApiRange api_range_("fpo_leaf_bounds");
+    if (!leaf_dijk || !bounds_out) return fail(FPO_E_INVALID, "leaf_dijk and bounds_out must not be NULL");
+    if (n_leaves < 1) return fail(FPO_E_INVALID, "n_leaves out of range");
+    if (max_depth < 1 || max_depth > FPO_MAX_DEPTH) return fail(FPO_E_INVALID, "max_depth must be in 1..10");
+    const int32_t G = int32_t(1) << max_depth;
+    int32_t lo[3] = {G, G, G}, hi[3] = {0, 0, 0};
+    for (int64_t l = 0; l < n_leaves; ++l) {
+        const int32_t* c = leaf_dijk + 4 * l;
+        if (c[0] < 1 || c[0] > max_depth) return fail(FPO_E_INVALID, "leaf " + std::to_string(l) + ": depth out of range");
+        const int32_t sh = max_depth - c[0], g = int32_t(1) << c[0];
+        for (int a = 0; a < 3; ++a) {
+            if (c[1 + a] < 0 || c[1 + a] >= g)
+                return fail(FPO_E_INVALID, "leaf " + std::to_string(l) + ": coordinate out of range");
+            lo[a] = std::min(lo[a], c[1 + a] << sh);
+            hi[a] = std::max(hi[a], (c[1 + a] + 1) << sh);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        bounds_out[a] = lo[a];
+        bounds_out[3 + a] = hi[a];
+    }
+    return FPO_OK;
+}
 
 extern "C" fpo_status fpo_build_tree(const int32_t* leaf_dijk, int64_t n_leaves, int32_t max_depth,
                                      int32_t* children_out, int64_t cap_nodes, int64_t* n_nodes_out,

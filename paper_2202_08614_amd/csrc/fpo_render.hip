@@ -230,7 +230,12 @@ __global__ __launch_bounds__(64 * WAVES, BUF ? 32 / WAVES : 1) void render_cam_k
     sh.stop_T = a.stop_T;
     Ray r;
     const int64_t pix = ((int64_t)ci * a.H + py) * a.W + px;
-    if (setup_ray(cam.frame[0], cam.frame[1], cam.frame[2], dx, dy, dz, r)) {
+    // the plain walk starts on the face of the leaves' bounds (rays that miss
+    // them end here); the skip pre-pass measures along the cube's chord
+    bool hit;
+    if constexpr (SKIP) hit = setup_ray(cam.frame[0], cam.frame[1], cam.frame[2], dx, dy, dz, r);
+    else hit = setup_ray_in(a.tree.box_lo, a.tree.box_hi, cam.frame[0], cam.frame[1], cam.frame[2], dx, dy, dz, r);
+    if (hit) {
         sh9(r.d[0], r.d[1], r.d[2], sh.Y);
         if constexpr (!SKIP) {
             walk<(MODE >= 16), kThreads>(a.tree, r, s_stack + threadIdx.x, sh);

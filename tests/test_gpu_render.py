@@ -54,6 +54,57 @@ def test_c1_render_parity(oracle_lib, c1, dev):
     assert np.max(np.abs(T - ref["T"][:, 0])[~exempt]) <= TOL
 
 
+def test_bounds_clip_keeps_the_image(oracle_lib, c1, dev):
+    """Camera renders start each ray on the leaves' bounds (fpo_leaf_bounds)
+    instead of the unit cube.  Nothing lies outside the leaves, so the image
+    is the cube walk's up to FP32 rounding of the entry point, in Fourier and
+    in snapshot mode; rays that miss the box return the background with
+    T = 1 exactly; the clipped image passes the oracle parity."""
+    import copy
+    import torch
+    sc, tree = c1
+    G = 1 << sc.max_depth
+    assert tree.bounds is not None and (tree.bounds[:3] > 0).all() and (tree.bounds[3:] < G).all()
+    cube = copy.copy(tree)
+    cube.bounds = None
+    # a wide view: many rays cross the cube but miss the box
+    cams = [sc.cameras[0], synth.ring_camera(math.radians(35), math.radians(20), 1.25, 80.0, 64, 64, sc.cameras[0].time)]
+    basis = torch.from_numpy(_lib.time_basis([cams[0].time])).to(dev)
+    snap = _lib.bake_times(tree, basis, _lib.FPO_F32)[0]
+    bg = (0.2, 0.3, 0.4)
+    fourier = _lib.make_opts(stop_T=1e-3, bg=bg)
+    snapshot = _lib.make_opts(stop_T=1e-3, bg=bg, snapshot=snap, snapshot_dtype=_lib.FPO_F32)
+    out = {}
+    for name, opts in (("fourier", fourier), ("snapshot", snapshot)):
+        for t, tr in (("clip", tree), ("cube", cube)):
+            note(f"c1 fpo_render {name} {t}")
+            out[name, t] = _lib.render(tr, cams, opts, want_T=True)
+    torch.cuda.synchronize()
+    for name in ("fourier", "snapshot"):
+        (a, ta), (b, tb) = out[name, "clip"], out[name, "cube"]
+        assert float((a - b).abs().max()) < 1e-4 and float((ta - tb).abs().max()) < 1e-4, name
+    # rays that miss the box grown by 1e-5 on every side stay clear of it in FP32 too
+    lo, hi = tree.bounds[:3] / G - 1e-5, tree.bounds[3:] / G + 1e-5
+    for c, cam in enumerate(cams):
+        o, d = oracle_lib.camera_rays(cam)
+        inv = 1.0 / np.where(d == 0, 1e-300, d)
+        t1, t2 = (lo - o) * inv, (hi - o) * inv
+        t_in = np.maximum(np.minimum(t1, t2).max(1), 0.0)
+        t_out = np.maximum(t1, t2).min(1)
+        miss = t_out < t_in
+        assert miss.sum() > 100, (c, int(miss.sum()))
+        for name in ("fourier", "snapshot"):
+            rgb, T = out[name, "clip"]
+            assert (T[c].reshape(-1).cpu().numpy()[miss] == 1.0).all()
+            assert (rgb[c].reshape(-1, 3).cpu().numpy()[miss] == np.float32(bg)).all()
+        ref = conditioned_reference(oracle_lib, oracle_lib.OracleTree(sc.leaf_dijk, sc.max_depth), sc.coeffs,
+                                    oracle_lib.make_params(stop_T=1e-3, bg=bg), [cam.time], o, d,
+                                    np.zeros(len(o), np.int32))
+        assert (ref["T"][:, 0] < 0.99).sum() > 100
+        for name in ("fourier", "snapshot"):
+            check_parity(out[name, "clip"][0][c].reshape(-1, 3).cpu().numpy(), ref, TOL, max_exempt_frac=0.02)
+
+
 def _compare_lists(gpu_ids, gpu_t, n_vis, o, d, ref_trace, boxes, perm):
     """Visited leaves equal after dropping FP64-short segments on both sides."""
     lo, hi = boxes

@@ -293,6 +293,43 @@ def test_prune_entries_validate_before_launching():
         assert L.fpo_prune_at_sigma(tv, p, 10, 1, p, None) == _lib.FPO_E_INVALID, bad
         assert "level_offsets" in L.fpo_last_error().decode()
     view.level_offsets = None
+    # bounds: 0 <= lo < hi <= 2^max_depth on every axis
+    for bad in ([0, 0, 0, 8, 8, 9], [-1, 0, 0, 8, 8, 8], [3, 0, 0, 3, 8, 8], [0, 5, 0, 8, 4, 8]):
+        b = np.array(bad, dtype=np.int32)
+        view.bounds = b.ctypes.data
+        assert L.fpo_prune_at_sigma(tv, p, 10, 1, p, None) == _lib.FPO_E_INVALID, bad
+        assert "bounds" in L.fpo_last_error().decode()
+    view.bounds = None
+
+
+def test_leaf_bounds_of_built_trees():
+    """fpo_leaf_bounds is the smallest box on the finest lattice that holds
+    every leaf: leaf (d, i, j, k) covers [i, i + 1) 2^(D - d) per axis, and the
+    box is the union of those ranges."""
+    for depth, dijk in ((6, synth.random_tree_leaves(13, 6, p_split=0.6)), (5, synth.shell_leaves(5, 0.33, 0.09)),
+                        (7, synth.blob_leaves(7, 40000)), (9, synth.c2_scene().leaf_dijk)):
+        b = _lib.leaf_bounds(dijk, depth)
+        sh = (depth - dijk[:, 0].astype(np.int64))[:, None]
+        c = dijk[:, 1:].astype(np.int64)
+        assert b.tolist() == (c << sh).min(0).tolist() + ((c + 1) << sh).max(0).tolist()
+    # the root's eight children fill the cube; one finest cell is its own box
+    eight = np.array([[1, x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)], dtype=np.int32)
+    assert _lib.leaf_bounds(eight, 5).tolist() == [0, 0, 0, 32, 32, 32]
+    assert _lib.leaf_bounds(np.array([[3, 2, 5, 7]], np.int32), 3).tolist() == [2, 5, 7, 3, 6, 8]
+    assert _lib.leaf_bounds(np.array([[1, 1, 0, 1], [3, 0, 6, 2]], np.int32), 4).tolist() == [0, 0, 4, 16, 14, 16]
+    L = _lib.lib()
+    out = np.zeros(6, np.int32)
+    one = np.array([[1, 0, 0, 0]], np.int32)
+    ptr = lambda a: a.ctypes.data
+    assert L.fpo_leaf_bounds(None, 1, 3, ptr(out)) == _lib.FPO_E_INVALID
+    assert L.fpo_leaf_bounds(ptr(one), 1, 3, None) == _lib.FPO_E_INVALID
+    assert L.fpo_leaf_bounds(ptr(one), 0, 3, ptr(out)) == _lib.FPO_E_INVALID
+    assert L.fpo_leaf_bounds(ptr(one), 1, 0, ptr(out)) == _lib.FPO_E_INVALID
+    assert L.fpo_leaf_bounds(ptr(one), 1, 11, ptr(out)) == _lib.FPO_E_INVALID
+    for bad in ([4, 0, 0, 0], [0, 0, 0, 0], [2, 4, 0, 0], [2, 0, -1, 0]):
+        assert L.fpo_leaf_bounds(ptr(np.array([bad], np.int32)), 1, 3, ptr(out)) == _lib.FPO_E_INVALID, bad
+        assert "leaf 0" in L.fpo_last_error().decode()
+    assert not out.any()
 
 
 def test_level_offsets_of_built_trees():
