@@ -987,7 +987,8 @@ def main():
     log(f"scene: {sc.n_leaves} leaves, generated in {time.time() - t0:.1f}s")
     tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
     torch.cuda.synchronize()
-    log(f"tree: {tree.n_nodes} nodes uploaded")
+    clipped = tree.bounds is not None
+    log(f"tree: {tree.n_nodes} nodes uploaded; camera rays clipped to the leaves' bounds {tree.bounds.tolist() if clipped else None}")
 
     if args.only_proposal:
         import oracle
@@ -1250,7 +1251,7 @@ def main():
                                   "decode_pruned": n_t + 1 + sc.max_depth + (1 if two else 0)}[best],
             "two_level_tables": two and best != "fourier",
             "render_streams": args.render_streams,
-            "rays_clipped_to_leaf_bounds": tree.bounds is not None,
+            "rays_clipped_to_leaf_bounds": clipped,
         },
         "fps_1080p": round(fps, 2),
         "render_path": best,
