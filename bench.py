@@ -940,6 +940,8 @@ def main():
                     help="render launches of a step in flight at once (alternating between this many streams)")
     ap.add_argument("--no-grandchild", action="store_true",
                     help="decode modes: walk the child tables one level per read (no two-level tables)")
+    ap.add_argument("--no-clip", action="store_true",
+                    help="camera renders walk each ray from the cube's face (no clipping to the leaves' bounds)")
     ap.add_argument("--no-bake", action="store_true")
     ap.add_argument("--ft-steps", type=int, default=40)
     ap.add_argument("--no-proposal", action="store_true")
@@ -985,7 +987,7 @@ def main():
     t0 = time.time()
     sc = synth.c2_scene()
     log(f"scene: {sc.n_leaves} leaves, generated in {time.time() - t0:.1f}s")
-    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev)
+    tree = _lib.DeviceTree.from_leaves(sc.leaf_dijk, sc.coeffs, sc.max_depth, device=dev, clip=not args.no_clip)
     torch.cuda.synchronize()
     clipped = tree.bounds is not None
     log(f"tree: {tree.n_nodes} nodes uploaded; camera rays clipped to the leaves' bounds {tree.bounds.tolist() if clipped else None}")

@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_help_lists_the_contract_flags():
     r = _bench("--help")
     assert r.returncode == 0
-    for flag in ("--gpus", "--steps", "--warmup"):
+    for flag in ("--gpus", "--steps", "--warmup", "--render-streams", "--no-clip"):
         assert flag in r.stdout
 
 
