@@ -137,13 +137,15 @@ typedef struct {
                                      lattice (2^max_depth cells per axis) that holds every leaf,
                                      [bounds[0], bounds[3]) x [bounds[1], bounds[4]) x [bounds[2],
                                      bounds[5]), e.g. from fpo_leaf_bounds; 0 <= lo < hi <= 2^max_depth
-                                     per axis.  fpo_render and fpo_render_noalloc without skip flags
-                                     clip each camera ray to this box instead of the unit cube: a ray
-                                     that misses it ends at once, the others start their walk on its
-                                     face.  Outside the leaves there is nothing to composite (Eq. 2),
-                                     so the image is the same up to FP32 rounding of the entry point;
-                                     a box that cuts a leaf drops the part of it outside.  The other
-                                     calls ignore it */
+                                     per axis.  fpo_render and fpo_render_noalloc without skip flags,
+                                     fpo_render_rays, fpo_render_backward and fpo_trace_rays clip each
+                                     ray to this box instead of the unit cube: a ray that misses it
+                                     ends at once, the others start their walk on its face.  Outside
+                                     the leaves there is nothing to composite (Eq. 2), so colours and
+                                     gradients are the same up to FP32 rounding of the entry point; a
+                                     box that cuts a leaf drops the part of it outside.  The skip
+                                     modes, fpo_ray_labels and the fusion calls measure along the
+                                     cube's chord and ignore it */
 } fpo_tree_view;
 
 /* Pinhole camera: ray through pixel centre (u + 0.5, v + 0.5), row 0 at the

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void render_rays_kernel(RaysLaunch a)
     sh.C[0] = sh.C[1] = sh.C[2] = 0.0f;
     sh.stop_T = a.stop_T;
     Ray r;
-    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+    if (setup_ray_in(a.tree.box_lo, a.tree.box_hi, a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
                   a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
         sh9(r.d[0], r.d[1], r.d[2], sh.Y);
         walk(a.tree, r, s_stack + threadIdx.x, sh);
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kBlock, REC ? 8 : 1) void render_rays_wave_kernel(R
         sh.rec_cap = a.rec_cap;
     }
     Ray r;
-    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+    if (setup_ray_in(a.tree.box_lo, a.tree.box_hi, a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
                   a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
         float Y[FPO_N_SH];
         sh9(r.d[0], r.d[1], r.d[2], Y);
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void trace_rays_kernel(TraceLaunch a)
     if (r_id >= a.n) return;
     TraceVisitor v{a.ids + r_id * a.cap, a.t01 + r_id * a.cap * 2, a.cap, 0, 0.0f};
     Ray r;
-    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+    if (setup_ray_in(a.tree.box_lo, a.tree.box_hi, a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
                   a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
         v.t_in = r.t_in;
         walk(a.tree, r, s_stack + threadIdx.x, v);

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void render_backward_wave_kernel(BackwardLa
     }
     if (sh.g[0] == 0.0f && sh.g[1] == 0.0f && sh.g[2] == 0.0f) return;
     Ray r;
-    if (setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+    if (setup_ray_in(a.tree.box_lo, a.tree.box_hi, a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
                   a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r)) {
         float Y[FPO_N_SH];
         sh9(r.d[0], r.d[1], r.d[2], Y);
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void render_backward_rec_kernel(BackwardLau
     }
     if (sh.g[0] == 0.0f && sh.g[1] == 0.0f && sh.g[2] == 0.0f) return;
     Ray r;
-    if (!setup_ray(a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
+    if (!setup_ray_in(a.tree.box_lo, a.tree.box_hi, a.o[3 * r_id], a.o[3 * r_id + 1], a.o[3 * r_id + 2],
                    a.d[3 * r_id], a.d[3 * r_id + 1], a.d[3 * r_id + 2], r))
         return;
     const int ti = min(max(a.t_idx[r_id], 0), a.n_t - 1);
