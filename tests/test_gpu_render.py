@@ -55,8 +55,8 @@ def test_c1_render_parity(oracle_lib, c1, dev):
 
 
 def test_bounds_clip_keeps_the_image(oracle_lib, c1, dev):
-    """Camera renders start each ray on the leaves' bounds (fpo_leaf_bounds)
-    instead of the unit cube.  Nothing lies outside the leaves, so the image
+    """Camera renders and ray batches start each ray on the leaves' bounds
+    (fpo_leaf_bounds) instead of the unit cube.  Nothing lies outside the leaves, so the image
     is the cube walk's up to FP32 rounding of the entry point, in Fourier and
     in snapshot mode; rays that miss the box return the background with
     T = 1 exactly; the clipped image passes the oracle parity."""
@@ -103,6 +103,19 @@ def test_bounds_clip_keeps_the_image(oracle_lib, c1, dev):
         assert (ref["T"][:, 0] < 0.99).sum() > 100
         for name in ("fourier", "snapshot"):
             check_parity(out[name, "clip"][0][c].reshape(-1, 3).cpu().numpy(), ref, TOL, max_exempt_frac=0.02)
+        # ray batches clip the same way: one ray per wave (small batch) and one per lane (large)
+        for reps in (1, 12):
+            o_d = torch.from_numpy(np.tile(o, (reps, 1)).astype(np.float32)).to(dev)
+            d_d = torch.from_numpy(np.tile(d, (reps, 1)).astype(np.float32)).to(dev)
+            t_d = torch.zeros(len(o_d), dtype=torch.int32, device=dev)
+            note(f"c1 fpo_render_rays {len(o_d)} rays clip / cube")
+            a, ta = _lib.render_rays(tree, o_d, d_d, t_d, basis, fourier, want_T=True)
+            b, tb = _lib.render_rays(cube, o_d, d_d, t_d, basis, fourier, want_T=True)
+            torch.cuda.synchronize()
+            assert float((a - b).abs().max()) < 1e-4 and float((ta - tb).abs().max()) < 1e-4, reps
+            mm = np.tile(miss, reps)
+            assert (ta.cpu().numpy()[mm] == 1.0).all() and (a.cpu().numpy()[mm] == np.float32(bg)).all()
+            check_parity(a[:len(o)].cpu().numpy(), ref, TOL, max_exempt_frac=0.02)
 
 
 def _compare_lists(gpu_ids, gpu_t, n_vis, o, d, ref_trace, boxes, perm):
